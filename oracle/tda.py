@@ -1,0 +1,112 @@
+"""Two-electron integrals and the RHF Tamm-Dancoff matrix.  TEST INFRASTRUCTURE ONLY.
+
+Paper: Sec. 2 -- the two-electron integral (pq|rs) (definition after Eq. (5)), the RHF
+matrix A of Eq. (7) with delta_M = 2 (singlet) / 0 (triplet), the Tamm-Dancoff problem
+A X = omega X, the independent-particle excitations eps_a - eps_i, transition dipoles
+Eq. (8), oscillator strengths Eq. (9) and the strength function Eq. (10).
+
+Readings:
+
+* On the grid, (pq|rs) = dV sum_r conj(phi_r) phi_s (r) * v[conj(phi_p) phi_q](r) with v the
+  isolated Poisson solve of ``oracle.poisson``.
+* The coupling block C = A - diag(eps_a - eps_i) is C_{ia,jb} = delta_M (ai|jb) - (ab|ji);
+  row / column index ia = i * n_virt + a.
+* Oscillator strength in atomic units (m_e = hbar = 1): f = 2/3 omega |d|^2, with d taken
+  from the TDA eigenvector as printed in Eq. (8) (no extra spin factor; the paper does not
+  state one).
+* Strength function: each delta of Eq. (10) broadened by a normalised Lorentzian of
+  half-width gamma.
+
+Pinned by (tests/test_oracle_tda.py): brute-force double sums for single integrals on tiny
+grids, the 8-fold symmetry of real integrals, Hermiticity of C, singlet - triplet =
+2 (ai|jb), and diagonal integrals against the Gaussian closed form.
+"""
+
+import numpy as np
+
+from . import poisson
+
+
+def integral(phi_p, phi_q, phi_r, phi_s, h, khat=None):
+    """(pq|rs) on the grid."""
+    v = poisson.fft(np.conj(phi_p) * phi_q, h, khat)
+    return complex(np.sum(np.conj(phi_r) * phi_s * v) * h ** 3)
+
+
+def coupling_block(phi_occ, phi_virt, h, delta_m, khat=None):
+    """C_{ia,jb} = delta_M (ai|jb) - (ab|ji) for all i, j occupied and a, b virtual (Eq. (7)).
+
+    Computed from one Poisson solve per (a, i) and per (a, b) pair.
+    """
+    no, nv = phi_occ.shape[0], phi_virt.shape[0]
+    n = phi_occ.shape[1]
+    if khat is None:
+        khat = poisson.kernel_hat(n, h)
+    dv = h ** 3
+    po = phi_occ.reshape(no, -1)
+    pv = phi_virt.reshape(nv, -1)
+    # (ai|jb) = dV sum_r conj(phi_j) phi_b v_ai ;  v_ai = G (*) conj(phi_a) phi_i
+    ex = np.zeros((no, nv, no, nv), dtype=np.complex128)
+    for a in range(nv):
+        for i in range(no):
+            v = poisson.fft(np.conj(phi_virt[a]) * phi_occ[i], h, khat).reshape(-1)
+            # rows j, cols b: sum_r conj(phi_j(r)) phi_b(r) v(r)
+            ex[i, a] = dv * ((np.conj(po) * v[None, :]) @ pv.T)
+    # (ab|ji) = dV sum_r conj(phi_j) phi_i v_ab ;  v_ab = G (*) conj(phi_a) phi_b
+    co = np.zeros((no, nv, no, nv), dtype=np.complex128)
+    for a in range(nv):
+        for b in range(nv):
+            v = poisson.fft(np.conj(phi_virt[a]) * phi_virt[b], h, khat).reshape(-1)
+            co[:, a, :, b] = (dv * ((np.conj(po) * v[None, :]) @ po.T)).T   # [i, j]
+    c = delta_m * ex - co
+    c = c.reshape(no * nv, no * nv)
+    if not (np.iscomplexobj(phi_occ) or np.iscomplexobj(phi_virt)):
+        c = c.real
+    return c
+
+
+def coupling_element(phi_occ, phi_virt, h, delta_m, i, a, j, b, khat=None):
+    """One entry C_{ia,jb} = delta_M (ai|jb) - (ab|ji), from two Poisson solves."""
+    ex = integral(phi_virt[a], phi_occ[i], phi_occ[j], phi_virt[b], h, khat)
+    co = integral(phi_virt[a], phi_virt[b], phi_occ[j], phi_occ[i], h, khat)
+    return delta_m * ex - co
+
+
+def tda_matrix(coupling, eps_occ, eps_virt):
+    """A = diag(eps_a - eps_i) + C (Eq. (7)); index ia = i * n_virt + a."""
+    de = (np.asarray(eps_virt)[None, :] - np.asarray(eps_occ)[:, None]).reshape(-1)
+    return np.diag(de) + coupling
+
+
+def excitations(a_matrix):
+    """Tamm-Dancoff A X = omega X (Hermitian): eigenvalues ascending and eigenvectors."""
+    return np.linalg.eigh(a_matrix)
+
+
+def ipa_excitations(eps_occ, eps_virt):
+    """Independent-particle excitations eps_a - eps_i, sorted."""
+    return np.sort((np.asarray(eps_virt)[None, :] - np.asarray(eps_occ)[:, None]).reshape(-1))
+
+
+def dipole_elements(phi_occ, phi_virt, h, coords):
+    """<i| r |a> for each Cartesian direction: array (3, n_occ, n_virt)."""
+    no, nv = phi_occ.shape[0], phi_virt.shape[0]
+    po = phi_occ.reshape(no, -1)
+    pv = phi_virt.reshape(nv, -1)
+    out = []
+    for c in coords:
+        out.append(h ** 3 * ((np.conj(po) * c.reshape(-1)[None, :]) @ pv.T))
+    return np.stack(out)
+
+
+def oscillator_strengths(omega, x, dip):
+    """d_k = sum_ia <i|r|a> x_{k,ia} (Eq. (8)); f_k = 2/3 omega_k |d_k|^2 (Eq. (9))."""
+    d = dip.reshape(3, -1) @ x          # (3, n_states): column k is d_k
+    return 2.0 / 3.0 * omega * np.sum(np.abs(d) ** 2, axis=0)
+
+
+def strength_function(omega_grid, omega, f, gamma):
+    """S(w) = sum_k f_k L(w - omega_k), L a normalised Lorentzian of half-width gamma (Eq. (10))."""
+    w = np.asarray(omega_grid)[:, None]
+    lor = (gamma / np.pi) / ((w - omega[None, :]) ** 2 + gamma ** 2)
+    return lor @ f

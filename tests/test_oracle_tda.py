@@ -1,0 +1,117 @@
+"""Pins of the oracle's two-electron integrals and RHF TDA coupling block (paper Eq. (7)).
+
+* single integrals against an explicit double sum over grid points (tiny grid);
+* the (ii|ii) self-integral of a Gaussian orbital against its closed form;
+* symmetries: 8-fold for real orbitals, Hermiticity of the block, singlet - triplet =
+  2 (ai|jb) (the delta_M structure of Eq. (7));
+* the TDA matrix reduces to the independent-particle excitations when C = 0.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from golden_values import closed_forms
+from oracle import grid, poisson, tda
+
+
+def _brute_integral(p, q, r, s, h):
+    n = p.shape[0]
+    idx = np.indices((n, n, n)).reshape(3, -1).T.astype(np.float64)
+    d = idx[:, None, :] - idx[None, :, :]
+    g = grid.kernel_value(d[..., 0], d[..., 1], d[..., 2], h)
+    left = (np.conj(p) * q).reshape(-1)        # at r'
+    right = (np.conj(r) * s).reshape(-1)       # at r
+    return complex(right @ g @ left) * h ** 6
+
+
+def test_integral_brute_force():
+    rng = np.random.default_rng(2)
+    n, h = 6, 0.5
+    f = [rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n)) for _ in range(4)]
+    got = tda.integral(*f, h)
+    ref = _brute_integral(*f, h)
+    assert abs(got - ref) < 1e-12 * abs(ref)
+
+
+def test_gaussian_self_integral():
+    alpha = 0.7          # density exponent 2*alpha; h^4 terms stay below 1e-4
+    exact = -2.0 * closed_forms()["gaussian_exchange_coefficient"] * math.sqrt(alpha)
+    vals = []
+    for n, h in ((48, 0.25), (60, 0.2)):
+        x = grid.coords(n, h)
+        r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+        g = (2.0 * alpha / math.pi) ** 0.75 * np.exp(-alpha * r2)
+        vals.append(tda.integral(g, g, g, g, h).real)
+    ext = (0.25 ** 2 * vals[1] - 0.2 ** 2 * vals[0]) / (0.25 ** 2 - 0.2 ** 2)
+    assert abs(ext - exact) / exact < 1e-4
+
+
+@pytest.fixture(scope="module")
+def small():
+    return synth.small_real(41, 10, 0.5, 3, 4)
+
+
+def test_real_eightfold_symmetry(small):
+    o, v, h = small.phi, small.phi_virt, small.h
+    base = tda.integral(o[0], v[1], o[2], v[3], h)
+    for perm in [(v[1], o[0], o[2], v[3]), (o[0], v[1], v[3], o[2]),
+                 (o[2], v[3], o[0], v[1]), (v[3], o[2], v[1], o[0])]:
+        assert abs(tda.integral(*perm, h) - base) < 1e-13 * abs(base)
+
+
+@pytest.mark.parametrize("delta_m", [2, 0])
+def test_block_structure(small, delta_m):
+    o, v, h = small.phi, small.phi_virt, small.h
+    c = tda.coupling_block(o, v, h, delta_m)
+    assert c.shape == (12, 12)
+    assert np.max(np.abs(c - c.T)) < 1e-13 * np.max(np.abs(c))
+    for (i, a, j, b) in [(0, 0, 0, 0), (1, 2, 0, 3), (2, 3, 1, 1)]:
+        e = tda.coupling_element(o, v, h, delta_m, i, a, j, b)
+        assert abs(c[i * 4 + a, j * 4 + b] - e.real) < 1e-13 * np.max(np.abs(c))
+
+
+def test_singlet_minus_triplet(small):
+    o, v, h = small.phi, small.phi_virt, small.h
+    cs = tda.coupling_block(o, v, h, 2)
+    ct = tda.coupling_block(o, v, h, 0)
+    for (i, a, j, b) in [(0, 1, 2, 3), (1, 1, 1, 1)]:
+        ex = tda.integral(v[a], o[i], o[j], v[b], h).real
+        assert cs[i * 4 + a, j * 4 + b] - ct[i * 4 + a, j * 4 + b] == pytest.approx(2 * ex, rel=1e-12)
+
+
+def test_complex_block_hermitian():
+    m = synth.small_complex(43, 8, 0.5, 4)
+    o, v = m.phi[:2], m.phi[2:]
+    c = tda.coupling_block(o, v, m.h, 2)
+    assert np.max(np.abs(c - c.conj().T)) < 1e-13 * np.max(np.abs(c))
+
+
+def test_tda_reduces_to_ipa(small):
+    eo, ev = small.eps_occ, small.eps_virt
+    w, _ = tda.excitations(tda.tda_matrix(np.zeros((12, 12)), eo, ev))
+    assert np.allclose(w, tda.ipa_excitations(eo, ev), atol=1e-15)
+
+
+def test_oscillator_two_level():
+    # one transition, no coupling: f = 2/3 (eps_a - eps_i) |<i|r|a>|^2
+    n, h = 16, 0.4
+    x = grid.coords(n, h)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    s = np.exp(-r2)
+    p = x[:, None, None] * np.exp(-r2)
+    s /= math.sqrt(np.sum(s * s) * h ** 3)
+    p /= math.sqrt(np.sum(p * p) * h ** 3)
+    mesh = np.meshgrid(x, x, x, indexing="ij")
+    dip = tda.dipole_elements(s[None], p[None], h, mesh)
+    # <s|x|p> for these two normalised functions: sum x s p dV, evaluated independently
+    dx = float(np.sum(mesh[0] * s * p) * h ** 3)
+    assert abs(dip[0, 0, 0] - dx) < 1e-14 and abs(dip[1, 0, 0]) < 1e-14
+    f = tda.oscillator_strengths(np.array([0.5]), np.ones((1, 1)), dip)
+    assert f[0] == pytest.approx(2.0 / 3.0 * 0.5 * dx * dx, rel=1e-13)
+    # strength function integrates to the oscillator strength
+    wg = np.linspace(-200.0, 200.0, 400001)
+    sfun = tda.strength_function(wg, np.array([0.5]), f, 0.01)
+    assert np.trapezoid(sfun, wg) == pytest.approx(f[0], rel=1e-4)
