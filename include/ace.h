@@ -1,0 +1,159 @@
+/*
+ * ace.h -- C ABI of libace: real-space exact exchange through Adaptively Compressed
+ * Exchange (ACE) and the Tamm-Dancoff coupling block, on one AMD Instinct MI355X (gfx950).
+ *
+ * Paper: U. Panta and D. A. Strubbe, "Implementation of time-dependent Hartree-Fock in real
+ * space", arXiv:2405.01522.  Each entry point cites the passage that defines what it computes.
+ *
+ * Grid.  A cubic box of N^3 points with spacing h (bohr), isolated (orbitals vanish outside
+ * the box, the zero-boundary domain of Sec. 3.4).  Point (x, y, z) is stored at
+ * ((x * N) + y) * N + z (z fastest).  An "orbital array" holds `count` such volumes back to
+ * back: element [k][x][y][z].  Complex values are interleaved (re, im).
+ *
+ * Poisson kernel.  v(r) = dV sum_{r'} G(r - r') rho(r') with G(d) = 1/(h |d|) for integer
+ * displacements d != 0 and G(0) = C0 / h, C0 = 3 ln(2 + sqrt 3) - pi/2 (cube average of
+ * 1/|r|), dV = h^3.  Evaluated exactly (up to rounding) by a 2x zero-padded FFT.
+ *
+ * Precision.  The orbital storage type fixes the arithmetic:
+ *   ACE_C128, ACE_R64 : every step in FP64;
+ *   ACE_C64,  ACE_R32 : pair densities, FFTs, W, xi and K psi in FP32; the Coulomb kernel
+ *                       spectrum, Gram cross-tile sums, M, the Cholesky factor and E_x in FP64.
+ *
+ * Memory and streams.  All array arguments are DEVICE pointers unless marked (host).  The
+ * caller owns every input and output; the context owns its workspaces, the kernel spectrum
+ * and a device status word.  Every call enqueues work on the context's HIP stream and returns
+ * without synchronising (except ace_ctx_create, ace_ctx_status and calls that must grow a
+ * workspace, which synchronise the stream first).  A context is not thread-safe; use one per
+ * stream.
+ *
+ * Errors.  Functions return 0 on success or a negative ACE_ERR_* code; nothing is enqueued
+ * when argument checking fails.  Numerical failures found on the device (non positive
+ * definite -M, non-finite M) are recorded in the status word and reported by ace_ctx_status.
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ace_ctx ace_ctx;
+
+typedef enum { ACE_C128 = 0, ACE_C64 = 1, ACE_R64 = 2, ACE_R32 = 3 } ace_dtype;
+
+enum {
+  ACE_OK = 0,
+  ACE_ERR_INVALID = -1,     /* null pointer, count < 1, bad index, bad flag */
+  ACE_ERR_UNSUPPORTED = -2, /* box edge not compiled, or FFT plane does not fit in LDS */
+  ACE_ERR_HIP = -3,         /* a HIP runtime call failed */
+  ACE_ERR_OOM = -4,         /* device allocation failed */
+  ACE_ERR_NOT_POSDEF = -5,  /* -M not positive definite (device status; info = pivot) */
+  ACE_ERR_NONFINITE = -6    /* M not finite (device status) */
+};
+
+/* Largest orbital count accepted by ace_build / ace_apply. */
+#define ACE_MAX_ORBITALS 32
+
+/*
+ * Create a context for an N^3 box of spacing h holding orbitals of storage type `dtype`.
+ * Computes the spectrum of the isolated Coulomb kernel on the padded (2N)^3 grid in FP64 on
+ * the device (kept as its real-even octant) -- the Poisson problem of Sec. 3.1.
+ * n: box edge (see ace_size_supported); h > 0 in bohr; hip_stream: a hipStream_t, or NULL
+ * for the null stream.  *out receives the context.  Synchronises the stream once.
+ */
+int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out);
+
+/* Destroy a context (synchronises its stream, frees its device memory).  NULL is allowed. */
+int ace_ctx_destroy(ace_ctx* ctx);
+
+/* Change the stream later calls enqueue on (NULL = null stream). */
+int ace_ctx_set_stream(ace_ctx* ctx, void* hip_stream);
+
+/* 1 if a box edge n is compiled for the given dtype, else 0. */
+int ace_size_supported(int n, int dtype);
+
+/*
+ * Batched isolated Poisson solves of pair densities (Sec. 3.1: the integral of Eq. (2) posed
+ * as a Poisson problem for rho = phi_j phi_i):
+ *   v_out[p] = dV * G (*) ( conj(phi_a[pairs[2p]]) * phi_b[pairs[2p+1]] ),  p = 0..np-1.
+ * phi_a: [na][N^3], phi_b: [nb][N^3] orbital arrays of the context dtype;
+ * pairs (host): np index pairs (j, i) with 0 <= j < na, 0 <= i < nb;
+ * v_out: [np][N^3] of the context dtype (real dtypes give real v; pairs are then solved two
+ * per complex FFT).  v_out must not overlap the inputs.
+ */
+int pair_poisson_batched(ace_ctx* ctx, const void* phi_a, int na, const void* phi_b, int nb,
+                         const int32_t* pairs, int np, void* v_out);
+
+/*
+ * Build the ACE operator from n orbitals phi (Sec. 3.1, Eqs. (11)-(12)):
+ *   W_i  = -sum_j phi_j v_ji,  v_ji = dV G (*) (conj(phi_j) phi_i)      (Eq. (11), Eq. (2))
+ *   M    = dV Phi^H W  (Hermitised),  -M = L L^H  (L lower, positive diagonal)
+ *   xi   = W L^{-H}                                                    (Eq. (12))
+ *   E_x  = 1/2 sum_i M_ii   (occupation 1 per orbital; multiply by 2 for a closed-shell RHF
+ *                            determinant built from spatial orbitals)
+ * phi: [n][N^3], 1 <= n <= ACE_MAX_ORBITALS; xi_out: [n][N^3] (context dtype);
+ * M_out: n*n FP64, complex interleaved for complex dtypes, row-major M[k][l], or NULL;
+ * ex_out: one double, or NULL.  n(n+1)/2 pair solves are made.  If -M is not positive
+ * definite the status word records ACE_ERR_NOT_POSDEF with the pivot and xi is zero.
+ */
+int ace_build(ace_ctx* ctx, const void* phi, int n, void* xi_out, double* M_out,
+              double* ex_out);
+
+/*
+ * Apply the ACE operator (Eq. (13)): kpsi_out[v] = -sum_k xi_k dV <xi_k | psi_v>.
+ * xi: [n][N^3] from ace_build; psi: [nv][N^3]; kpsi_out: [nv][N^3] (may not alias psi).
+ */
+int ace_apply(ace_ctx* ctx, const void* xi, int n, const void* psi, int nv, void* kpsi_out);
+
+/*
+ * Direct exact exchange (Eq. (2)), the operator ACE compresses:
+ *   kpsi_out[v] = -sum_j phi_j * dV G (*) (conj(phi_j) psi_v).
+ * phi: [n][N^3]; psi: [nv][N^3]; kpsi_out: [nv][N^3].  n*nv pair solves.
+ */
+int exchange_apply_direct(ace_ctx* ctx, const void* phi, int n, const void* psi, int nv,
+                          void* kpsi_out);
+
+/*
+ * Coupling block of the RHF Tamm-Dancoff matrix for real orbitals (Sec. 2, Eq. (7), without
+ * the diagonal (eps_a - eps_i) term, which the caller adds):
+ *   C[ia][jb] = delta_M (ai|jb) - (ab|ji),  row/col index ia = i * n_virt + a,
+ * with (pq|rs) = dV sum_r phi_r phi_s (r) v_pq(r).  Needs a real dtype (ACE_R64 / ACE_R32).
+ * phi_occ: [no][N^3], phi_virt: [nv][N^3]; delta_M: 2 (singlet) or 0 (triplet);
+ * C_out: (no*nv)^2 doubles, row-major.  Makes no*nv + no(no+1)/2 pair solves.
+ */
+int tda_coupling(ace_ctx* ctx, const void* phi_occ, int no, const void* phi_virt, int nv,
+                 int delta_M, double* C_out);
+
+/*
+ * Synchronise the context stream and report the device status word: *status (host) receives
+ * ACE_OK or the first device-side error recorded since the last call, *info (host, may be
+ * NULL) the failing pivot for ACE_ERR_NOT_POSDEF.  The word is then cleared.
+ */
+int ace_ctx_status(ace_ctx* ctx, int* status, int* info);
+
+/*
+ * Event tracing of the library's own launches (a measurement aid, not part of the method).
+ * When enabled, every group of launches of one kernel class on the context stream is
+ * bracketed by a pair of HIP events; totals are accumulated when read.
+ *   ace_trace_enable(ctx, on)             start / stop recording (pending records are kept);
+ *   ace_trace_read(ctx, id, &ms, &count)  synchronise, return total milliseconds and the
+ *                                         number of recorded groups of class id;
+ *   ace_trace_reset(ctx)                  zero the totals;
+ *   ace_trace_count(), ace_trace_name(id) the classes (e.g. "poisson_xy").
+ */
+int ace_trace_enable(ace_ctx* ctx, int on);
+int ace_trace_read(ace_ctx* ctx, int id, double* total_ms, long long* count);
+int ace_trace_reset(ace_ctx* ctx);
+int ace_trace_count(void);
+const char* ace_trace_name(int id);
+
+/* Static message for a return code. */
+const char* ace_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACE_H */

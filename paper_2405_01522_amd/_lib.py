@@ -1,0 +1,66 @@
+"""ctypes loader for libace.so (the HIP library built from csrc/).
+
+The library must be built (``python -m paper_2405_01522_amd.build``); there is no fallback of
+any kind: a missing library raises immediately.  torch is imported first so that libace binds
+to the HIP runtime torch already loaded (same SONAME), keeping one runtime per process.
+"""
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime libace links against)
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libace.so")
+
+_lib = None
+
+# entry points declared in include/ace.h: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+SIGNATURES = {
+    "ace_ctx_create": (_I, [_I, _D, _I, _P, ctypes.POINTER(_P)]),
+    "ace_ctx_destroy": (_I, [_P]),
+    "ace_ctx_set_stream": (_I, [_P, _P]),
+    "ace_size_supported": (_I, [_I, _I]),
+    "pair_poisson_batched": (_I, [_P, _P, _I, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P]),
+    "ace_build": (_I, [_P, _P, _I, _P, _P, _P]),
+    "ace_apply": (_I, [_P, _P, _I, _P, _I, _P]),
+    "exchange_apply_direct": (_I, [_P, _P, _I, _P, _I, _P]),
+    "tda_coupling": (_I, [_P, _P, _I, _P, _I, _I, _P]),
+    "ace_ctx_status": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "ace_strerror": (ctypes.c_char_p, [_I]),
+    "ace_trace_enable": (_I, [_P, _I]),
+    "ace_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
+    "ace_trace_reset": (_I, [_P]),
+    "ace_trace_count": (_I, []),
+    "ace_trace_name": (ctypes.c_char_p, [_I]),
+}
+
+
+class AceError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().ace_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libace.so is not built (%s); run "
+                              "`python -m paper_2405_01522_amd.build`" % LIB_PATH)
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(code, where):
+    if code != 0:
+        raise AceError(code, where)

@@ -1,0 +1,206 @@
+"""Python binding of the libace C ABI (include/ace.h).
+
+Argument marshalling only: tensors are checked (device, dtype, shape, contiguity), their data
+pointers and the current HIP stream are passed to the library, and every step of the
+computation runs in the library's kernels.  Function names follow the C entry points.
+
+Orbital arrays are torch tensors on the GPU shaped (count, N, N, N), C-contiguous, of one of
+complex128, complex64, float64, float32 (the context's storage type).
+"""
+
+import ctypes
+
+import torch
+
+from ._lib import check, lib
+
+ACE_C128, ACE_C64, ACE_R64, ACE_R32 = 0, 1, 2, 3
+_DTYPES = {torch.complex128: ACE_C128, torch.complex64: ACE_C64,
+           torch.float64: ACE_R64, torch.float32: ACE_R32}
+_TORCH = {v: k for k, v in _DTYPES.items()}
+MAX_ORBITALS = 32
+
+
+def dtype_code(dtype):
+    if dtype not in _DTYPES:
+        raise TypeError("unsupported orbital dtype %s" % dtype)
+    return _DTYPES[dtype]
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def size_supported(n, dtype):
+    return bool(lib().ace_size_supported(int(n), dtype_code(dtype)))
+
+
+class AceContext:
+    """One box (N^3 points, spacing h) and one orbital storage type; owns the kernel spectrum
+    and the library workspaces.  Calls run on torch's current stream."""
+
+    def __init__(self, n, h, dtype, device=None):
+        self.n = int(n)
+        self.h = float(h)
+        self.dtype = dtype
+        self.code = dtype_code(dtype)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            handle = ctypes.c_void_p()
+            check(lib().ace_ctx_create(self.n, self.h, self.code, _stream_handle(),
+                                       ctypes.byref(handle)), "ace_ctx_create")
+        self._h = handle
+        self._stream = torch.cuda.current_stream(self.device).cuda_stream
+
+    # -- plumbing -----------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        """Point the context at torch's current stream (a no-op when it is unchanged)."""
+        cur = torch.cuda.current_stream(self.device).cuda_stream
+        if cur != self._stream:
+            check(lib().ace_ctx_set_stream(self._h, ctypes.c_void_p(cur)), "ace_ctx_set_stream")
+            self._stream = cur
+
+    def _vol(self, t, name, count=None):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if t.dtype != self.dtype:
+            raise TypeError("%s has dtype %s, context expects %s" % (name, t.dtype, self.dtype))
+        if t.dim() != 4 or tuple(t.shape[1:]) != (self.n,) * 3:
+            raise ValueError("%s must be shaped (count, %d, %d, %d), got %s"
+                             % (name, self.n, self.n, self.n, tuple(t.shape)))
+        if count is not None and t.shape[0] != count:
+            raise ValueError("%s must hold %d volumes" % (name, count))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _empty(self, count, dtype=None):
+        return torch.empty((count, self.n, self.n, self.n), dtype=dtype or self.dtype,
+                           device=self.device)
+
+    # -- entry points ---------------------------------------------------------------------
+    def pair_poisson_batched(self, phi_a, phi_b, pairs, out=None):
+        pr = torch.as_tensor(pairs, dtype=torch.int32).reshape(-1, 2).contiguous().cpu()
+        np_ = pr.shape[0]
+        if out is None:
+            out = self._empty(np_)
+        pa = self._vol(phi_a, "phi_a")
+        pb = self._vol(phi_b, "phi_b")
+        po = self._vol(out, "v_out", np_)
+        self._sync_stream()
+        ptr = ctypes.cast(pr.data_ptr(), ctypes.POINTER(ctypes.c_int32))
+        check(lib().pair_poisson_batched(self._h, pa, phi_a.shape[0], pb, phi_b.shape[0], ptr,
+                                         np_, po), "pair_poisson_batched")
+        return out
+
+    def ace_build(self, phi, xi_out=None, m_out=None, ex_out=None):
+        n = phi.shape[0]
+        if xi_out is None:
+            xi_out = self._empty(n)
+        cplx = self.dtype.is_complex
+        if m_out is None:
+            m_out = torch.empty((n, n), dtype=torch.complex128 if cplx else torch.float64,
+                                device=self.device)
+        if ex_out is None:
+            ex_out = torch.empty((), dtype=torch.float64, device=self.device)
+        p = self._vol(phi, "phi")
+        x = self._vol(xi_out, "xi_out", n)
+        self._sync_stream()
+        check(lib().ace_build(self._h, p, n, x, ctypes.c_void_p(m_out.data_ptr()),
+                              ctypes.c_void_p(ex_out.data_ptr())), "ace_build")
+        return xi_out, m_out, ex_out
+
+    def ace_apply(self, xi, psi, out=None):
+        if out is None:
+            out = self._empty(psi.shape[0])
+        x = self._vol(xi, "xi")
+        p = self._vol(psi, "psi")
+        o = self._vol(out, "kpsi_out", psi.shape[0])
+        self._sync_stream()
+        check(lib().ace_apply(self._h, x, xi.shape[0], p, psi.shape[0], o), "ace_apply")
+        return out
+
+    def exchange_apply_direct(self, phi, psi, out=None):
+        if out is None:
+            out = self._empty(psi.shape[0])
+        p = self._vol(phi, "phi")
+        s = self._vol(psi, "psi")
+        o = self._vol(out, "kpsi_out", psi.shape[0])
+        self._sync_stream()
+        check(lib().exchange_apply_direct(self._h, p, phi.shape[0], s, psi.shape[0], o),
+              "exchange_apply_direct")
+        return out
+
+    def tda_coupling(self, phi_occ, phi_virt, delta_m, out=None):
+        no, nv = phi_occ.shape[0], phi_virt.shape[0]
+        if out is None:
+            out = torch.empty((no * nv, no * nv), dtype=torch.float64, device=self.device)
+        po = self._vol(phi_occ, "phi_occ")
+        pv = self._vol(phi_virt, "phi_virt")
+        self._sync_stream()
+        check(lib().tda_coupling(self._h, po, no, pv, nv, int(delta_m),
+                                 ctypes.c_void_p(out.data_ptr())), "tda_coupling")
+        return out
+
+    def trace(self, on=True):
+        """Enable / disable event timing of the library's kernel classes."""
+        check(lib().ace_trace_enable(self._h, 1 if on else 0), "ace_trace_enable")
+
+    def trace_reset(self):
+        check(lib().ace_trace_reset(self._h), "ace_trace_reset")
+
+    def trace_read(self):
+        """{class name: (total ms, groups)} for every class recorded so far (synchronises)."""
+        out = {}
+        for i in range(lib().ace_trace_count()):
+            ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+            check(lib().ace_trace_read(self._h, i, ctypes.byref(ms), ctypes.byref(cnt)),
+                  "ace_trace_read")
+            if cnt.value:
+                out[lib().ace_trace_name(i).decode()] = (ms.value, cnt.value)
+        return out
+
+    def status(self):
+        st, info = ctypes.c_int(), ctypes.c_int()
+        check(lib().ace_ctx_status(self._h, ctypes.byref(st), ctypes.byref(info)), "ace_ctx_status")
+        return st.value, info.value
+
+
+# Module-level functions with the C entry-point names.
+def ace_ctx_create(n, h, dtype, device=None):
+    return AceContext(n, h, dtype, device)
+
+
+def pair_poisson_batched(ctx, phi_a, phi_b, pairs, out=None):
+    return ctx.pair_poisson_batched(phi_a, phi_b, pairs, out)
+
+
+def ace_build(ctx, phi, xi_out=None, m_out=None, ex_out=None):
+    return ctx.ace_build(phi, xi_out, m_out, ex_out)
+
+
+def ace_apply(ctx, xi, psi, out=None):
+    return ctx.ace_apply(xi, psi, out)
+
+
+def exchange_apply_direct(ctx, phi, psi, out=None):
+    return ctx.exchange_apply_direct(phi, psi, out)
+
+
+def tda_coupling(ctx, phi_occ, phi_virt, delta_m, out=None):
+    return ctx.tda_coupling(phi_occ, phi_virt, delta_m, out)
+
+
+def ace_ctx_status(ctx):
+    return ctx.status()

@@ -1,0 +1,496 @@
+// C ABI of libace: argument checking, workspace management and the launch sequences of the
+// exchange / ACE / TDA calls.  Everything numerical happens in the kernels of poisson.hip,
+// ace_kernels.hip and tda.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ace.h"
+#include "ace_kernels.hpp"
+#include "common.hpp"
+#include "internal.hpp"
+#include "tda.hpp"
+
+namespace {
+
+using namespace ace;
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+constexpr double kC0 = 2.380077363979553;  // 3 ln(2 + sqrt 3) - pi/2
+
+size_t elem_bytes(int dt) {
+  switch (dt) {
+    case ACE_C128: return 16;
+    case ACE_C64: return 8;
+    case ACE_R64: return 8;
+    case ACE_R32: return 4;
+  }
+  return 0;
+}
+bool is_fp64(int dt) { return dt == ACE_C128 || dt == ACE_R64; }
+bool is_cplx(int dt) { return dt == ACE_C128 || dt == ACE_C64; }
+
+}  // namespace
+
+// Event tracer: one event pair per traced launch group, pooled events, totals per kernel class.
+struct ace::Trace {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[ace::TR_COUNT] = {};
+  long long count[ace::TR_COUNT] = {};
+  int depth = 0;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  int collect() {
+    if (pending.empty()) return ACE_OK;
+    if (hipStreamSynchronize(stream) != hipSuccess) return ACE_ERR_HIP;
+    for (Rec& r : pending) {
+      float ms = 0.f;
+      if (r.a && r.b && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        total_ms[r.id] += ms;
+        count[r.id] += 1;
+      }
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    pending.clear();
+    return ACE_OK;
+  }
+  void release() {
+    (void)hipStreamSynchronize(stream);
+    for (Rec& r : pending) {
+      if (r.a) pool.push_back(r.a);
+      if (r.b) pool.push_back(r.b);
+    }
+    pending.clear();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+void ace::trace_begin(Trace* t, int id) {
+  if (!t || !t->on) return;
+  Trace::Rec r{id, t->get(), nullptr};
+  if (r.a) (void)hipEventRecord(r.a, t->stream);
+  t->pending.push_back(r);
+}
+
+void ace::trace_end(Trace* t, int id) {
+  if (!t || !t->on) return;
+  for (auto it = t->pending.rbegin(); it != t->pending.rend(); ++it)
+    if (it->id == id && it->b == nullptr) {
+      it->b = t->get();
+      if (it->b) (void)hipEventRecord(it->b, t->stream);
+      return;
+    }
+}
+
+struct ace_ctx {
+  int n = 0, dtype = 0;
+  double h = 0;
+  size_t ng = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double* ghat64 = nullptr;
+  float* ghat32 = nullptr;
+  void* tw = nullptr;        // P twiddles exp(-2 pi i m / P) in the compute precision
+  int* status = nullptr;     // device: [code, info]
+  Buf work, vbuf, wbuf, part, small, pairs, tda;
+  std::vector<int> pairs_cached;
+  int* pinned_pairs = nullptr;
+  size_t pinned_cap = 0;
+  ace::Trace trace;
+  ace::Trace* tr() {
+    trace.stream = stream;
+    return trace.on ? &trace : nullptr;
+  }
+};
+
+namespace {
+
+int hip_check(hipError_t e) { return e == hipSuccess ? ACE_OK : ACE_ERR_HIP; }
+
+int ensure(ace_ctx* c, Buf& b, size_t bytes) {
+  if (bytes <= b.cap) return ACE_OK;
+  if (b.p) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return ACE_ERR_HIP;
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return ACE_ERR_OOM;
+  }
+  b.cap = want;
+  return ACE_OK;
+}
+
+// Upload a pair list to the context's device pair buffer (skipped if unchanged).
+int upload_pairs(ace_ctx* c, const int* host, int count) {
+  const size_t bytes = sizeof(int) * 2 * (size_t)count;
+  if ((int)c->pairs_cached.size() == 2 * count &&
+      std::memcmp(c->pairs_cached.data(), host, bytes) == 0)
+    return ACE_OK;
+  int rc = ensure(c, c->pairs, bytes);
+  if (rc) return rc;
+  // the pinned staging buffer may still feed an earlier copy: wait for the stream
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return ACE_ERR_HIP;
+  if (c->pinned_cap < bytes) {
+    if (c->pinned_pairs) (void)hipHostFree(c->pinned_pairs);
+    c->pinned_pairs = nullptr;
+    if (hipHostMalloc((void**)&c->pinned_pairs, bytes) != hipSuccess) {
+      c->pinned_cap = 0;
+      return ACE_ERR_OOM;
+    }
+    c->pinned_cap = bytes;
+  }
+  std::memcpy(c->pinned_pairs, host, bytes);
+  if (hipMemcpyAsync(c->pairs.p, c->pinned_pairs, bytes, hipMemcpyHostToDevice, c->stream) !=
+      hipSuccess)
+    return ACE_ERR_HIP;
+  c->pairs_cached.assign(host, host + 2 * count);
+  return ACE_OK;
+}
+
+// Pair solves in batches bounded by the FFT workspace; pairs already on the device.
+int run_pairs(ace_ctx* c, const void* pa, const void* pb, const int* pairs_dev, int np,
+              void* vout) {
+  const bool fp64 = is_fp64(c->dtype), rp = !is_cplx(c->dtype);
+  const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
+  const int items = rp ? (np + 1) / 2 : np;
+  const size_t budget = size_t(1) << 30;  // 1 GiB of FFT volumes per launch sequence
+  int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)items, budget / per_item));
+  int rc = ensure(c, c->work, per_item * (size_t)batch);
+  if (rc) return rc;
+  const void* gh = fp64 ? (const void*)c->ghat64 : (const void*)c->ghat32;
+  const size_t eb = elem_bytes(c->dtype);
+  for (int i0 = 0; i0 < items; i0 += batch) {
+    const int ni = std::min(batch, items - i0);
+    const int p0 = rp ? 2 * i0 : i0;
+    const int npb = rp ? std::min(2 * ni, np - p0) : ni;
+    launch_pair_poisson(c->n, fp64, rp, pa, pb, pairs_dev + 2 * p0, npb, c->work.p,
+                        (char*)vout + eb * c->ng * (size_t)p0, gh, c->tw, c->stream, c->tr());
+  }
+  return hip_check(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int ace_size_supported(int n, int dtype) {
+  if (dtype < ACE_C128 || dtype > ACE_R32) return 0;
+  return poisson_size_supported(n, is_fp64(dtype)) ? 1 : 0;
+}
+
+int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) {
+  if (!out || !(h > 0.0) || !std::isfinite(h)) return ACE_ERR_INVALID;
+  if (dtype < ACE_C128 || dtype > ACE_R32) return ACE_ERR_INVALID;
+  *out = nullptr;
+  if (!ace_size_supported(n, dtype)) return ACE_ERR_UNSUPPORTED;
+  ace_ctx* c = new (std::nothrow) ace_ctx();
+  if (!c) return ACE_ERR_OOM;
+  c->n = n;
+  c->h = h;
+  c->dtype = dtype;
+  c->ng = (size_t)n * n * n;
+  c->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&c->device);
+  const int p = 2 * n, ho = p / 2 + 1;
+  const size_t oct = (size_t)ho * ho * ho;
+  // cosine weights w(a) cos(2 pi k a / P) for the real-even kernel transform
+  std::vector<double> cosw((size_t)ho * ho);
+  for (int k = 0; k < ho; ++k)
+    for (int a = 0; a < ho; ++a) {
+      const double w = (a == 0 || a == p / 2) ? 1.0 : 2.0;
+      cosw[(size_t)k * ho + a] = w * cossin_2pi((long long)k * a, p).c;
+    }
+  const bool fp64 = is_fp64(dtype);
+  std::vector<double> tw64(2 * (size_t)p);
+  std::vector<float> tw32(2 * (size_t)p);
+  for (int m = 0; m < p; ++m) {
+    CosSin cs = cossin_2pi(m, p);
+    tw64[2 * m] = cs.c;
+    tw64[2 * m + 1] = -cs.s;
+    tw32[2 * m] = (float)cs.c;
+    tw32[2 * m + 1] = (float)-cs.s;
+  }
+  double *d_cos = nullptr, *t0 = nullptr, *t1 = nullptr;
+  int rc = ACE_OK;
+  if (hipMalloc(&c->ghat64, oct * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->ghat32, oct * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->tw, (fp64 ? 16 : 8) * (size_t)p) != hipSuccess ||
+      hipMalloc(&c->status, 4 * sizeof(int)) != hipSuccess ||
+      hipMalloc(&d_cos, cosw.size() * sizeof(double)) != hipSuccess ||
+      hipMalloc(&t0, oct * sizeof(double)) != hipSuccess ||
+      hipMalloc(&t1, oct * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = ACE_ERR_OOM;
+  }
+  if (!rc) {
+    if (hipMemcpy(d_cos, cosw.data(), cosw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->tw, fp64 ? (const void*)tw64.data() : (const void*)tw32.data(),
+                  (fp64 ? 16 : 8) * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(c->status, 0, 4 * sizeof(int), c->stream) != hipSuccess)
+      rc = ACE_ERR_HIP;
+  }
+  if (!rc) {
+    launch_kernel_setup(n, h, kC0, d_cos, t0, t1, c->ghat64, c->ghat32, c->stream);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = ACE_ERR_HIP;
+  }
+  if (d_cos) (void)hipFree(d_cos);
+  if (t0) (void)hipFree(t0);
+  if (t1) (void)hipFree(t1);
+  if (rc) {
+    ace_ctx_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return ACE_OK;
+}
+
+int ace_ctx_destroy(ace_ctx* c) {
+  if (!c) return ACE_OK;
+  (void)hipStreamSynchronize(c->stream);
+  c->trace.stream = c->stream;
+  c->trace.release();
+  for (Buf* b : {&c->work, &c->vbuf, &c->wbuf, &c->part, &c->small, &c->pairs, &c->tda})
+    if (b->p) (void)hipFree(b->p);
+  if (c->ghat64) (void)hipFree(c->ghat64);
+  if (c->ghat32) (void)hipFree(c->ghat32);
+  if (c->tw) (void)hipFree(c->tw);
+  if (c->status) (void)hipFree(c->status);
+  if (c->pinned_pairs) (void)hipHostFree(c->pinned_pairs);
+  delete c;
+  return ACE_OK;
+}
+
+int ace_ctx_set_stream(ace_ctx* c, void* s) {
+  if (!c) return ACE_ERR_INVALID;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return ACE_ERR_HIP;
+  c->trace.stream = c->stream;
+  int rc = c->trace.collect();
+  c->stream = (hipStream_t)s;
+  return rc;
+}
+
+int pair_poisson_batched(ace_ctx* c, const void* phi_a, int na, const void* phi_b, int nb,
+                         const int32_t* pairs, int np, void* v_out) {
+  if (!c || !phi_a || !phi_b || !pairs || !v_out || na < 1 || nb < 1 || np < 1)
+    return ACE_ERR_INVALID;
+  for (int p = 0; p < np; ++p)
+    if (pairs[2 * p] < 0 || pairs[2 * p] >= na || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= nb)
+      return ACE_ERR_INVALID;
+  int rc = upload_pairs(c, pairs, np);
+  if (rc) return rc;
+  return run_pairs(c, phi_a, phi_b, (const int*)c->pairs.p, np, v_out);
+}
+
+int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, double* ex_out) {
+  if (!c || !phi || !xi_out || n < 1 || n > ACE_MAX_ORBITALS) return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const int np = n * (n + 1) / 2;
+  std::vector<int> pl(2 * (size_t)np);
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a <= b; ++a) {
+      const int p = b * (b + 1) / 2 + a;
+      pl[2 * p] = a;
+      pl[2 * p + 1] = b;
+    }
+  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+  size_t chunk;
+  const int nblk = gram_blocks(ng, &chunk);
+  int rc = upload_pairs(c, pl.data(), np);
+  if (!rc) rc = ensure(c, c->vbuf, eb * ng * (size_t)np);
+  if (!rc) rc = ensure(c, c->wbuf, eb * ng * (size_t)n);
+  if (!rc) rc = ensure(c, c->part, wide * (size_t)nblk * n * n);
+  if (!rc) rc = ensure(c, c->small, wide * 2 * (size_t)n * n);
+  if (rc) return rc;
+  rc = run_pairs(c, phi, phi, (const int*)c->pairs.p, np, c->vbuf.p);
+  if (rc) return rc;
+  launch_wacc(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->stream, c->tr());
+  char* mred = (char*)c->small.p;
+  char* linvh = mred + wide * (size_t)n * n;
+  launch_gram(c->dtype, phi, n, c->wbuf.p, n, ng, c->part.p, c->h * c->h * c->h, mred, c->stream,
+              c->tr());
+  launch_chol(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->stream, c->tr());
+  launch_trsm(c->dtype, c->wbuf.p, n, ng, linvh, xi_out, c->stream, c->tr());
+  return hip_check(hipGetLastError());
+}
+
+int ace_apply(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* out) {
+  if (!c || !xi || !psi || !out || n < 1 || n > ACE_MAX_ORBITALS || nv < 1) return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+  const int chunk_v = std::max(1, std::min(nv, 1024 / n));
+  size_t chunk;
+  const int nblk = gram_blocks(ng, &chunk);
+  int rc = ensure(c, c->part, wide * (size_t)nblk * n * chunk_v);
+  if (!rc) rc = ensure(c, c->small, wide * (size_t)n * chunk_v + wide * 2 * 32 * 32);
+  if (rc) return rc;
+  for (int v0 = 0; v0 < nv; v0 += chunk_v) {
+    const int cv = std::min(chunk_v, nv - v0);
+    const char* ps = (const char*)psi + eb * ng * (size_t)v0;
+    char* o = (char*)out + eb * ng * (size_t)v0;
+    launch_gram(c->dtype, xi, n, ps, cv, ng, c->part.p, c->h * c->h * c->h, c->small.p, c->stream,
+                c->tr());
+    launch_apply_out(c->dtype, xi, n, ng, c->small.p, cv, o, c->stream, c->tr());
+  }
+  return hip_check(hipGetLastError());
+}
+
+int exchange_apply_direct(ace_ctx* c, const void* phi, int n, const void* psi, int nv, void* out) {
+  if (!c || !phi || !psi || !out || n < 1 || n > ACE_MAX_ORBITALS || nv < 1) return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  // vectors in groups so that the pair volumes stay within about 1 GiB
+  const size_t per_vec = eb * ng * (size_t)n;
+  const int gv = (int)std::max<size_t>(1, std::min<size_t>((size_t)nv, (size_t(1) << 30) / per_vec));
+  int rc = ensure(c, c->vbuf, per_vec * (size_t)gv);
+  if (rc) return rc;
+  for (int v0 = 0; v0 < nv; v0 += gv) {
+    const int cv = std::min(gv, nv - v0);
+    std::vector<int> pl(2 * (size_t)n * cv);
+    for (int v = 0; v < cv; ++v)
+      for (int j = 0; j < n; ++j) {
+        pl[2 * ((size_t)v * n + j)] = j;
+        pl[2 * ((size_t)v * n + j) + 1] = v;
+      }
+    rc = upload_pairs(c, pl.data(), n * cv);
+    if (rc) return rc;
+    const char* ps = (const char*)psi + eb * ng * (size_t)v0;
+    rc = run_pairs(c, phi, ps, (const int*)c->pairs.p, n * cv, c->vbuf.p);
+    if (rc) return rc;
+    launch_direct_acc(c->dtype, phi, n, c->vbuf.p, cv, ng, (char*)out + eb * ng * (size_t)v0,
+                      c->stream, c->tr());
+  }
+  return hip_check(hipGetLastError());
+}
+
+int tda_coupling(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, int nv,
+                 int delta_M, double* C_out) {
+  if (!c || !phi_occ || !phi_virt || !C_out || no < 1 || nv < 1) return ACE_ERR_INVALID;
+  if (delta_M != 0 && delta_M != 2) return ACE_ERR_INVALID;
+  if (is_cplx(c->dtype)) return ACE_ERR_UNSUPPORTED;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const int nov = no * nv, noo = no * (no + 1) / 2;
+  // pair list: ov pairs (j, b) -> j*nv + b (phi_a = occ, phi_b = virt), then oo pairs (a<=b)
+  std::vector<int> pov(2 * (size_t)nov), poo(2 * (size_t)noo);
+  for (int j = 0; j < no; ++j)
+    for (int b = 0; b < nv; ++b) {
+      pov[2 * ((size_t)j * nv + b)] = j;
+      pov[2 * ((size_t)j * nv + b) + 1] = b;
+    }
+  for (int b = 0; b < no; ++b)
+    for (int a = 0; a <= b; ++a) {
+      const int p = b * (b + 1) / 2 + a;
+      poo[2 * p] = a;
+      poo[2 * p + 1] = b;
+    }
+  const size_t vbytes = eb * ng * (size_t)(nov + noo);
+  int rc = ensure(c, c->vbuf, vbytes);
+  if (rc) return rc;
+  char* v_ov = (char*)c->vbuf.p;
+  char* v_oo = v_ov + eb * ng * (size_t)nov;
+  rc = upload_pairs(c, pov.data(), nov);
+  if (!rc) rc = run_pairs(c, phi_occ, phi_virt, (const int*)c->pairs.p, nov, v_ov);
+  if (!rc) rc = upload_pairs(c, poo.data(), noo);
+  if (!rc) rc = run_pairs(c, phi_occ, phi_occ, (const int*)c->pairs.p, noo, v_oo);
+  if (rc) return rc;
+  TdaWork tw;
+  rc = ensure(c, c->tda, tda_workspace_bytes(no, nv, ng, is_fp64(c->dtype), &tw));
+  if (rc) return rc;
+  launch_tda(is_fp64(c->dtype), phi_occ, no, phi_virt, nv, v_ov, v_oo, ng, c->h * c->h * c->h,
+             delta_M, c->tda.p, tw, C_out, c->stream, c->tr());
+  return hip_check(hipGetLastError());
+}
+
+int ace_ctx_status(ace_ctx* c, int* status, int* info) {
+  if (!c || !status) return ACE_ERR_INVALID;
+  int st[4] = {0, 0, 0, 0};
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return ACE_ERR_HIP;
+  if (hipMemcpy(st, c->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return ACE_ERR_HIP;
+  if (hipMemset(c->status, 0, sizeof(st)) != hipSuccess) return ACE_ERR_HIP;
+  *status = st[0];
+  if (info) *info = st[1];
+  return ACE_OK;
+}
+
+int ace_trace_enable(ace_ctx* c, int on) {
+  if (!c) return ACE_ERR_INVALID;
+  c->trace.stream = c->stream;
+  int rc = c->trace.collect();
+  c->trace.on = on != 0;
+  return rc;
+}
+
+int ace_trace_read(ace_ctx* c, int id, double* total_ms, long long* count) {
+  if (!c || id < 0 || id >= TR_COUNT || !total_ms) return ACE_ERR_INVALID;
+  c->trace.stream = c->stream;
+  int rc = c->trace.collect();
+  *total_ms = c->trace.total_ms[id];
+  if (count) *count = c->trace.count[id];
+  return rc;
+}
+
+int ace_trace_reset(ace_ctx* c) {
+  if (!c) return ACE_ERR_INVALID;
+  c->trace.stream = c->stream;
+  int rc = c->trace.collect();
+  for (int i = 0; i < TR_COUNT; ++i) {
+    c->trace.total_ms[i] = 0.0;
+    c->trace.count[i] = 0;
+  }
+  return rc;
+}
+
+const char* ace_trace_name(int id) {
+  static const char* names[TR_COUNT] = {"poisson_zfwd", "poisson_xy", "poisson_zinv", "w_accumulate",
+                                        "gram", "cholesky", "xi_trsm", "apply_update",
+                                        "direct_accumulate", "tda_gemm", "tda_reduce", "setup"};
+  if (id < 0 || id >= TR_COUNT) return "";
+  return names[id];
+}
+
+int ace_trace_count(void) { return TR_COUNT; }
+
+const char* ace_strerror(int code) {
+  switch (code) {
+    case ACE_OK: return "ok";
+    case ACE_ERR_INVALID: return "invalid argument";
+    case ACE_ERR_UNSUPPORTED: return "unsupported box size or dtype";
+    case ACE_ERR_HIP: return "HIP runtime error";
+    case ACE_ERR_OOM: return "device out of memory";
+    case ACE_ERR_NOT_POSDEF: return "-M is not positive definite";
+    case ACE_ERR_NONFINITE: return "non-finite value in M";
+  }
+  return "unknown error";
+}
+
+}  // extern "C"

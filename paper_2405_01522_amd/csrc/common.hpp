@@ -1,0 +1,254 @@
+// Shared device helpers: complex type, compile-time trigonometry, register-resident DFTs.
+//
+// The register DFTs are the building block of every FFT pass: a length-P transform is split
+// as P = P1 * P2 (Cooley-Tukey, one LDS exchange between the two factors) and each factor
+// runs entirely in one lane's registers.  All twiddles inside a factor are compile-time
+// constants; multiplications by 0 and +-1 fold away after unrolling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ace {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+  T r, i;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) {
+  return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+// a * conj(b)
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cmul_conjb(C2<T> a, C2<T> b) {
+  return {a.r * b.r + a.i * b.i, a.i * b.r - a.r * b.i};
+}
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cscale(C2<T> a, T s) { return {a.r * s, a.i * s}; }
+
+// ---------------------------------------------------------------------------------------
+// Compile-time cos / sin of 2*pi*m/n with exact quadrant / octant reduction (integer
+// arithmetic), then a Taylor series on |x| <= pi/4.  Accurate to about 1 ulp in double.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double sin_series(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cos_series(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+struct CosSin {
+  double c, s;
+};
+
+// cos and sin of 2*pi*m/n for integers m (any sign), n > 0.
+constexpr CosSin cossin_2pi(long long m, long long n) {
+  long long r = m % n;
+  if (r < 0) r += n;
+  // angle = 2*pi*r/n = (pi/2) * (4r/n): quadrant q, remainder rr in units of pi/(2n)
+  long long q = (4 * r) / n;
+  long long rr = 4 * r - q * n;  // angle within quadrant = (pi/2) * rr / n
+  double c0 = 0, s0 = 0;
+  if (2 * rr <= n) {
+    double x = kPi * double(rr) / double(2 * n);
+    c0 = cos_series(x);
+    s0 = sin_series(x);
+  } else {
+    double x = kPi * double(n - rr) / double(2 * n);
+    c0 = sin_series(x);
+    s0 = cos_series(x);
+  }
+  if (q == 0) return {c0, s0};
+  if (q == 1) return {-s0, c0};
+  if (q == 2) return {-c0, -s0};
+  return {s0, -c0};
+}
+
+template <int N>
+struct TwTable {
+  double c[N];
+  double s[N];
+  constexpr TwTable() : c(), s() {
+    for (int m = 0; m < N; ++m) {
+      CosSin v = cossin_2pi(m, N);
+      c[m] = v.c;
+      s[m] = v.s;
+    }
+  }
+};
+template <int N>
+inline constexpr TwTable<N> kTw{};
+
+// a * (c + i s) for compile-time constants c, s (branches fold after unrolling).
+template <typename T>
+__host__ __device__ __forceinline__ C2<T> cmul_k(C2<T> a, double c, double s) {
+  if (s == 0.0) {
+    if (c == 1.0) return a;
+    if (c == -1.0) return {-a.r, -a.i};
+    return {a.r * T(c), a.i * T(c)};
+  }
+  if (c == 0.0) {
+    if (s == 1.0) return {-a.i, a.r};
+    if (s == -1.0) return {a.i, -a.r};
+    return {-a.i * T(s), a.r * T(s)};
+  }
+  return {a.r * T(c) - a.i * T(s), a.r * T(s) + a.i * T(c)};
+}
+
+// W_N^{m} with sign DIR: exp(DIR * 2 pi i m / N); DIR = -1 forward, +1 inverse.
+template <typename T, int N, int DIR>
+__host__ __device__ __forceinline__ C2<T> twk(C2<T> a, int m) {
+  const int mm = m % N;
+  return cmul_k<T>(a, kTw<N>.c[mm], DIR * kTw<N>.s[mm]);
+}
+
+constexpr int pick_radix(int n) {
+  return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5 : n;
+}
+
+// Odd-prime (or small) direct butterfly, natural order in/out.
+template <typename T, int R, int DIR>
+__host__ __device__ __forceinline__ void butterfly(C2<T>* x) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    C2<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    C2<T> s02 = cadd(x[0], x[2]), d02 = csub(x[0], x[2]);
+    C2<T> s13 = cadd(x[1], x[3]), d13 = csub(x[1], x[3]);
+    // DIR * i * d13
+    C2<T> j13 = (DIR < 0) ? C2<T>{d13.i, -d13.r} : C2<T>{-d13.i, d13.r};
+    x[0] = cadd(s02, s13);
+    x[2] = csub(s02, s13);
+    x[1] = cadd(d02, j13);
+    x[3] = csub(d02, j13);
+  } else {
+    // X_k = x0 + sum_{m=1}^{(R-1)/2} [(x_m + x_{R-m}) cos(2 pi m k/R) + DIR i (x_m - x_{R-m}) sin(2 pi m k/R)]
+    static_assert(R % 2 == 1, "odd radix expected");
+    constexpr int Hh = (R - 1) / 2;
+    C2<T> sp[Hh], sm[Hh];
+#pragma unroll
+    for (int m = 1; m <= Hh; ++m) {
+      sp[m - 1] = cadd(x[m], x[R - m]);
+      sm[m - 1] = csub(x[m], x[R - m]);
+    }
+    C2<T> out[R];
+    C2<T> x0 = x[0];
+    C2<T> tot = x0;
+#pragma unroll
+    for (int m = 0; m < Hh; ++m) tot = cadd(tot, sp[m]);
+    out[0] = tot;
+#pragma unroll
+    for (int k = 1; k <= Hh; ++k) {
+      C2<T> re = x0, im = {T(0), T(0)};
+#pragma unroll
+      for (int m = 1; m <= Hh; ++m) {
+        const int mk = (m * k) % R;
+        const T c = T(kTw<R>.c[mk]);
+        const T s = T(kTw<R>.s[mk]);
+        re.r += sp[m - 1].r * c;
+        re.i += sp[m - 1].i * c;
+        im.r += sm[m - 1].r * s;
+        im.i += sm[m - 1].i * s;
+      }
+      // DIR * i * im
+      C2<T> jim = (DIR < 0) ? C2<T>{im.i, -im.r} : C2<T>{-im.i, im.r};
+      out[k] = cadd(re, jim);
+      out[R - k] = csub(re, jim);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = out[k];
+  }
+}
+
+// In-register DFT of length N, natural order in and out, unnormalised.
+// X_k = sum_n x_n exp(DIR 2 pi i n k / N).
+template <typename T, int N, int DIR>
+__host__ __device__ __forceinline__ void dft(C2<T>* x) {
+  constexpr int R = pick_radix(N);
+  constexpr int M = N / R;
+  if constexpr (M == 1) {
+    butterfly<T, R, DIR>(x);
+  } else {
+    // decimation in time: y_r = DFT_M(x[r + R m]); X[k + M s] = sum_r W_R^{rs} W_N^{rk} y_r[k]
+    C2<T> y[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int m = 0; m < M; ++m) y[r][m] = x[r + R * m];
+#pragma unroll
+    for (int r = 0; r < R; ++r) dft<T, M, DIR>(y[r]);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      C2<T> t[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) t[r] = twk<T, N, DIR>(y[r][k], r * k);
+      butterfly<T, R, DIR>(t);
+#pragma unroll
+      for (int s = 0; s < R; ++s) x[k + M * s] = t[s];
+    }
+  }
+}
+
+// Length-N DFT whose inputs x[N/2 .. N) are zero (N even).  Reads x[0..N/2), writes x[0..N).
+template <typename T, int N, int DIR>
+__host__ __device__ __forceinline__ void dft_in_half(C2<T>* x) {
+  static_assert(N % 2 == 0, "even length");
+  constexpr int H = N / 2;
+  C2<T> e[H], o[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    e[m] = x[m];
+    o[m] = twk<T, N, DIR>(x[m], m);
+  }
+  dft<T, H, DIR>(e);
+  dft<T, H, DIR>(o);
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    x[2 * m] = e[m];
+    x[2 * m + 1] = o[m];
+  }
+}
+
+// Length-N DFT of which only outputs x[0 .. N/2) are needed (N even).  Reads x[0..N).
+template <typename T, int N, int DIR>
+__host__ __device__ __forceinline__ void dft_out_half(C2<T>* x) {
+  static_assert(N % 2 == 0, "even length");
+  constexpr int H = N / 2;
+  C2<T> e[H], o[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    e[m] = x[2 * m];
+    o[m] = x[2 * m + 1];
+  }
+  dft<T, H, DIR>(e);
+  dft<T, H, DIR>(o);
+#pragma unroll
+  for (int m = 0; m < H; ++m) x[m] = cadd(e[m], twk<T, N, DIR>(o[m], m));
+}
+
+}  // namespace ace

@@ -1,0 +1,397 @@
+// Isolated Poisson solves of pair densities on an N^3 box: zero-padded (P = 2N) FFT
+// convolution with the sampled Coulomb kernel (the exchange integral of Eq. (2) posed as a
+// Poisson problem, paper Sec. 3.1).
+//
+// Three passes per pair, with one volume of N*N*P complex values between them (the z axis
+// is the only one ever padded in HBM):
+//   Z-forward  (grid: x-plane x pair)   rho = conj(a) b on the box, pruned FFT along z,
+//                                       written transposed as work[pair][qz][x][y];
+//   XY         (grid: qz-plane x pair)  one N x N slice -> P x P plane in LDS; pruned FFT
+//                                       along y then x, multiply by the kernel spectrum,
+//                                       inverse along x then y keeping only the N x N box;
+//                                       written back in place;
+//   Z-inverse  (grid: x-plane x pair)   inverse FFT along z keeping z < N -> v[pair][x][y][z].
+// Every 1-D transform is P = P1 * P2 with one LDS exchange; see fftplan.hpp.  The x-axis
+// forward second factor, the kernel multiply and the inverse first factor are fused in
+// registers.  The kernel spectrum is real and even, so it is stored as the octant
+// (P/2+1)^3 and indexed by min(k, P-k) per axis; it already carries dV / P^3.
+#include "common.hpp"
+#include "fftplan.hpp"
+#include "internal.hpp"
+
+namespace ace {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ C2<T>* lds() {
+  extern __shared__ __align__(16) unsigned char ace_smem[];
+  return reinterpret_cast<C2<T>*>(ace_smem);
+}
+
+// ---------------------------------------------------------------------------------------
+// Z-forward pass
+template <typename T, int N, bool RP>
+__global__ __launch_bounds__(kThreads) void k_zfwd(const void* __restrict__ pa_,
+                                                   const void* __restrict__ pb_,
+                                                   const int* __restrict__ pairs, int np,
+                                                   C2<T>* __restrict__ work,
+                                                   const C2<T>* __restrict__ tw) {
+  typedef Plan<N> PL;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
+  constexpr size_t NG = (size_t)N * N * N;
+  C2<T>* buf = lds<T>();
+  const int x = blockIdx.x;
+  const int p = blockIdx.y;
+  const size_t plane = (size_t)x * N * N;
+
+  const C2<T>* ca = nullptr;
+  const C2<T>* cb = nullptr;
+  const T *ra0 = nullptr, *rb0 = nullptr, *ra1 = nullptr, *rb1 = nullptr;
+  if constexpr (RP) {
+    const int q0 = 2 * p, q1 = 2 * p + 1;
+    ra0 = reinterpret_cast<const T*>(pa_) + (size_t)pairs[2 * q0] * NG + plane;
+    rb0 = reinterpret_cast<const T*>(pb_) + (size_t)pairs[2 * q0 + 1] * NG + plane;
+    if (q1 < np) {
+      ra1 = reinterpret_cast<const T*>(pa_) + (size_t)pairs[2 * q1] * NG + plane;
+      rb1 = reinterpret_cast<const T*>(pb_) + (size_t)pairs[2 * q1 + 1] * NG + plane;
+    }
+  } else {
+    ca = reinterpret_cast<const C2<T>*>(pa_) + (size_t)pairs[2 * p] * NG + plane;
+    cb = reinterpret_cast<const C2<T>*>(pb_) + (size_t)pairs[2 * p + 1] * NG + plane;
+  }
+
+  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+    const int n2 = it % P2, y = it / P2;
+    C2<T> v[P1];
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) {
+      const int idx = y * N + n1 * P2 + n2;
+      if constexpr (RP) {
+        v[n1].r = ra0[idx] * rb0[idx];
+        v[n1].i = ra1 ? ra1[idx] * rb1[idx] : T(0);
+      } else {
+        v[n1] = cmulc(ca[idx], cb[idx]);
+      }
+    }
+    dft_in_half<T, P1, -1>(v);
+    buf[y * RS + n2] = v[0];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) buf[y * RS + k1 * P2 + n2] = cmul(v[k1], tw[n2 * k1]);
+  }
+  __syncthreads();
+  C2<T>* dst0 = work + (size_t)p * P * N * N + (size_t)x * N;
+  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+    const int y = it % N, k1 = it / N;
+    C2<T> v[P2];
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = buf[y * RS + k1 * P2 + k2];
+    dft<T, P2, -1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) dst0[(size_t)(k1 * P2 + k2) * N * N + y] = v[k2];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// XY pass: one qz plane per workgroup, the whole P x P plane in LDS.
+template <typename T, int N>
+__global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
+                                                 const T* __restrict__ ghat,
+                                                 const C2<T>* __restrict__ tw) {
+  typedef Plan<N> PL;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1, HO = PL::HO;
+  C2<T>* pl = lds<T>();
+  const int qz = blockIdx.x, p = blockIdx.y;
+  C2<T>* g = work + ((size_t)p * P + qz) * N * N;
+  const int kz = PL::freq(qz);
+  const T* gz = ghat + (kz <= P - kz ? kz : P - kz);
+
+  // 1. y forward, first factor (rows x < N, input y < N): global -> LDS
+  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+    const int n2 = it % P2, x = it / P2;
+    C2<T> v[P1];
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) v[n1] = g[x * N + n1 * P2 + n2];
+    dft_in_half<T, P1, -1>(v);
+    pl[x * RS + n2] = v[0];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) pl[x * RS + k1 * P2 + n2] = cmul(v[k1], tw[n2 * k1]);
+  }
+  __syncthreads();
+  // 2. y forward, second factor
+  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+    const int x = it % N, k1 = it / N;
+    C2<T> v[P2];
+    C2<T>* row = pl + x * RS + k1 * P2;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = row[k2];
+    dft<T, P2, -1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) row[k2] = v[k2];
+  }
+  __syncthreads();
+  // 3. x forward, first factor (columns qy, input x < N)
+  for (int it = threadIdx.x; it < P * P2; it += kThreads) {
+    const int qy = it % P, n2 = it / P;
+    C2<T> v[P1];
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) v[n1] = pl[(n1 * P2 + n2) * RS + qy];
+    dft_in_half<T, P1, -1>(v);
+    pl[n2 * RS + qy] = v[0];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) pl[(k1 * P2 + n2) * RS + qy] = cmul(v[k1], tw[n2 * k1]);
+  }
+  __syncthreads();
+  // 4. x forward second factor, kernel multiply, x inverse first factor (in registers)
+  for (int it = threadIdx.x; it < P * P1; it += kThreads) {
+    const int qy = it % P, k1 = it / P;
+    C2<T> v[P2];
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = pl[(k1 * P2 + k2) * RS + qy];
+    dft<T, P2, -1>(v);
+    const int ky = PL::freq(qy);
+    const T* gy = gz + (size_t)(ky <= P - ky ? ky : P - ky) * HO;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) {
+      const int kx = k1 + P1 * k2;
+      const T gk = gy[(size_t)(kx <= P - kx ? kx : P - kx) * HO * HO];
+      v[k2] = cscale(v[k2], gk);
+    }
+    dft<T, P2, 1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) pl[(k1 * P2 + k2) * RS + qy] = v[k2];
+  }
+  __syncthreads();
+  // 5. x inverse, second factor, output x < N only
+  for (int it = threadIdx.x; it < P * P2; it += kThreads) {
+    const int qy = it % P, n2 = it / P;
+    C2<T> v[P1];
+    v[0] = pl[n2 * RS + qy];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(pl[(k1 * P2 + n2) * RS + qy], tw[n2 * k1]);
+    dft_out_half<T, P1, 1>(v);
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) pl[(n1 * P2 + n2) * RS + qy] = v[n1];
+  }
+  __syncthreads();
+  // 6. y inverse, first factor (rows x < N)
+  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+    const int x = it % N, k1 = it / N;
+    C2<T> v[P2];
+    C2<T>* row = pl + x * RS + k1 * P2;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = row[k2];
+    dft<T, P2, 1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) row[k2] = v[k2];
+  }
+  __syncthreads();
+  // 7. y inverse, second factor, output y < N: LDS -> global (in place over the input slice)
+  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+    const int n2 = it % P2, x = it / P2;
+    C2<T> v[P1];
+    v[0] = pl[x * RS + n2];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(pl[x * RS + k1 * P2 + n2], tw[n2 * k1]);
+    dft_out_half<T, P1, 1>(v);
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) g[x * N + n1 * P2 + n2] = v[n1];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Z-inverse pass
+template <typename T, int N, bool RP>
+__global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ work,
+                                                   void* __restrict__ vout_, int np,
+                                                   const C2<T>* __restrict__ tw) {
+  typedef Plan<N> PL;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
+  constexpr size_t NG = (size_t)N * N * N;
+  C2<T>* buf = lds<T>();
+  const int x = blockIdx.x, p = blockIdx.y;
+  const C2<T>* src0 = work + (size_t)p * P * N * N + (size_t)x * N;
+  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+    const int y = it % N, k1 = it / N;
+    C2<T> v[P2];
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = src0[(size_t)(k1 * P2 + k2) * N * N + y];
+    dft<T, P2, 1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) buf[y * RS + k1 * P2 + k2] = v[k2];
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+    const int n2 = it % P2, y = it / P2;
+    C2<T> v[P1];
+    v[0] = buf[y * RS + n2];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(buf[y * RS + k1 * P2 + n2], tw[n2 * k1]);
+    dft_out_half<T, P1, 1>(v);
+    const size_t base = ((size_t)x * N + y) * N + n2;
+    if constexpr (RP) {
+      T* o0 = reinterpret_cast<T*>(vout_) + (size_t)(2 * p) * NG + base;
+      const bool has1 = (2 * p + 1) < np;
+      T* o1 = reinterpret_cast<T*>(vout_) + (size_t)(2 * p + 1) * NG + base;
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) {
+        o0[n1 * P2] = v[n1].r;
+        if (has1) o1[n1 * P2] = v[n1].i;
+      }
+    } else {
+      C2<T>* o = reinterpret_cast<C2<T>*>(vout_) + (size_t)p * NG + base;
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) o[n1 * P2] = v[n1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernel spectrum setup (FP64).
+__global__ void k_ghat_init(double* __restrict__ g, int ho, double h, double c0) {
+  const int total = ho * ho * ho;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int c = i % ho, b = (i / ho) % ho, a = i / (ho * ho);
+    const double r2 = double(a) * a + double(b) * b + double(c) * c;
+    g[i] = (r2 == 0.0) ? c0 / h : 1.0 / (h * sqrt(r2));
+  }
+}
+
+// out[..k..] = sum_a cosw[k * ho + a] * in[..a..] along one axis of an ho^3 array.
+__global__ void k_axis_cos(const double* __restrict__ in, double* __restrict__ out,
+                           const double* __restrict__ cosw, int ho, int axis) {
+  const int total = ho * ho * ho;
+  const int stride = axis == 0 ? ho * ho : (axis == 1 ? ho : 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int k = (i / stride) % ho;
+    const int base = i - k * stride;
+    double s = 0.0;
+    for (int a = 0; a < ho; ++a) s += cosw[k * ho + a] * in[base + a * stride];
+    out[i] = s;
+  }
+}
+
+__global__ void k_ghat_final(const double* __restrict__ in, double* __restrict__ g64,
+                             float* __restrict__ g32, double scale, int total) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const double v = in[i] * scale;
+    g64[i] = v;
+    g32[i] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)bytes);
+}
+
+template <typename T, int N>
+void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int np, void* work,
+                 void* vout, const void* ghat, const void* tw, hipStream_t s, Trace* tr) {
+  typedef Plan<N> PL;
+  constexpr int P = PL::P;
+  const int items = rp ? (np + 1) / 2 : np;
+  if (items <= 0) return;
+  const size_t lds_z = (size_t)N * (P + 1) * sizeof(C2<T>);
+  const size_t lds_xy = (size_t)P * (P + 1) * sizeof(C2<T>);
+  C2<T>* w = reinterpret_cast<C2<T>*>(work);
+  const C2<T>* t = reinterpret_cast<const C2<T>*>(tw);
+  const T* gh = reinterpret_cast<const T*>(ghat);
+  if (rp) {
+    allow_lds(k_zfwd<T, N, true>, lds_z);
+    allow_lds(k_zinv<T, N, true>, lds_z);
+  } else {
+    allow_lds(k_zfwd<T, N, false>, lds_z);
+    allow_lds(k_zinv<T, N, false>, lds_z);
+  }
+  allow_lds(k_xy<T, N>, lds_xy);
+  dim3 gz(N, items), gxy(P, items);
+  {
+    TraceScope ts(tr, TR_ZFWD);
+    if (rp)
+      k_zfwd<T, N, true><<<gz, kThreads, lds_z, s>>>(pa, pb, pairs, np, w, t);
+    else
+      k_zfwd<T, N, false><<<gz, kThreads, lds_z, s>>>(pa, pb, pairs, np, w, t);
+  }
+  {
+    TraceScope ts(tr, TR_XY);
+    k_xy<T, N><<<gxy, kThreads, lds_xy, s>>>(w, gh, t);
+  }
+  {
+    TraceScope ts(tr, TR_ZINV);
+    if (rp)
+      k_zinv<T, N, true><<<gz, kThreads, lds_z, s>>>(w, vout, np, t);
+    else
+      k_zinv<T, N, false><<<gz, kThreads, lds_z, s>>>(w, vout, np, t);
+  }
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+template <typename T, int N>
+constexpr bool fits() {
+  return (size_t)(2 * N) * (2 * N + 1) * sizeof(C2<T>) <= kMaxLds;
+}
+
+#define ACE_SIZES(X) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(24) X(32) X(40) X(48) X(56) X(64)
+
+}  // namespace
+
+bool poisson_size_supported(int n, bool fp64) {
+#define ACE_CASE(NN) \
+  case NN:           \
+    return fp64 ? fits<double, NN>() : fits<float, NN>();
+  switch (n) {
+    ACE_SIZES(ACE_CASE)
+    default:
+      return false;
+  }
+#undef ACE_CASE
+}
+
+size_t poisson_work_bytes_per_item(int n, bool fp64) {
+  return (size_t)n * n * (2 * n) * (fp64 ? 16 : 8);
+}
+
+void launch_kernel_setup(int n, double h, double c0, const double* cosw, double* tmp0,
+                         double* tmp1, double* ghat64, float* ghat32, hipStream_t s) {
+  const int p = 2 * n, ho = p / 2 + 1, total = ho * ho * ho;
+  const int blocks = (total + 255) / 256;
+  k_ghat_init<<<blocks, 256, 0, s>>>(tmp0, ho, h, c0);
+  k_axis_cos<<<blocks, 256, 0, s>>>(tmp0, tmp1, cosw, ho, 0);
+  k_axis_cos<<<blocks, 256, 0, s>>>(tmp1, tmp0, cosw, ho, 1);
+  k_axis_cos<<<blocks, 256, 0, s>>>(tmp0, tmp1, cosw, ho, 2);
+  const double scale = h * h * h / ((double)p * p * p);
+  k_ghat_final<<<blocks, 256, 0, s>>>(tmp1, ghat64, ghat32, scale, total);
+}
+
+void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
+                         const void* phi_b, const int* pairs_dev, int np, void* work,
+                         void* v_out, const void* ghat, const void* tw, hipStream_t s,
+                         Trace* tr) {
+#define ACE_CASE(NN)                                                                          \
+  case NN:                                                                                    \
+    if constexpr (fits<double, NN>()) {                                                       \
+      if (fp64) {                                                                             \
+        run_poisson<double, NN>(real_packed, phi_a, phi_b, pairs_dev, np, work, v_out, ghat, \
+                                tw, s, tr);                                                   \
+        return;                                                                               \
+      }                                                                                       \
+    }                                                                                         \
+    if (!fp64)                                                                                \
+      run_poisson<float, NN>(real_packed, phi_a, phi_b, pairs_dev, np, work, v_out, ghat, tw, \
+                             s, tr);                                                              \
+    return;
+  switch (n) {
+    ACE_SIZES(ACE_CASE)
+    default:
+      return;
+  }
+#undef ACE_CASE
+}
+
+}  // namespace ace

@@ -1,0 +1,179 @@
+// Coupling block of the RHF Tamm-Dancoff matrix for real orbitals (paper Sec. 2, Eq. (7)):
+//   C[ia][jb] = delta_M (ai|jb) - (ab|ji)
+//             = delta_M * CJ[ia][jb] - CK[ij][ab]
+//   CJ[ia][jb] = dV sum_r (phi_i phi_a)(r) v_jb(r)      ("exchange" integrals, Eq. (7))
+//   CK[ij][ab] = dV sum_r v_ij(r) (phi_a phi_b)(r)      ("Coulomb" integrals)
+// using the symmetry (pq|rs) = (rs|pq) of real orbitals, so only the n_occ*n_virt and
+// n_occ(n_occ+1)/2 pair potentials are solved.  The products phi_i phi_a and phi_a phi_b are
+// generated while tiles are staged, never stored.  Both contractions are split over the grid
+// (split-K) with FP64 partial sums reduced in a fixed order.
+#include <algorithm>
+
+#include "common.hpp"
+#include "tda.hpp"
+
+namespace ace {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, kThreads = 256;
+constexpr int kSub = 256;  // points summed in the storage precision before an FP64 add
+
+template <typename T>
+struct Op {
+  const T* p;   // rows of length ng, or first factor
+  const T* q;   // second factor (product mode) or null
+  int div;      // product mode: row -> (row / div, row % div)
+};
+
+template <typename T>
+__device__ __forceinline__ T op_load(const Op<T>& o, int row, size_t k, size_t ng) {
+  if (o.q) return o.p[(size_t)(row / o.div) * ng + k] * o.q[(size_t)(row % o.div) * ng + k];
+  return o.p[(size_t)row * ng + k];
+}
+
+// part[z][m][n] = sum_{k in split z} A(m,k) B(n,k)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gemm_nt(Op<T> A, int M, Op<T> B, int N, size_t ng,
+                                                      size_t kchunk, double* __restrict__ part) {
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const size_t k0 = (size_t)blockIdx.z * kchunk;
+  const size_t k1 = k0 + kchunk < ng ? k0 + kchunk : ng;
+  double acc[4][4];
+  T sub[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = 0.0;
+      sub[i][j] = T(0);
+    }
+  int steps = 0;
+  for (size_t kt = k0; kt < k1; kt += BK) {
+    for (int idx = threadIdx.x; idx < BM * BK; idx += kThreads) {
+      const int r = idx / BK, kk = idx % BK;
+      const size_t k = kt + kk;
+      const int m = m0 + r, n = n0 + r;
+      As[kk][r] = (m < M && k < k1) ? op_load(A, m, k, ng) : T(0);
+      Bs[kk][r] = (n < N && k < k1) ? op_load(B, n, k, ng) : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sub[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+    if (++steps == kSub / BK) {
+      steps = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] += (double)sub[i][j];
+          sub[i][j] = T(0);
+        }
+    }
+  }
+  double* dst = part + (size_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (m < M && n < N) dst[(size_t)m * N + n] = acc[i][j] + (double)sub[i][j];
+    }
+}
+
+__global__ void k_split_reduce(const double* __restrict__ part, int nsplit, size_t count,
+                               double scale, double* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * count + i];
+    out[i] = s * scale;
+  }
+}
+
+__global__ void k_tda_assemble(const double* __restrict__ cj, const double* __restrict__ ck,
+                               int no, int nv, int delta_m, double* __restrict__ c) {
+  const size_t nov = (size_t)no * nv;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nov * nov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / nov, col = idx % nov;
+    const int i = (int)(row / nv), a = (int)(row % nv), j = (int)(col / nv), b = (int)(col % nv);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    const size_t q = (size_t)hi * (hi + 1) / 2 + lo;
+    c[idx] = delta_m * cj[idx] - ck[q * (size_t)nv * nv + (size_t)a * nv + b];
+  }
+}
+
+template <typename T>
+void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_ov,
+              const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
+              double* c_out, hipStream_t s, Trace* tr) {
+  const int nov = no * nv, noo = no * (no + 1) / 2, nvv = nv * nv;
+  char* base = (char*)ws;
+  double* pj = (double*)(base + w.off_pj);
+  double* pk = (double*)(base + w.off_pk);
+  double* cj = (double*)(base + w.off_cj);
+  double* ck = (double*)(base + w.off_ck);
+  Op<T> a_ov{(const T*)occ, (const T*)virt, nv};
+  Op<T> b_ov{(const T*)v_ov, nullptr, 1};
+  Op<T> a_oo{(const T*)v_oo, nullptr, 1};
+  Op<T> b_vv{(const T*)virt, (const T*)virt, nv};
+  {
+    TraceScope ts(tr, TR_TDA_GEMM);
+    dim3 gj((nov + BM - 1) / BM, (nov + BN - 1) / BN, w.nsplit);
+    k_gemm_nt<T><<<gj, kThreads, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, pj);
+    dim3 gk((noo + BM - 1) / BM, (nvv + BN - 1) / BN, w.nsplit);
+    k_gemm_nt<T><<<gk, kThreads, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, pk);
+  }
+  TraceScope ts(tr, TR_TDA_REDUCE);
+  const size_t cntj = (size_t)nov * nov, cntk = (size_t)noo * nvv;
+  k_split_reduce<<<(unsigned)std::min<size_t>(4096, (cntj + 255) / 256), 256, 0, s>>>(pj, w.nsplit, cntj, dv, cj);
+  k_split_reduce<<<(unsigned)std::min<size_t>(4096, (cntk + 255) / 256), 256, 0, s>>>(pk, w.nsplit, cntk, dv, ck);
+  k_tda_assemble<<<(unsigned)std::min<size_t>(4096, (cntj + 255) / 256), 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out);
+}
+
+}  // namespace
+
+size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
+  (void)fp64;
+  const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2, nvv = (size_t)nv * nv;
+  // enough blocks for the GPU: at least ~1024 for the larger contraction
+  const size_t tiles = ((nov + BM - 1) / BM) * ((nov + BN - 1) / BN);
+  size_t nsplit = (1024 + tiles - 1) / tiles;
+  size_t kchunk = (ng + nsplit - 1) / nsplit;
+  kchunk = ((kchunk + kSub - 1) / kSub) * kSub;
+  if (kchunk < kSub) kchunk = kSub;
+  nsplit = (ng + kchunk - 1) / kchunk;
+  w->nsplit = (int)nsplit;
+  w->kchunk = kchunk;
+  w->off_pj = 0;
+  w->off_pk = w->off_pj + nsplit * nov * nov * sizeof(double);
+  w->off_cj = w->off_pk + nsplit * noo * nvv * sizeof(double);
+  w->off_ck = w->off_cj + nov * nov * sizeof(double);
+  return w->off_ck + noo * nvv * sizeof(double);
+}
+
+void launch_tda(bool fp64, const void* occ, int no, const void* virt, int nv, const void* v_ov,
+                const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
+                double* c_out, hipStream_t s, Trace* tr) {
+  if (fp64)
+    tda_impl<double>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, s, tr);
+  else
+    tda_impl<float>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, s, tr);
+}
+
+}  // namespace ace

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every entry point that
+include/ace.h declares, and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ace.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+([a-z_]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    from paper_2405_01522_amd import _lib
+    decl = _declared()
+    assert "ace_build" in decl and "tda_coupling" in decl and "pair_poisson_batched" in decl
+    assert set(decl) == set(_lib.SIGNATURES)
+
+
+def test_library_exports_every_symbol():
+    from paper_2405_01522_amd import _lib
+    lib = _lib.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for name in _declared():
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
+def test_size_table_and_messages():
+    from paper_2405_01522_amd import _lib
+    lib = _lib.lib()
+    for n in (8, 9, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64):
+        assert lib.ace_size_supported(n, 1) == 1          # FP32 complex
+    assert lib.ace_size_supported(48, 0) == 1             # FP64: P = 96 plane fits in LDS
+    assert lib.ace_size_supported(56, 0) == 0             # FP64: P = 112 plane does not
+    assert lib.ace_size_supported(11, 1) == 0             # radix 11 not compiled
+    assert lib.ace_size_supported(16, 7) == 0             # bad dtype
+    assert lib.ace_strerror(-5).decode() == "-M is not positive definite"
+
+
+def test_invalid_arguments_rejected_on_host():
+    from paper_2405_01522_amd import _lib
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    assert lib.ace_ctx_create(16, 0.0, 0, None, ctypes.byref(h)) == -1
+    assert lib.ace_ctx_create(16, 0.3, 9, None, ctypes.byref(h)) == -1
+    assert lib.ace_ctx_create(11, 0.3, 0, None, ctypes.byref(h)) == -2
+    assert lib.ace_ctx_create(16, 0.3, 0, None, None) == -1
+    assert lib.ace_build(None, None, 1, None, None, None) == -1
+    assert lib.ace_apply(None, None, 1, None, 1, None) == -1
+    assert lib.pair_poisson_batched(None, None, 1, None, 1, None, 1, None) == -1
+    assert lib.tda_coupling(None, None, 1, None, 1, 2, None) == -1
+    assert lib.ace_ctx_destroy(None) == 0
+
+
+@pytest.mark.slow
+def test_register_dft_and_two_step_transform_on_host(tmp_path):
+    """The register DFTs and the P = P1*P2 two-step transform of the Poisson passes, run on the
+    CPU against a naive long-double DFT (the routines are __host__ __device__)."""
+    exe = tmp_path / "dft_check"
+    src = os.path.join(ROOT, "tests", "native", "dft_host_check.hip")
+    res = subprocess.run(["hipcc", "-O1", "-std=c++17", "-o", str(exe), src],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-3000:]
+    run = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert run.returncode == 0 and "OK" in run.stdout, run.stdout
