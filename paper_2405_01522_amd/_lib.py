@@ -10,7 +10,10 @@ import os
 
 import torch  # noqa: F401  (loads the HIP runtime libace links against)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libace.so")
+# ACE_LIBRARY may name another build of the same sources (e.g. one compiled with different
+# tuning macros); by default the in-tree library is used.
+LIB_PATH = os.environ.get("ACE_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                          "libace.so")
 
 _lib = None
 

@@ -35,35 +35,41 @@ def common_flags():
             "-Wno-unused-command-line-argument", "-I" + os.path.join(ROOT, "include")]
 
 
-def compile_one(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-c"] + common_flags() + ["-x", "hip", os.path.join(CSRC, src), "-o", obj]
+def compile_one(src, defines=(), build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), "-c"] + common_flags() + ["-D" + d for d in defines] + \
+        ["-x", "hip", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), res.stderr[-6000:]))
     return obj
 
 
-def build(jobs=4, verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs=4, verbose=False, defines=(), out=LIB):
+    """Compile and link.  ``defines`` are extra -D macros (tuning knobs such as
+    ACE_XY_THREADS); ``out`` is the library path (default: the in-tree libace.so)."""
+    build_dir = BUILD if out == LIB else os.path.join(BUILD, os.path.basename(out) + ".d")
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: compile_one(s, defines, build_dir), SOURCES))
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), res.stderr[-6000:]))
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("-D", dest="defines", action="append", default=[])
+    ap.add_argument("--out", default=LIB)
     a = ap.parse_args(argv)
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, defines=a.defines, out=os.path.abspath(a.out))
 
 
 if __name__ == "__main__":

@@ -116,6 +116,7 @@ struct ace_ctx {
   int device = 0;
   double* ghat64 = nullptr;
   float* ghat32 = nullptr;
+  void* gpos = nullptr;      // kernel spectrum in FFT position order, compute precision
   void* tw = nullptr;        // P twiddles exp(-2 pi i m / P) in the compute precision
   int* status = nullptr;     // device: [code, info]
   Buf work, vbuf, wbuf, part, small, pairs, tda;
@@ -188,7 +189,7 @@ int run_pairs(ace_ctx* c, const void* pa, const void* pb, const int* pairs_dev, 
   int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)items, budget / per_item));
   int rc = ensure(c, c->work, per_item * (size_t)batch);
   if (rc) return rc;
-  const void* gh = fp64 ? (const void*)c->ghat64 : (const void*)c->ghat32;
+  const void* gh = c->gpos;
   const size_t eb = elem_bytes(c->dtype);
   for (int i0 = 0; i0 < items; i0 += batch) {
     const int ni = std::min(batch, items - i0);
@@ -246,6 +247,7 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
   if (hipMalloc(&c->ghat64, oct * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->ghat32, oct * sizeof(float)) != hipSuccess ||
       hipMalloc(&c->tw, (fp64 ? 16 : 8) * (size_t)p) != hipSuccess ||
+      hipMalloc(&c->gpos, (fp64 ? 8 : 4) * (size_t)p * p * p) != hipSuccess ||
       hipMalloc(&c->status, 4 * sizeof(int)) != hipSuccess ||
       hipMalloc(&d_cos, cosw.size() * sizeof(double)) != hipSuccess ||
       hipMalloc(&t0, oct * sizeof(double)) != hipSuccess ||
@@ -262,6 +264,7 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
   }
   if (!rc) {
     launch_kernel_setup(n, h, kC0, d_cos, t0, t1, c->ghat64, c->ghat32, c->stream);
+    launch_kernel_positions(n, fp64, c->ghat64, c->gpos, c->stream);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
       rc = ACE_ERR_HIP;
   }
@@ -286,6 +289,7 @@ int ace_ctx_destroy(ace_ctx* c) {
   if (c->ghat64) (void)hipFree(c->ghat64);
   if (c->ghat32) (void)hipFree(c->ghat32);
   if (c->tw) (void)hipFree(c->tw);
+  if (c->gpos) (void)hipFree(c->gpos);
   if (c->status) (void)hipFree(c->status);
   if (c->pinned_pairs) (void)hipHostFree(c->pinned_pairs);
   delete c;

@@ -41,9 +41,12 @@ __global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
 }
 
 // Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) over one chunk of points per block.
-// Tiles of kTile points are staged through LDS; products are summed in the storage
-// precision over one tile, then added into FP64 accumulators.  Up to 4 outputs per thread.
-constexpr int kTile = 32;
+// Tiles of kTile points are staged through LDS (rows padded by one element against bank
+// conflicts); a thread owns one output (k, l) and a strided subset of the tile's points when
+// there are at most 256 outputs, else up to 4 outputs over all points.  Products are summed in
+// the storage precision over one tile, then added into FP64 accumulators.
+constexpr int kTile = 64;
+constexpr int kLS = kTile + 1;
 
 template <typename E>
 __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int na,
@@ -53,10 +56,11 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
   typedef typename Elem<E>::wide W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   E* sA = reinterpret_cast<E*>(smem_raw);
-  E* sB = sA + (size_t)na * kTile;
+  E* sB = sA + (size_t)na * kLS;
   const int no = na * nb;
-  const int lanes = no <= kThreads ? kThreads / no : 1;
-  const int lane = no <= kThreads ? threadIdx.x / no : 0;
+  const bool few = no <= kThreads;
+  const int lanes = few ? kThreads / no : 1;
+  const int lane = few ? threadIdx.x / no : 0;
   const size_t start = (size_t)blockIdx.x * chunk;
   const size_t end = start + chunk < ng ? start + chunk : ng;
   W acc[4];
@@ -68,30 +72,26 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
       const size_t r = t0 + c;
       E val = e_zero<E>();
       if (r < end) val = row < na ? A[(size_t)row * ng + r] : B[(size_t)(row - na) * ng + r];
-      if (row < na)
-        sA[row * kTile + c] = val;
-      else
-        sB[(row - na) * kTile + c] = val;
+      sA[row * kLS + c] = val;  // sB rows follow sA rows contiguously
     }
     __syncthreads();
     if (lane < lanes) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int o = no <= kThreads ? (m == 0 ? (int)(threadIdx.x % no) : no)
-                                     : (int)threadIdx.x + m * kThreads;
+        const int o = few ? (m == 0 ? (int)(threadIdx.x % no) : no) : (int)threadIdx.x + m * kThreads;
         if (o < no) {
-          const int k = o / nb, l = o % nb;
+          const E* ra = sA + (o / nb) * kLS;
+          const E* rb = sB + (o % nb) * kLS;
           E s = e_zero<E>();
-          for (int c = lane; c < kTile; c += lanes) s = e_add(s, e_mulc(sA[k * kTile + c], sB[l * kTile + c]));
+          for (int c = lane; c < kTile; c += lanes) s = e_add(s, e_mulc(ra[c], rb[c]));
           acc[m] = e_add(acc[m], e_wide(s));
         }
       }
     }
     __syncthreads();
   }
-  // reduce the lanes (only when several lanes share an output)
   W* red = reinterpret_cast<W*>(smem_raw);
-  if (no <= kThreads) {
+  if (few) {
     red[threadIdx.x] = acc[0];
     __syncthreads();
     if ((int)threadIdx.x < no) {
@@ -217,23 +217,31 @@ __global__ __launch_bounds__(kThreads) void k_trsm(const E* w, int n, size_t ng,
   }
 }
 
-// out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).
+// out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
+// vector groups of kVB): more threads than points so that the GPU is filled.
+constexpr int kVB = 4;
+
 template <typename E, int NMAX>
 __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi, int n, size_t ng,
                                                         const typename Elem<E>::wide* __restrict__ z,
                                                         int nv, E* __restrict__ out) {
   const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const int v0 = blockIdx.y * kVB;
   if (r >= ng) return;
   E xr[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k)
     if (k < n) xr[k] = xi[(size_t)k * ng + r];
-  for (int v = 0; v < nv; ++v) {
-    E s = e_zero<E>();
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-      if (k < n) s = e_add(s, e_mul(xr[k], e_narrow<E>(z[k * nv + v])));
-    out[(size_t)v * ng + r] = e_neg(s);
+  for (int vb = 0; vb < kVB; ++vb) {
+    const int v = v0 + vb;
+    if (v < nv) {
+      E s = e_zero<E>();
+#pragma unroll
+      for (int k = 0; k < NMAX; ++k)
+        if (k < n) s = e_add(s, e_mul(xr[k], e_narrow<E>(z[k * nv + v])));
+      out[(size_t)v * ng + r] = e_neg(s);
+    }
   }
 }
 
@@ -241,7 +249,7 @@ template <typename E>
 void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nblk,
                size_t chunk, double scale, void* out, hipStream_t s) {
   typedef typename Elem<E>::wide W;
-  const size_t lds_tiles = (size_t)(na + nb) * kTile * sizeof(E);
+  const size_t lds_tiles = (size_t)(na + nb) * kLS * sizeof(E);
   const size_t lds_red = (size_t)kThreads * sizeof(W);
   const size_t lds = lds_tiles > lds_red ? lds_tiles : lds_red;
   k_gram<E><<<nblk, kThreads, lds, s>>>((const E*)A, na, (const E*)B, nb, ng, chunk, (W*)part);
@@ -252,8 +260,8 @@ void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* pa
 }  // namespace
 
 int gram_blocks(size_t ng, size_t* chunk) {
-  // about 2048 points per block, at least one block
-  size_t c = 2048;
+  // 256 points per block: enough blocks to fill the GPU at the box sizes of interest
+  size_t c = 256;
   size_t nblk = (ng + c - 1) / c;
   if (nblk < 1) nblk = 1;
   *chunk = c;
@@ -324,7 +332,7 @@ template <typename E>
 static void apply_impl(const void* xi, int n, size_t ng, const void* z, int nv, void* out,
                        hipStream_t s) {
   typedef typename Elem<E>::wide W;
-  const unsigned blocks = (unsigned)((ng + kThreads - 1) / kThreads);
+  dim3 blocks((unsigned)((ng + kThreads - 1) / kThreads), (unsigned)((nv + kVB - 1) / kVB));
   if (n <= 8)
     k_apply_out<E, 8><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
   else if (n <= 16)

@@ -38,10 +38,15 @@ size_t poisson_work_bytes_per_item(int n, bool fp64);
 void launch_kernel_setup(int n, double h, double c0, const double* cosw, double* tmp0,
                          double* tmp1, double* ghat64, float* ghat32, hipStream_t s);
 
+// Kernel spectrum reordered to the position order of the FFT passes, full (2N)^3 array in
+// the compute precision (double if fp64 else float), from the FP64 octant.
+void launch_kernel_positions(int n, bool fp64, const double* oct, void* gpos, hipStream_t s);
+
 // Pair Poisson solves for items [0, nitems).  Complex mode: item p is pair (pairs[2p],
 // pairs[2p+1]) and v[p] = G (*) (conj(a_j) b_i).  Real-packed mode: item p covers pairs 2p
 // and 2p+1 of the list (np pairs in total) and v is real, one volume per pair.
-// phi_*: orbital arrays; work: nitems * work_bytes_per_item; v_out: output volumes.
+// phi_*: orbital arrays; work: nitems * work_bytes_per_item; v_out: output volumes;
+// ghat: the position-ordered kernel spectrum of launch_kernel_positions.
 void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
                          const void* phi_b, const int* pairs_dev, int np, void* work,
                          void* v_out, const void* ghat, const void* tw, hipStream_t s,

@@ -15,6 +15,8 @@
 // forward second factor, the kernel multiply and the inverse first factor are fused in
 // registers.  The kernel spectrum is real and even, so it is stored as the octant
 // (P/2+1)^3 and indexed by min(k, P-k) per axis; it already carries dV / P^3.
+#include <algorithm>
+
 #include "common.hpp"
 #include "fftplan.hpp"
 #include "internal.hpp"
@@ -23,12 +25,25 @@ namespace ace {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // z passes
+#ifndef ACE_XY_THREADS
+#define ACE_XY_THREADS 256
+#endif
+constexpr int kXyThreads = ACE_XY_THREADS;  // XY pass (one P x P plane per workgroup)
 
 template <typename T>
 __device__ __forceinline__ C2<T>* lds() {
   extern __shared__ __align__(16) unsigned char ace_smem[];
   return reinterpret_cast<C2<T>*>(ace_smem);
+}
+
+// Copy the P twiddles exp(-2 pi i m / P) into LDS (after `off` elements of the LDS array).
+template <typename T, int P>
+__device__ __forceinline__ const C2<T>* stage_twiddles(C2<T>* base, int off,
+                                                       const C2<T>* __restrict__ tw) {
+  C2<T>* s = base + off;
+  for (int m = threadIdx.x; m < P; m += blockDim.x) s[m] = tw[m];
+  return s;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -38,11 +53,13 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(const void* __restrict__ pa_,
                                                    const void* __restrict__ pb_,
                                                    const int* __restrict__ pairs, int np,
                                                    C2<T>* __restrict__ work,
-                                                   const C2<T>* __restrict__ tw) {
+                                                   const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   constexpr size_t NG = (size_t)N * N * N;
   C2<T>* buf = lds<T>();
+  const C2<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
+  __syncthreads();
   const int x = blockIdx.x;
   const int p = blockIdx.y;
   const size_t plane = (size_t)x * N * N;
@@ -97,19 +114,20 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(const void* __restrict__ pa_,
 // ---------------------------------------------------------------------------------------
 // XY pass: one qz plane per workgroup, the whole P x P plane in LDS.
 template <typename T, int N>
-__global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
-                                                 const T* __restrict__ ghat,
-                                                 const C2<T>* __restrict__ tw) {
+__global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
+                                                 const T* __restrict__ gpos,
+                                                 const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
-  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1, HO = PL::HO;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   C2<T>* pl = lds<T>();
+  const C2<T>* tw = stage_twiddles<T, P>(pl, P * RS, twg);
+  __syncthreads();
   const int qz = blockIdx.x, p = blockIdx.y;
   C2<T>* g = work + ((size_t)p * P + qz) * N * N;
-  const int kz = PL::freq(qz);
-  const T* gz = ghat + (kz <= P - kz ? kz : P - kz);
+  const T* gz = gpos + (size_t)qz * P * P;  // kernel spectrum in position order [qz][qx][qy]
 
   // 1. y forward, first factor (rows x < N, input y < N): global -> LDS
-  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P2; it += kXyThreads) {
     const int n2 = it % P2, x = it / P2;
     C2<T> v[P1];
 #pragma unroll
@@ -121,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
   }
   __syncthreads();
   // 2. y forward, second factor
-  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P1; it += kXyThreads) {
     const int x = it % N, k1 = it / N;
     C2<T> v[P2];
     C2<T>* row = pl + x * RS + k1 * P2;
@@ -133,7 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
   }
   __syncthreads();
   // 3. x forward, first factor (columns qy, input x < N)
-  for (int it = threadIdx.x; it < P * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < P * P2; it += kXyThreads) {
     const int qy = it % P, n2 = it / P;
     C2<T> v[P1];
 #pragma unroll
@@ -145,27 +163,21 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
   }
   __syncthreads();
   // 4. x forward second factor, kernel multiply, x inverse first factor (in registers)
-  for (int it = threadIdx.x; it < P * P1; it += kThreads) {
+  for (int it = threadIdx.x; it < P * P1; it += kXyThreads) {
     const int qy = it % P, k1 = it / P;
     C2<T> v[P2];
 #pragma unroll
     for (int k2 = 0; k2 < P2; ++k2) v[k2] = pl[(k1 * P2 + k2) * RS + qy];
     dft<T, P2, -1>(v);
-    const int ky = PL::freq(qy);
-    const T* gy = gz + (size_t)(ky <= P - ky ? ky : P - ky) * HO;
 #pragma unroll
-    for (int k2 = 0; k2 < P2; ++k2) {
-      const int kx = k1 + P1 * k2;
-      const T gk = gy[(size_t)(kx <= P - kx ? kx : P - kx) * HO * HO];
-      v[k2] = cscale(v[k2], gk);
-    }
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = cscale(v[k2], gz[(k1 * P2 + k2) * P + qy]);
     dft<T, P2, 1>(v);
 #pragma unroll
     for (int k2 = 0; k2 < P2; ++k2) pl[(k1 * P2 + k2) * RS + qy] = v[k2];
   }
   __syncthreads();
   // 5. x inverse, second factor, output x < N only
-  for (int it = threadIdx.x; it < P * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < P * P2; it += kXyThreads) {
     const int qy = it % P, n2 = it / P;
     C2<T> v[P1];
     v[0] = pl[n2 * RS + qy];
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
   }
   __syncthreads();
   // 6. y inverse, first factor (rows x < N)
-  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P1; it += kXyThreads) {
     const int x = it % N, k1 = it / N;
     C2<T> v[P2];
     C2<T>* row = pl + x * RS + k1 * P2;
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
   }
   __syncthreads();
   // 7. y inverse, second factor, output y < N: LDS -> global (in place over the input slice)
-  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P2; it += kXyThreads) {
     const int n2 = it % P2, x = it / P2;
     C2<T> v[P1];
     v[0] = pl[x * RS + n2];
@@ -206,11 +218,12 @@ __global__ __launch_bounds__(kThreads) void k_xy(C2<T>* __restrict__ work,
 template <typename T, int N, bool RP>
 __global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ work,
                                                    void* __restrict__ vout_, int np,
-                                                   const C2<T>* __restrict__ tw) {
+                                                   const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   constexpr size_t NG = (size_t)N * N * N;
   C2<T>* buf = lds<T>();
+  const C2<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
   const int x = blockIdx.x, p = blockIdx.y;
   const C2<T>* src0 = work + (size_t)p * P * N * N + (size_t)x * N;
   for (int it = threadIdx.x; it < N * P1; it += kThreads) {
@@ -282,6 +295,24 @@ __global__ void k_ghat_final(const double* __restrict__ in, double* __restrict__
   }
 }
 
+// Kernel spectrum in the position order of the passes: g[qz][qx][qy] = ghat(f(qx), f(qy),
+// f(qz)) with f(q) = q / P2 + P1 (q % P2) and the octant folded by min(k, P - k).
+template <typename T>
+__global__ void k_ghat_positions(const double* __restrict__ oct, T* __restrict__ g, int p,
+                                 int p1, int p2) {
+  const int ho = p / 2 + 1;
+  const size_t total = (size_t)p * p * p;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int qy = (int)(i % p), qx = (int)((i / p) % p), qz = (int)(i / ((size_t)p * p));
+    int fx = qx / p2 + p1 * (qx % p2), fy = qy / p2 + p1 * (qy % p2), fz = qz / p2 + p1 * (qz % p2);
+    fx = fx <= p - fx ? fx : p - fx;
+    fy = fy <= p - fy ? fy : p - fy;
+    fz = fz <= p - fz ? fz : p - fz;
+    g[i] = (T)oct[((size_t)fx * ho + fy) * ho + fz];
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
@@ -296,8 +327,8 @@ void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int 
   constexpr int P = PL::P;
   const int items = rp ? (np + 1) / 2 : np;
   if (items <= 0) return;
-  const size_t lds_z = (size_t)N * (P + 1) * sizeof(C2<T>);
-  const size_t lds_xy = (size_t)P * (P + 1) * sizeof(C2<T>);
+  const size_t lds_z = ((size_t)N * (P + 1) + P) * sizeof(C2<T>);
+  const size_t lds_xy = ((size_t)P * (P + 1) + P) * sizeof(C2<T>);
   C2<T>* w = reinterpret_cast<C2<T>*>(work);
   const C2<T>* t = reinterpret_cast<const C2<T>*>(tw);
   const T* gh = reinterpret_cast<const T*>(ghat);
@@ -319,7 +350,7 @@ void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int 
   }
   {
     TraceScope ts(tr, TR_XY);
-    k_xy<T, N><<<gxy, kThreads, lds_xy, s>>>(w, gh, t);
+    k_xy<T, N><<<gxy, kXyThreads, lds_xy, s>>>(w, gh, t);
   }
   {
     TraceScope ts(tr, TR_ZINV);
@@ -334,7 +365,7 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename T, int N>
 constexpr bool fits() {
-  return (size_t)(2 * N) * (2 * N + 1) * sizeof(C2<T>) <= kMaxLds;
+  return ((size_t)(2 * N) * (2 * N + 1) + 2 * N) * sizeof(C2<T>) <= kMaxLds;
 }
 
 #define ACE_SIZES(X) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(24) X(32) X(40) X(48) X(56) X(64)
@@ -351,6 +382,16 @@ bool poisson_size_supported(int n, bool fp64) {
       return false;
   }
 #undef ACE_CASE
+}
+
+void launch_kernel_positions(int n, bool fp64, const double* oct, void* gpos, hipStream_t s) {
+  const int p = 2 * n, p1 = plan_p1(p), p2 = p / p1;
+  const size_t total = (size_t)p * p * p;
+  const unsigned blocks = (unsigned)std::min<size_t>(65535, (total + 255) / 256);
+  if (fp64)
+    k_ghat_positions<double><<<blocks, 256, 0, s>>>(oct, (double*)gpos, p, p1, p2);
+  else
+    k_ghat_positions<float><<<blocks, 256, 0, s>>>(oct, (float*)gpos, p, p1, p2);
 }
 
 size_t poisson_work_bytes_per_item(int n, bool fp64) {
