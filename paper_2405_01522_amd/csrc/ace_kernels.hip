@@ -42,9 +42,9 @@ __global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
 
 // Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) over one chunk of points per block.
 // Tiles of kTile points are staged through LDS (rows padded by one element against bank
-// conflicts); a thread owns one output (k, l) and a strided subset of the tile's points when
-// there are at most 256 outputs, else up to 4 outputs over all points.  Products are summed in
-// the storage precision over one tile, then added into FP64 accumulators.
+// conflicts).  A thread owns a 2x2 block of outputs (k, k+1) x (l, l+1) and a strided subset of
+// the tile's points; products are summed in the storage precision over one tile, then added
+// into FP64 accumulators.  Partials are written output-major: part[o][block].
 constexpr int kTile = 64;
 constexpr int kLS = kTile + 1;
 
@@ -56,142 +56,169 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
   typedef typename Elem<E>::wide W;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   E* sA = reinterpret_cast<E*>(smem_raw);
-  E* sB = sA + (size_t)na * kLS;
-  const int no = na * nb;
-  const bool few = no <= kThreads;
-  const int lanes = few ? kThreads / no : 1;
-  const int lane = few ? threadIdx.x / no : 0;
+  E* sB = sA + (size_t)(na + 1) * kLS;      // one spare row each so k+1 / l+1 are readable
+  const int qa = (na + 1) / 2, qb = (nb + 1) / 2, nq = qa * qb;
+  const int lanes = nq <= kThreads ? kThreads / nq : 1;
+  const int q = threadIdx.x % nq, lane = threadIdx.x / nq;
+  const int k0 = 2 * (q / qb), l0 = 2 * (q % qb);
+  const bool active = nq <= kThreads ? lane < lanes : true;
   const size_t start = (size_t)blockIdx.x * chunk;
   const size_t end = start + chunk < ng ? start + chunk : ng;
-  W acc[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) acc[m] = W{};
+  W acc[2][2] = {};
   for (size_t t0 = start; t0 < end; t0 += kTile) {
-    for (int idx = threadIdx.x; idx < (na + nb) * kTile; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < (na + nb + 2) * kTile; idx += kThreads) {
       const int row = idx / kTile, c = idx % kTile;
       const size_t r = t0 + c;
       E val = e_zero<E>();
-      if (r < end) val = row < na ? A[(size_t)row * ng + r] : B[(size_t)(row - na) * ng + r];
-      sA[row * kLS + c] = val;  // sB rows follow sA rows contiguously
+      if (r < end) {
+        if (row < na) val = A[(size_t)row * ng + r];
+        else if (row > na && row <= na + nb) val = B[(size_t)(row - na - 1) * ng + r];
+      }
+      sA[row * kLS + c] = val;  // rows: A[0..na), spare, B[0..nb), spare
     }
     __syncthreads();
-    if (lane < lanes) {
+    if (active && nq <= kThreads) {
+      const E* a0 = sA + k0 * kLS;
+      const E* b0 = sB + l0 * kLS;
+      E s00 = e_zero<E>(), s01 = e_zero<E>(), s10 = e_zero<E>(), s11 = e_zero<E>();
+      for (int c = lane; c < kTile; c += lanes) {
+        const E x0 = a0[c], x1 = a0[kLS + c], y0 = b0[c], y1 = b0[kLS + c];
+        s00 = e_add(s00, e_mulc(x0, y0));
+        s01 = e_add(s01, e_mulc(x0, y1));
+        s10 = e_add(s10, e_mulc(x1, y0));
+        s11 = e_add(s11, e_mulc(x1, y1));
+      }
+      acc[0][0] = e_add(acc[0][0], e_wide(s00));
+      acc[0][1] = e_add(acc[0][1], e_wide(s01));
+      acc[1][0] = e_add(acc[1][0], e_wide(s10));
+      acc[1][1] = e_add(acc[1][1], e_wide(s11));
+    }
+    __syncthreads();
+  }
+  if (nq > kThreads) return;  // more outputs than threads: rejected on the host
+  // reduce the lanes of each 2x2 block in fixed order, then write output-major partials
+  W* red = reinterpret_cast<W*>(smem_raw);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int o = few ? (m == 0 ? (int)(threadIdx.x % no) : no) : (int)threadIdx.x + m * kThreads;
-        if (o < no) {
-          const E* ra = sA + (o / nb) * kLS;
-          const E* rb = sB + (o % nb) * kLS;
-          E s = e_zero<E>();
-          for (int c = lane; c < kTile; c += lanes) s = e_add(s, e_mulc(ra[c], rb[c]));
-          acc[m] = e_add(acc[m], e_wide(s));
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      red[threadIdx.x] = active ? acc[u][v] : W{};
+      __syncthreads();
+      if ((int)threadIdx.x < nq) {
+        W s = W{};
+        for (int w = 0; w < lanes; ++w) s = e_add(s, red[w * nq + threadIdx.x]);
+        const int k = k0 + u, l = l0 + v;
+        if (k < na && l < nb) part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = s;
+      }
+      __syncthreads();
+    }
+}
+
+// out[o] = scale * sum_b part[o][b]: one block per output, fixed-order tree.
+template <typename W>
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(const W* __restrict__ part, int nblk,
+                                                          double scale, W* __restrict__ out) {
+  __shared__ W red[kThreads];
+  const int o = blockIdx.x;
+  W s = W{};
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)o * nblk + b]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = e_add(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[o] = e_scale(red[0], scale);
+}
+
+// Cholesky of -M (Hermitised), L^{-H} and E_x in one wavefront, FP64.  Lane i holds row i of
+// the working matrix in registers (right-looking factorisation, pivots broadcast by
+// shuffles); L goes through LDS for the triangular inverse, lane c solving column c.
+template <typename W>
+__device__ __forceinline__ W shfl_w(W v, int src);
+template <>
+__device__ __forceinline__ double shfl_w<double>(double v, int src) { return __shfl(v, src, 64); }
+template <>
+__device__ __forceinline__ C2<double> shfl_w<C2<double>>(C2<double> v, int src) {
+  return {__shfl(v.r, src, 64), __shfl(v.i, src, 64)};
+}
+__device__ __forceinline__ double w_from_real(double r, double) { return r; }
+__device__ __forceinline__ C2<double> w_from_real(double r, C2<double>) { return {r, 0.0}; }
+
+template <typename W, int NMAX>
+__global__ __launch_bounds__(64) void k_chol(const W* __restrict__ mred, int n,
+                                             W* __restrict__ m_out, double* __restrict__ ex_out,
+                                             W* __restrict__ linvh, int* __restrict__ status) {
+  __shared__ W L[NMAX * NMAX];
+  const int i = threadIdx.x;
+  const bool row = i < n;
+  W a[NMAX];
+  bool bad = false;
+  double diag = 0.0;
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) {
+    a[k] = W{};
+    if (row && k < n) {
+      const W mik = mred[i * n + k], mki = mred[k * n + i];
+      bad |= !e_finite(mik);
+      const W herm = e_scale(e_add(mik, e_conj(mki)), 0.5);
+      if (m_out) m_out[i * n + k] = herm;
+      if (k == i) diag = e_re(herm);
+      a[k] = e_neg(herm);
+    }
+  }
+  // E_x = 1/2 sum_i M_ii
+  double e = diag;
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if (i == 0 && ex_out) *ex_out = 0.5 * e;
+  const bool any_bad = __any(bad);
+  int fail = -1;
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    if (j < n) {
+      const double piv = __shfl(e_re(a[j]), j, 64);
+      if (!(piv > 0.0) && fail < 0) fail = j;
+      const double d = piv > 0.0 ? sqrt(piv) : 1.0;
+      const W lij = (i > j) ? e_scale(a[j], 1.0 / d) : (i == j ? w_from_real(d, W{}) : W{});
+      a[j] = lij;
+#pragma unroll
+      for (int k = j + 1; k < NMAX; ++k) {
+        if (k < n) {
+          const W lkj = shfl_w(lij, k);
+          a[k] = e_sub(a[k], e_mul(lij, e_conj(lkj)));
         }
       }
     }
-    __syncthreads();
   }
-  W* red = reinterpret_cast<W*>(smem_raw);
-  if (few) {
-    red[threadIdx.x] = acc[0];
-    __syncthreads();
-    if ((int)threadIdx.x < no) {
-      W s = W{};
-      for (int q = 0; q < lanes; ++q) s = e_add(s, red[q * no + threadIdx.x]);
-      part[(size_t)blockIdx.x * no + threadIdx.x] = s;
-    }
-  } else {
+  if (row) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int o = (int)threadIdx.x + m * kThreads;
-      if (o < no) part[(size_t)blockIdx.x * no + o] = acc[m];
-    }
-  }
-}
-
-template <typename W>
-__global__ void k_gram_reduce(const W* __restrict__ part, int nblk, int no, double scale,
-                              W* __restrict__ out) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= no) return;
-  W s = W{};
-  for (int b = 0; b < nblk; ++b) s = e_add(s, part[(size_t)b * no + o]);
-  out[o] = e_scale(s, scale);
-}
-
-// Cholesky of -M (Hermitised), L^{-H}, E_x; one workgroup.  W is double or C2<double>.
-template <typename W>
-__global__ __launch_bounds__(kThreads) void k_chol(const W* __restrict__ mred, int n,
-                                                   W* __restrict__ m_out, double* __restrict__ ex_out,
-                                                   W* __restrict__ linvh, int* __restrict__ status) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  W* a = reinterpret_cast<W*>(smem_raw);  // n*n: -M, then L in the lower triangle
-  W* x = a + n * n;                       // n*n: L^{-1}
-  __shared__ int fail, bad;
-  if (threadIdx.x == 0) {
-    fail = -1;
-    bad = 0;
+    for (int k = 0; k < NMAX; ++k)
+      if (k < n) L[i * NMAX + k] = k <= i ? a[k] : W{};
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n * n; idx += kThreads) {
-    const int k = idx / n, l = idx % n;
-    const W mkl = mred[k * n + l], mlk = mred[l * n + k];
-    if (!e_finite(mkl)) bad = 1;
-    const W herm = e_scale(e_add(mkl, e_conj(mlk)), 0.5);
-    if (m_out) m_out[idx] = herm;
-    a[idx] = e_neg(herm);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && ex_out) {
-    double e = 0.0;
-    for (int k = 0; k < n; ++k) e += -e_re(a[k * n + k]);
-    *ex_out = 0.5 * e;
-  }
-  // left-looking Cholesky, column by column
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = e_re(a[j * n + j]);
-      for (int k = 0; k < j; ++k) d -= e_abs2(a[j * n + k]);
-      if (!(d > 0.0) && fail < 0) fail = j;
-      double s = d > 0.0 ? sqrt(d) : 1.0;
-      W dj = W{};
-      if constexpr (Elem<W>::cplx) dj.r = s; else dj = s;
-      a[j * n + j] = dj;
+  const bool ok = fail < 0 && !any_bad;
+  // column c = i of X = L^{-1}: X[r][c] = (delta_rc - sum_{c<=k<r} L[r][k] X[k][c]) / L[r][r]
+  if (row) {
+    W x[NMAX];
+#pragma unroll
+    for (int r = 0; r < NMAX; ++r) {
+      x[r] = W{};
+      if (r < n && r >= i) {
+        W s = (r == i) ? w_from_real(1.0, W{}) : W{};
+#pragma unroll
+        for (int k = 0; k < r; ++k)
+          if (k >= i) s = e_sub(s, e_mul(L[r * NMAX + k], x[k]));
+        x[r] = e_scale(s, 1.0 / e_re(L[r * NMAX + r]));
+      }
     }
-    __syncthreads();
-    const double djj = e_re(a[j * n + j]);
-    for (int i = j + 1 + threadIdx.x; i < n; i += kThreads) {
-      W s = a[i * n + j];
-      for (int k = 0; k < j; ++k) s = e_sub(s, e_mulc(a[j * n + k], a[i * n + k]));
-      a[i * n + j] = e_scale(s, 1.0 / djj);
-    }
-    __syncthreads();
+    // L^{-H}[c][k] = conj(X[k][c])
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+      if (k < n) linvh[i * n + k] = ok ? e_conj(x[k]) : W{};
   }
-  // X = L^{-1}: column c solved by one thread
-  for (int c = threadIdx.x; c < n; c += kThreads) {
-    for (int i = 0; i < n; ++i) x[i * n + c] = W{};
-    {
-      W inv = W{};
-      if constexpr (Elem<W>::cplx) inv.r = 1.0 / e_re(a[c * n + c]); else inv = 1.0 / a[c * n + c];
-      x[c * n + c] = inv;
-    }
-    for (int i = c + 1; i < n; ++i) {
-      W s = W{};
-      for (int k = c; k < i; ++k) s = e_add(s, e_mul(a[i * n + k], x[k * n + c]));
-      x[i * n + c] = e_scale(s, -1.0 / e_re(a[i * n + i]));
-    }
-  }
-  __syncthreads();
-  const bool ok = fail < 0 && !bad;
-  // L^{-H}[i][k] = conj(X[k][i])
-  for (int idx = threadIdx.x; idx < n * n; idx += kThreads) {
-    const int i = idx / n, k = idx % n;
-    linvh[idx] = ok ? e_conj(x[k * n + i]) : W{};
-  }
-  if (threadIdx.x == 0 && !ok && status) {
-    if (status[0] == 0) {
-      status[0] = bad ? -6 : -5;
-      status[1] = bad ? -1 : fail;
-    }
+  if (i == 0 && !ok && status && status[0] == 0) {
+    status[0] = any_bad ? -6 : -5;
+    status[1] = any_bad ? -1 : fail;
   }
 }
 
@@ -249,12 +276,12 @@ template <typename E>
 void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nblk,
                size_t chunk, double scale, void* out, hipStream_t s) {
   typedef typename Elem<E>::wide W;
-  const size_t lds_tiles = (size_t)(na + nb) * kLS * sizeof(E);
+  const size_t lds_tiles = (size_t)(na + nb + 2) * kLS * sizeof(E);
   const size_t lds_red = (size_t)kThreads * sizeof(W);
   const size_t lds = lds_tiles > lds_red ? lds_tiles : lds_red;
   k_gram<E><<<nblk, kThreads, lds, s>>>((const E*)A, na, (const E*)B, nb, ng, chunk, (W*)part);
   const int no = na * nb;
-  k_gram_reduce<W><<<(no + 255) / 256, 256, 0, s>>>((const W*)part, nblk, no, scale, (W*)out);
+  k_gram_reduce<W><<<no, kThreads, 0, s>>>((const W*)part, nblk, scale, (W*)out);
 }
 
 }  // namespace
@@ -296,13 +323,21 @@ void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, v
                  int* status, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_CHOL);
   if (et == ET_C128 || et == ET_C64) {
-    const size_t lds = 2 * (size_t)n * n * sizeof(C2<double>);
-    k_chol<C2<double>><<<1, kThreads, lds, s>>>((const C2<double>*)mred, n, (C2<double>*)m_out, ex_out,
-                                                (C2<double>*)linvh, status);
+    typedef C2<double> W;
+    if (n <= 8)
+      k_chol<W, 8><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
+    else if (n <= 16)
+      k_chol<W, 16><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
+    else
+      k_chol<W, 32><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
   } else {
-    const size_t lds = 2 * (size_t)n * n * sizeof(double);
-    k_chol<double><<<1, kThreads, lds, s>>>((const double*)mred, n, (double*)m_out, ex_out,
-                                            (double*)linvh, status);
+    typedef double W;
+    if (n <= 8)
+      k_chol<W, 8><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
+    else if (n <= 16)
+      k_chol<W, 16><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
+    else
+      k_chol<W, 32><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
   }
 }
 

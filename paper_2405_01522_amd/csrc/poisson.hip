@@ -27,7 +27,7 @@ namespace {
 
 constexpr int kThreads = 256;  // z passes
 #ifndef ACE_XY_THREADS
-#define ACE_XY_THREADS 256
+#define ACE_XY_THREADS 1024
 #endif
 constexpr int kXyThreads = ACE_XY_THREADS;  // XY pass (one P x P plane per workgroup)
 
