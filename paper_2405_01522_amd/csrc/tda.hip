@@ -95,6 +95,83 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(Op<T> A, int M, Op<T> B, i
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// FP32 contraction on the matrix cores: part[z][m][n] = sum_{k in split z} A(m,k) B(n,k).
+// Block tile 128 x 128, 4 waves of 64 x 64, v_mfma_f32_16x16x4f32 (each wave 4 x 4 MFMA
+// tiles).  Operand tiles of 128 rows x 32 points are staged through LDS (row stride 33 words,
+// conflict-free fragment reads); generated operands (products of two orbitals) are formed
+// while staging.  Lane layout of the 16x16x4 instruction: A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+constexpr int MT = 128, KT = 32, KS = KT + 1;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<float> B, int N,
+                                                      size_t ng, size_t kchunk,
+                                                      float* __restrict__ part) {
+  __shared__ float As[MT * KS];
+  __shared__ float Bs[MT * KS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // wave's 64 x 64 quadrant
+  const int m0 = blockIdx.x * MT, n0 = blockIdx.y * MT;
+  const size_t k0 = (size_t)blockIdx.z * kchunk;
+  const size_t k1 = k0 + kchunk < ng ? k0 + kchunk : ng;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int li = lane & 15, lk = lane >> 4;
+  for (size_t kt = k0; kt < k1; kt += KT) {
+    // stage: 128 rows x 32 points per operand, 16 elements per thread
+#pragma unroll 4
+    for (int e = threadIdx.x; e < MT * KT; e += 256) {
+      const int r = e / KT, kk = e % KT;
+      const size_t k = kt + kk;
+      const bool kin = k < k1;
+      const int m = m0 + r, n = n0 + r;
+      As[r * KS + kk] = (m < M && kin) ? op_load(A, m, k, ng) : 0.f;
+      Bs[r * KS + kk] = (n < N && kin) ? op_load(B, n, k, ng) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 4) {
+      float af[4], bf[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        af[t] = As[(wr * 64 + t * 16 + li) * KS + ks + lk];
+        bf[t] = Bs[(wc * 64 + t * 16 + li) * KS + ks + lk];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* dst = part + (size_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wr * 64 + i * 16 + 4 * lk + r;
+        const int n = n0 + wc * 64 + j * 16 + li;
+        if (m < M && n < N) dst[(size_t)m * N + n] = acc[i][j][r];
+      }
+}
+
+__global__ void k_split_reduce_f32(const float* __restrict__ part, int nsplit, size_t count,
+                                   double scale, double* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += (double)part[(size_t)z * count + i];
+    out[i] = s * scale;
+  }
+}
+
 __global__ void k_split_reduce(const double* __restrict__ part, int nsplit, size_t count,
                                double scale, double* __restrict__ out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
@@ -132,27 +209,42 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
   Op<T> b_ov{(const T*)v_ov, nullptr, 1};
   Op<T> a_oo{(const T*)v_oo, nullptr, 1};
   Op<T> b_vv{(const T*)virt, (const T*)virt, nv};
-  {
-    TraceScope ts(tr, TR_TDA_GEMM);
-    dim3 gj((nov + BM - 1) / BM, (nov + BN - 1) / BN, w.nsplit);
-    k_gemm_nt<T><<<gj, kThreads, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, pj);
-    dim3 gk((noo + BM - 1) / BM, (nvv + BN - 1) / BN, w.nsplit);
-    k_gemm_nt<T><<<gk, kThreads, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, pk);
-  }
-  TraceScope ts(tr, TR_TDA_REDUCE);
   const size_t cntj = (size_t)nov * nov, cntk = (size_t)noo * nvv;
-  k_split_reduce<<<(unsigned)std::min<size_t>(4096, (cntj + 255) / 256), 256, 0, s>>>(pj, w.nsplit, cntj, dv, cj);
-  k_split_reduce<<<(unsigned)std::min<size_t>(4096, (cntk + 255) / 256), 256, 0, s>>>(pk, w.nsplit, cntk, dv, ck);
+  const unsigned rbj = (unsigned)std::min<size_t>(4096, (cntj + 255) / 256);
+  const unsigned rbk = (unsigned)std::min<size_t>(4096, (cntk + 255) / 256);
+  if constexpr (sizeof(T) == 4) {
+    {
+      TraceScope ts(tr, TR_TDA_GEMM);
+      dim3 gj((nov + MT - 1) / MT, (nov + MT - 1) / MT, w.nsplit);
+      k_gemm_nt_mfma<<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj);
+      dim3 gk((noo + MT - 1) / MT, (nvv + MT - 1) / MT, w.nsplit);
+      k_gemm_nt_mfma<<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk);
+    }
+    TraceScope ts(tr, TR_TDA_REDUCE);
+    k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj);
+    k_split_reduce_f32<<<rbk, 256, 0, s>>>((const float*)pk, w.nsplit, cntk, dv, ck);
+  } else {
+    {
+      TraceScope ts(tr, TR_TDA_GEMM);
+      dim3 gj((nov + BM - 1) / BM, (nov + BN - 1) / BN, w.nsplit);
+      k_gemm_nt<T><<<gj, kThreads, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, pj);
+      dim3 gk((noo + BM - 1) / BM, (nvv + BN - 1) / BN, w.nsplit);
+      k_gemm_nt<T><<<gk, kThreads, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, pk);
+    }
+    TraceScope ts(tr, TR_TDA_REDUCE);
+    k_split_reduce<<<rbj, 256, 0, s>>>(pj, w.nsplit, cntj, dv, cj);
+    k_split_reduce<<<rbk, 256, 0, s>>>(pk, w.nsplit, cntk, dv, ck);
+  }
   k_tda_assemble<<<(unsigned)std::min<size_t>(4096, (cntj + 255) / 256), 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out);
 }
 
 }  // namespace
 
 size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
-  (void)fp64;
   const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2, nvv = (size_t)nv * nv;
   // enough blocks for the GPU: at least ~1024 for the larger contraction
-  const size_t tiles = ((nov + BM - 1) / BM) * ((nov + BN - 1) / BN);
+  const size_t tile = fp64 ? BM : MT;
+  const size_t tiles = ((nov + tile - 1) / tile) * ((nov + tile - 1) / tile);
   size_t nsplit = (1024 + tiles - 1) / tiles;
   size_t kchunk = (ng + nsplit - 1) / nsplit;
   kchunk = ((kchunk + kSub - 1) / kSub) * kSub;
