@@ -353,8 +353,8 @@ int ace_apply(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* 
   if (!c || !xi || !psi || !out || n < 1 || n > ACE_MAX_ORBITALS || nv < 1) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   const size_t wide = is_cplx(c->dtype) ? 16 : 8;
-  // the Gram kernel gives each thread a 2x2 block of outputs: ceil(n/2)*ceil(cv/2) <= 256
-  const int chunk_v = std::max(1, std::min(nv, 2 * (256 / ((n + 1) / 2))));
+  // vectors per Gram / update pass (bounds the partial-sum workspace)
+  const int chunk_v = std::max(1, std::min(nv, 64));
   size_t chunk;
   const int nblk = gram_blocks(ng, &chunk);
   int rc = ensure(c, c->part, wide * (size_t)nblk * n * chunk_v);

@@ -40,78 +40,99 @@ __global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
   w[(size_t)i * ng + r] = e_neg(acc);
 }
 
-// Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) over one chunk of points per block.
-// Tiles of kTile points are staged through LDS (rows padded by one element against bank
-// conflicts).  A thread owns a 2x2 block of outputs (k, k+1) x (l, l+1) and a strided subset of
-// the tile's points; products are summed in the storage precision over one tile, then added
-// into FP64 accumulators.  Partials are written output-major: part[o][block].
-constexpr int kTile = 64;
-constexpr int kLS = kTile + 1;
+// Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) on the matrix cores.  Each wavefront
+// owns one chunk of points and one 16 x 16 output tile (k-tile, l-tile) and issues
+// v_mfma_{f32,f64}_16x16x4 with the points as the contraction index: lane (i, g) = (lane % 16,
+// lane / 16) feeds A_{k0+i} and B_{l0+i} at 4 consecutive points r0 + 4g + s, s = 0..3, one
+// instruction per s.  Complex products are four real contractions:
+// conj(a) b = (ar br + ai bi) + i (ar bi - ai br).  Products accumulate in the storage
+// precision over the chunk; the chunk sums are written as FP64 partials part[o][chunk].
+// Lane layout of the 16x16x4 instructions: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16 (i / 4), element i % 4.
+constexpr int kGramChunk = 128;  // points per wavefront
+
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+typedef double gf64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  typedef gf32x4 type;
+  static __device__ __forceinline__ type mma(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaAcc<double> {
+  typedef gf64x4 type;
+  static __device__ __forceinline__ type mma(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ void split_ri(float v, float& r, float& i) { r = v; i = 0.f; }
+__device__ __forceinline__ void split_ri(double v, double& r, double& i) { r = v; i = 0.0; }
+template <typename T>
+__device__ __forceinline__ void split_ri(C2<T> v, T& r, T& i) { r = v.r; i = v.i; }
 
 template <typename E>
 __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int na,
                                                    const E* __restrict__ B, int nb, size_t ng,
-                                                   size_t chunk,
+                                                   int nchunks,
                                                    typename Elem<E>::wide* __restrict__ part) {
+  typedef typename Elem<E>::real T;
   typedef typename Elem<E>::wide W;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  E* sA = reinterpret_cast<E*>(smem_raw);
-  E* sB = sA + (size_t)(na + 1) * kLS;      // one spare row each so k+1 / l+1 are readable
-  const int qa = (na + 1) / 2, qb = (nb + 1) / 2, nq = qa * qb;
-  const int lanes = nq <= kThreads ? kThreads / nq : 1;
-  const int q = threadIdx.x % nq, lane = threadIdx.x / nq;
-  const int k0 = 2 * (q / qb), l0 = 2 * (q % qb);
-  const bool active = nq <= kThreads ? lane < lanes : true;
-  const size_t start = (size_t)blockIdx.x * chunk;
-  const size_t end = start + chunk < ng ? start + chunk : ng;
-  W acc[2][2] = {};
-  for (size_t t0 = start; t0 < end; t0 += kTile) {
-    for (int idx = threadIdx.x; idx < (na + nb + 2) * kTile; idx += kThreads) {
-      const int row = idx / kTile, c = idx % kTile;
-      const size_t r = t0 + c;
-      E val = e_zero<E>();
-      if (r < end) {
-        if (row < na) val = A[(size_t)row * ng + r];
-        else if (row > na && row <= na + nb) val = B[(size_t)(row - na - 1) * ng + r];
-      }
-      sA[row * kLS + c] = val;  // rows: A[0..na), spare, B[0..nb), spare
+  typedef MfmaAcc<T> MA;
+  typedef typename MA::type V;
+  constexpr bool CPLX = Elem<E>::cplx;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (c >= nchunks) return;
+  const int tiles_l = (nb + 15) / 16;
+  const int k0 = (blockIdx.y / tiles_l) * 16, l0 = (blockIdx.y % tiles_l) * 16;
+  const int li = lane & 15, g = lane >> 4;
+  const int ka = k0 + li, lb = l0 + li;
+  const E* ra = ka < na ? A + (size_t)ka * ng : nullptr;
+  const E* rb = lb < nb ? B + (size_t)lb * ng : nullptr;
+  const size_t start = (size_t)c * kGramChunk;
+  const size_t end = start + kGramChunk < ng ? start + kGramChunk : ng;
+  V rr = {}, ii = {}, ri = {}, ir = {};
+  for (size_t r0 = start; r0 < end; r0 += 16) {
+    E av[4], bv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const size_t r = r0 + 4 * g + s;
+      av[s] = (ra && r < end) ? ra[r] : e_zero<E>();
+      bv[s] = (rb && r < end) ? rb[r] : e_zero<E>();
     }
-    __syncthreads();
-    if (active && nq <= kThreads) {
-      const E* a0 = sA + k0 * kLS;
-      const E* b0 = sB + l0 * kLS;
-      E s00 = e_zero<E>(), s01 = e_zero<E>(), s10 = e_zero<E>(), s11 = e_zero<E>();
-      for (int c = lane; c < kTile; c += lanes) {
-        const E x0 = a0[c], x1 = a0[kLS + c], y0 = b0[c], y1 = b0[kLS + c];
-        s00 = e_add(s00, e_mulc(x0, y0));
-        s01 = e_add(s01, e_mulc(x0, y1));
-        s10 = e_add(s10, e_mulc(x1, y0));
-        s11 = e_add(s11, e_mulc(x1, y1));
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      T ar, ai, br, bi;
+      split_ri(av[s], ar, ai);
+      split_ri(bv[s], br, bi);
+      rr = MA::mma(ar, br, rr);
+      if constexpr (CPLX) {
+        ii = MA::mma(ai, bi, ii);
+        ri = MA::mma(ar, bi, ri);
+        ir = MA::mma(ai, br, ir);
       }
-      acc[0][0] = e_add(acc[0][0], e_wide(s00));
-      acc[0][1] = e_add(acc[0][1], e_wide(s01));
-      acc[1][0] = e_add(acc[1][0], e_wide(s10));
-      acc[1][1] = e_add(acc[1][1], e_wide(s11));
     }
-    __syncthreads();
   }
-  if (nq > kThreads) return;  // more outputs than threads: rejected on the host
-  // reduce the lanes of each 2x2 block in fixed order, then write output-major partials
-  W* red = reinterpret_cast<W*>(smem_raw);
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      red[threadIdx.x] = active ? acc[u][v] : W{};
-      __syncthreads();
-      if ((int)threadIdx.x < nq) {
-        W s = W{};
-        for (int w = 0; w < lanes; ++w) s = e_add(s, red[w * nq + threadIdx.x]);
-        const int k = k0 + u, l = l0 + v;
-        if (k < na && l < nb) part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = s;
+  for (int e = 0; e < 4; ++e) {
+    const int k = k0 + 4 * g + e, l = l0 + li;
+    if (k < na && l < nb) {
+      W v;
+      if constexpr (CPLX) {
+        v.r = (double)rr[e] + (double)ii[e];
+        v.i = (double)ri[e] - (double)ir[e];
+      } else {
+        v = (double)rr[e];
       }
-      __syncthreads();
+      part[((size_t)k * nb + l) * nchunks + c] = v;
     }
+  }
 }
 
 // out[o] = scale * sum_b part[o][b]: one block per output, fixed-order tree.
@@ -273,22 +294,21 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
 }
 
 template <typename E>
-void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nblk,
-               size_t chunk, double scale, void* out, hipStream_t s) {
+void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nchunks,
+               double scale, void* out, hipStream_t s) {
   typedef typename Elem<E>::wide W;
-  const size_t lds_tiles = (size_t)(na + nb + 2) * kLS * sizeof(E);
-  const size_t lds_red = (size_t)kThreads * sizeof(W);
-  const size_t lds = lds_tiles > lds_red ? lds_tiles : lds_red;
-  k_gram<E><<<nblk, kThreads, lds, s>>>((const E*)A, na, (const E*)B, nb, ng, chunk, (W*)part);
+  const int per_block = kThreads / 64;
+  dim3 grid((nchunks + per_block - 1) / per_block, ((na + 15) / 16) * ((nb + 15) / 16));
+  k_gram<E><<<grid, kThreads, 0, s>>>((const E*)A, na, (const E*)B, nb, ng, nchunks, (W*)part);
   const int no = na * nb;
-  k_gram_reduce<W><<<no, kThreads, 0, s>>>((const W*)part, nblk, scale, (W*)out);
+  k_gram_reduce<W><<<no, kThreads, 0, s>>>((const W*)part, nchunks, scale, (W*)out);
 }
 
 }  // namespace
 
 int gram_blocks(size_t ng, size_t* chunk) {
-  // 256 points per block: enough blocks to fill the GPU at the box sizes of interest
-  size_t c = 256;
+  // one chunk of points per wavefront
+  size_t c = kGramChunk;
   size_t nblk = (ng + c - 1) / c;
   if (nblk < 1) nblk = 1;
   *chunk = c;
@@ -310,12 +330,12 @@ void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng
                  double scale, void* out, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_GRAM);
   size_t chunk;
-  const int nblk = gram_blocks(ng, &chunk);
+  const int nch = gram_blocks(ng, &chunk);
   switch (et) {
-    case ET_C128: gram_impl<C2<double>>(A, na, B, nb, ng, part, nblk, chunk, scale, out, s); break;
-    case ET_C64: gram_impl<C2<float>>(A, na, B, nb, ng, part, nblk, chunk, scale, out, s); break;
-    case ET_R64: gram_impl<double>(A, na, B, nb, ng, part, nblk, chunk, scale, out, s); break;
-    case ET_R32: gram_impl<float>(A, na, B, nb, ng, part, nblk, chunk, scale, out, s); break;
+    case ET_C128: gram_impl<C2<double>>(A, na, B, nb, ng, part, nch, scale, out, s); break;
+    case ET_C64: gram_impl<C2<float>>(A, na, B, nb, ng, part, nch, scale, out, s); break;
+    case ET_R64: gram_impl<double>(A, na, B, nb, ng, part, nch, scale, out, s); break;
+    case ET_R32: gram_impl<float>(A, na, B, nb, ng, part, nch, scale, out, s); break;
   }
 }
 

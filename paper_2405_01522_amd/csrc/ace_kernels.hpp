@@ -11,12 +11,12 @@ namespace ace {
 // storage element types (same numbering as the public ace_dtype)
 enum { ET_C128 = 0, ET_C64 = 1, ET_R64 = 2, ET_R32 = 3 };
 
-// number of Gram partial blocks for ng points (and the points per block)
+// number of Gram partial chunks for ng points (and the points per chunk)
 int gram_blocks(size_t ng, size_t* chunk);
 
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr);
-// out[k*nb + l] = scale * sum_r conj(A_k(r)) B_l(r), FP64 (complex or real);
-// ceil(na/2) * ceil(nb/2) <= 256.  part: gram_blocks(ng) * na * nb FP64 elements.
+// out[k*nb + l] = scale * sum_r conj(A_k(r)) B_l(r), FP64 (complex or real), any na, nb.
+// part: gram_blocks(ng) * na * nb FP64 elements.
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
                  double scale, void* out, hipStream_t s, Trace* tr);
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,

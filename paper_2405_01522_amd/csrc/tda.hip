@@ -105,14 +105,25 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(Op<T> A, int M, Op<T> B, i
 constexpr int MT = 128, KT = 32, KS = KT + 1;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// tri != 0: M == N and the result is symmetric; blockIdx.x enumerates only the tiles (bx, by)
+// with bx <= by (blockIdx.y unused) and the lower tiles are never computed.
 __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<float> B, int N,
                                                       size_t ng, size_t kchunk,
-                                                      float* __restrict__ part) {
+                                                      float* __restrict__ part, int tri) {
   __shared__ float As[MT * KS];
   __shared__ float Bs[MT * KS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // wave's 64 x 64 quadrant
-  const int m0 = blockIdx.x * MT, n0 = blockIdx.y * MT;
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (tri) {
+    const int u = blockIdx.x;
+    int t = (int)((sqrtf(8.0f * u + 1.0f) - 1.0f) * 0.5f);
+    while ((t + 1) * (t + 2) / 2 <= u) ++t;
+    while (t * (t + 1) / 2 > u) --t;
+    by = t;
+    bx = u - t * (t + 1) / 2;
+  }
+  const int m0 = bx * MT, n0 = by * MT;
   const size_t k0 = (size_t)blockIdx.z * kchunk;
   const size_t k1 = k0 + kchunk < ng ? k0 + kchunk : ng;
   f32x4 acc[4][4];
@@ -162,10 +173,13 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
       }
 }
 
+// ncols > 0: row-major ncols-wide matrix whose tiles below the diagonal were not computed
+// (skipped here too).
 __global__ void k_split_reduce_f32(const float* __restrict__ part, int nsplit, size_t count,
-                                   double scale, double* __restrict__ out) {
+                                   double scale, double* __restrict__ out, int ncols) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x) {
+    if (ncols > 0 && (int)(i / ncols) / MT > (int)(i % ncols) / MT) continue;
     double s = 0.0;
     for (int z = 0; z < nsplit; ++z) s += (double)part[(size_t)z * count + i];
     out[i] = s * scale;
@@ -182,8 +196,12 @@ __global__ void k_split_reduce(const double* __restrict__ part, int nsplit, size
   }
 }
 
+// C[ia][jb] = delta_M CJ[ia][jb] - CK[ij][ab], symmetrised: CJ is taken from the computed
+// (upper) tile of the pair (ia, jb) / (jb, ia), averaged on diagonal tiles, and CK[ij] is
+// averaged over (a, b) / (b, a).  Both are symmetric in exact arithmetic for real orbitals.
+// tile > 0: only tiles with row-tile <= col-tile of CJ hold data.
 __global__ void k_tda_assemble(const double* __restrict__ cj, const double* __restrict__ ck,
-                               int no, int nv, int delta_m, double* __restrict__ c) {
+                               int no, int nv, int delta_m, double* __restrict__ c, int tile) {
   const size_t nov = (size_t)no * nv;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nov * nov;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -191,7 +209,17 @@ __global__ void k_tda_assemble(const double* __restrict__ cj, const double* __re
     const int i = (int)(row / nv), a = (int)(row % nv), j = (int)(col / nv), b = (int)(col % nv);
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     const size_t q = (size_t)hi * (hi + 1) / 2 + lo;
-    c[idx] = delta_m * cj[idx] - ck[q * (size_t)nv * nv + (size_t)a * nv + b];
+    const double* ckq = ck + q * (size_t)nv * nv;
+    const double k = 0.5 * (ckq[(size_t)a * nv + b] + ckq[(size_t)b * nv + a]);
+    double jv;
+    const int tr = tile > 0 ? (int)row / tile : 0, tc = tile > 0 ? (int)col / tile : 0;
+    if (tr < tc)
+      jv = cj[idx];
+    else if (tr > tc)
+      jv = cj[col * nov + row];
+    else
+      jv = 0.5 * (cj[idx] + cj[col * nov + row]);
+    c[idx] = delta_m * jv - k;
   }
 }
 
@@ -213,16 +241,19 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
   const unsigned rbj = (unsigned)std::min<size_t>(4096, (cntj + 255) / 256);
   const unsigned rbk = (unsigned)std::min<size_t>(4096, (cntk + 255) / 256);
   if constexpr (sizeof(T) == 4) {
+    const int tj = (nov + MT - 1) / MT;
     {
       TraceScope ts(tr, TR_TDA_GEMM);
-      dim3 gj((nov + MT - 1) / MT, (nov + MT - 1) / MT, w.nsplit);
-      k_gemm_nt_mfma<<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj);
+      dim3 gj(tj * (tj + 1) / 2, 1, w.nsplit);  // upper tiles only: CJ is symmetric
+      k_gemm_nt_mfma<<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
       dim3 gk((noo + MT - 1) / MT, (nvv + MT - 1) / MT, w.nsplit);
-      k_gemm_nt_mfma<<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk);
+      k_gemm_nt_mfma<<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
     }
     TraceScope ts(tr, TR_TDA_REDUCE);
-    k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj);
-    k_split_reduce_f32<<<rbk, 256, 0, s>>>((const float*)pk, w.nsplit, cntk, dv, ck);
+    k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj, nov);
+    k_split_reduce_f32<<<rbk, 256, 0, s>>>((const float*)pk, w.nsplit, cntk, dv, ck, 0);
+    k_tda_assemble<<<rbj, 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out, MT);
+    return;
   } else {
     {
       TraceScope ts(tr, TR_TDA_GEMM);
@@ -235,7 +266,7 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
     k_split_reduce<<<rbj, 256, 0, s>>>(pj, w.nsplit, cntj, dv, cj);
     k_split_reduce<<<rbk, 256, 0, s>>>(pk, w.nsplit, cntk, dv, ck);
   }
-  k_tda_assemble<<<(unsigned)std::min<size_t>(4096, (cntj + 255) / 256), 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out);
+  k_tda_assemble<<<rbj, 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out, 0);
 }
 
 }  // namespace
