@@ -21,117 +21,122 @@ __device__ __forceinline__ size_t pair_index(int a, int b) {  // a <= b
 }
 
 // W_i(r) = -sum_j phi_j(r) v_ji(r); v holds pair (a<=b) volumes G (*) conj(phi_a) phi_b.
-template <typename E>
+// One thread per point holds every phi_j(r) and W_i(r) in registers, so each pair volume is
+// read once: v_ab feeds W_b (with phi_a) and, for a != b, W_a (with phi_b and conj(v_ab)).
+template <typename E, int NMAX>
 __global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
                                                    const E* __restrict__ v, int n, size_t ng,
                                                    E* __restrict__ w) {
-  const int i = blockIdx.x % n;
-  const size_t r = (size_t)(blockIdx.x / n) * kThreads + threadIdx.x;
+  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
-  E acc = e_zero<E>();
-  for (int j = 0; j < n; ++j) {
-    E vj;
-    if (j <= i)
-      vj = v[pair_index(j, i) * ng + r];
-    else
-      vj = e_conj(v[pair_index(i, j) * ng + r]);
-    acc = e_add(acc, e_mul(phi[(size_t)j * ng + r], vj));
+  E ph[NMAX], acc[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    acc[j] = e_zero<E>();
+    if (j < n) ph[j] = phi[(size_t)j * ng + r];
   }
-  w[(size_t)i * ng + r] = e_neg(acc);
+#pragma unroll
+  for (int b = 0; b < NMAX; ++b) {
+    if (b < n) {
+#pragma unroll
+      for (int a = 0; a <= b; ++a) {
+        const E vab = v[pair_index(a, b) * ng + r];
+        acc[b] = e_add(acc[b], e_mul(ph[a], vab));
+        if (a != b) acc[a] = e_add(acc[a], e_mul(ph[b], e_conj(vab)));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    if (i < n) w[(size_t)i * ng + r] = e_neg(acc[i]);
 }
 
-// Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) on the matrix cores.  Each wavefront
-// owns one chunk of points and one 16 x 16 output tile (k-tile, l-tile) and issues
-// v_mfma_{f32,f64}_16x16x4 with the points as the contraction index: lane (i, g) = (lane % 16,
-// lane / 16) feeds A_{k0+i} and B_{l0+i} at 4 consecutive points r0 + 4g + s, s = 0..3, one
-// instruction per s.  Complex products are four real contractions:
-// conj(a) b = (ar br + ai bi) + i (ar bi - ai br).  Products accumulate in the storage
-// precision over the chunk; the chunk sums are written as FP64 partials part[o][chunk].
-// Lane layout of the 16x16x4 instructions: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
-// D[i][j] in lane j + 16 (i / 4), element i % 4.
-constexpr int kGramChunk = 128;  // points per wavefront
+// Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) on the matrix cores.  A workgroup of 4
+// wavefronts owns 4 consecutive chunks of kGramChunk points and one 16 x 16 output tile
+// (k-tile, l-tile).  Each wavefront loads its whole chunk first (lane (i, g) = (lane % 16,
+// lane / 16) reads A_{k0+i} and B_{l0+i} at points r0 + 4g + s of every 16-point group), then
+// issues v_mfma_f64_16x16x4f64 with the points as the contraction index.  Operands are
+// converted to FP64 in registers: products of FP32 inputs are exact in FP64 and the sums
+// carry FP64 rounding only, whatever the storage precision.  Complex products are four real
+// contractions: conj(a) b = (ar br + ai bi) + i (ar bi - ai br).  The four wavefront tiles
+// are summed in LDS in a fixed order; one FP64 partial per workgroup: part[o][block].
+// Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4.
+constexpr int kGramChunk = 64;                  // points per wavefront
+constexpr int kGramWaves = kThreads / 64;       // wavefronts per workgroup
+constexpr int kGramPoints = kGramChunk * kGramWaves;
 
-typedef float gf32x4 __attribute__((ext_vector_type(4)));
 typedef double gf64x4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
-struct MfmaAcc;
-template <>
-struct MfmaAcc<float> {
-  typedef gf32x4 type;
-  static __device__ __forceinline__ type mma(float a, float b, type c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct MfmaAcc<double> {
-  typedef gf64x4 type;
-  static __device__ __forceinline__ type mma(double a, double b, type c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
+__device__ __forceinline__ gf64x4 mma64(double a, double b, gf64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-__device__ __forceinline__ void split_ri(float v, float& r, float& i) { r = v; i = 0.f; }
+__device__ __forceinline__ void split_ri(float v, double& r, double& i) { r = v; i = 0.0; }
 __device__ __forceinline__ void split_ri(double v, double& r, double& i) { r = v; i = 0.0; }
 template <typename T>
-__device__ __forceinline__ void split_ri(C2<T> v, T& r, T& i) { r = v.r; i = v.i; }
+__device__ __forceinline__ void split_ri(C2<T> v, double& r, double& i) { r = v.r; i = v.i; }
 
 template <typename E>
 __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int na,
                                                    const E* __restrict__ B, int nb, size_t ng,
-                                                   int nchunks,
                                                    typename Elem<E>::wide* __restrict__ part) {
-  typedef typename Elem<E>::real T;
   typedef typename Elem<E>::wide W;
-  typedef MfmaAcc<T> MA;
-  typedef typename MA::type V;
   constexpr bool CPLX = Elem<E>::cplx;
-  const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-  if (c >= nchunks) return;
+  constexpr int NQ = kGramChunk / 16;
+  __shared__ W red[kGramWaves][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tiles_l = (nb + 15) / 16;
   const int k0 = (blockIdx.y / tiles_l) * 16, l0 = (blockIdx.y % tiles_l) * 16;
   const int li = lane & 15, g = lane >> 4;
   const int ka = k0 + li, lb = l0 + li;
   const E* ra = ka < na ? A + (size_t)ka * ng : nullptr;
   const E* rb = lb < nb ? B + (size_t)lb * ng : nullptr;
-  const size_t start = (size_t)c * kGramChunk;
-  const size_t end = start + kGramChunk < ng ? start + kGramChunk : ng;
-  V rr = {}, ii = {}, ri = {}, ir = {};
-  for (size_t r0 = start; r0 < end; r0 += 16) {
-    E av[4], bv[4];
+  const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * kGramChunk;
+  E av[NQ][4], bv[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const size_t r = r0 + 4 * g + s;
-      av[s] = (ra && r < end) ? ra[r] : e_zero<E>();
-      bv[s] = (rb && r < end) ? rb[r] : e_zero<E>();
+      const size_t r = start + 16 * q + 4 * g + s;
+      av[q][s] = (ra && r < ng) ? ra[r] : e_zero<E>();
+      bv[q][s] = (rb && r < ng) ? rb[r] : e_zero<E>();
     }
+  gf64x4 rr = {}, ii = {}, ri = {}, ir = {};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      T ar, ai, br, bi;
-      split_ri(av[s], ar, ai);
-      split_ri(bv[s], br, bi);
-      rr = MA::mma(ar, br, rr);
+      double ar, ai, br, bi;
+      split_ri(av[q][s], ar, ai);
+      split_ri(bv[q][s], br, bi);
+      rr = mma64(ar, br, rr);
       if constexpr (CPLX) {
-        ii = MA::mma(ai, bi, ii);
-        ri = MA::mma(ar, bi, ri);
-        ir = MA::mma(ai, br, ir);
+        ii = mma64(ai, bi, ii);
+        ri = mma64(ar, bi, ri);
+        ir = mma64(ai, br, ir);
       }
     }
-  }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int k = k0 + 4 * g + e, l = l0 + li;
-    if (k < na && l < nb) {
-      W v;
-      if constexpr (CPLX) {
-        v.r = (double)rr[e] + (double)ii[e];
-        v.i = (double)ri[e] - (double)ir[e];
-      } else {
-        v = (double)rr[e];
-      }
-      part[((size_t)k * nb + l) * nchunks + c] = v;
+    const int t = (g + 4 * e) * 16 + li;  // tile element (row g + 4e, column li)
+    W v;
+    if constexpr (CPLX) {
+      v.r = rr[e] + ii[e];
+      v.i = ri[e] - ir[e];
+    } else {
+      v = rr[e];
     }
+    red[wave][t] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;  // 256 threads, 256 tile elements
+  const int k = k0 + t / 16, l = l0 + t % 16;
+  if (k < na && l < nb) {
+    W v = red[0][t];
+#pragma unroll
+    for (int w = 1; w < kGramWaves; ++w) v = e_add(v, red[w][t]);
+    part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = v;
   }
 }
 
@@ -243,11 +248,16 @@ __global__ __launch_bounds__(64) void k_chol(const W* __restrict__ mred, int n,
   }
 }
 
-// xi_k(r) = sum_{i<=k} W_i(r) (L^{-H})_{ik}; in place allowed (xi may alias W).
+// xi_k(r) = sum_{i<=k} W_i(r) (L^{-H})_{ik}; in place allowed (xi may alias W).  L^{-H} is
+// staged in LDS, rounded once to the storage precision.
 template <typename E, int NMAX>
 __global__ __launch_bounds__(kThreads) void k_trsm(const E* w, int n, size_t ng,
                                                    const typename Elem<E>::wide* __restrict__ linvh,
                                                    E* xi) {
+  __shared__ E lh[NMAX * NMAX];
+  for (int t = threadIdx.x; t < n * n; t += kThreads)
+    lh[(t / n) * NMAX + t % n] = e_narrow<E>(linvh[t]);
+  __syncthreads();
   const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
   E wr[NMAX];
@@ -259,22 +269,28 @@ __global__ __launch_bounds__(kThreads) void k_trsm(const E* w, int n, size_t ng,
     if (k < n) {
       E s = e_zero<E>();
 #pragma unroll
-      for (int i = 0; i <= k; ++i) s = e_add(s, e_mul(wr[i], e_narrow<E>(linvh[i * n + k])));
+      for (int i = 0; i <= k; ++i) s = e_add(s, e_mul(wr[i], lh[i * NMAX + k]));
       xi[(size_t)k * ng + r] = s;
     }
   }
 }
 
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
-// vector groups of kVB): more threads than points so that the GPU is filled.
-constexpr int kVB = 4;
+// groups of kVB vectors); the group's slice of Z is staged in LDS in the storage precision.
+constexpr int kVB = 8;
 
 template <typename E, int NMAX>
 __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi, int n, size_t ng,
                                                         const typename Elem<E>::wide* __restrict__ z,
                                                         int nv, E* __restrict__ out) {
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  __shared__ E zs[NMAX * kVB];
   const int v0 = blockIdx.y * kVB;
+  for (int t = threadIdx.x; t < n * kVB; t += kThreads) {
+    const int k = t / kVB, vb = t % kVB;
+    zs[k * kVB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
+  }
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
   E xr[NMAX];
 #pragma unroll
@@ -287,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
       E s = e_zero<E>();
 #pragma unroll
       for (int k = 0; k < NMAX; ++k)
-        if (k < n) s = e_add(s, e_mul(xr[k], e_narrow<E>(z[k * nv + v])));
+        if (k < n) s = e_add(s, e_mul(xr[k], zs[k * kVB + vb]));
       out[(size_t)v * ng + r] = e_neg(s);
     }
   }
@@ -297,9 +313,8 @@ template <typename E>
 void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nchunks,
                double scale, void* out, hipStream_t s) {
   typedef typename Elem<E>::wide W;
-  const int per_block = kThreads / 64;
-  dim3 grid((nchunks + per_block - 1) / per_block, ((na + 15) / 16) * ((nb + 15) / 16));
-  k_gram<E><<<grid, kThreads, 0, s>>>((const E*)A, na, (const E*)B, nb, ng, nchunks, (W*)part);
+  dim3 grid(nchunks, ((na + 15) / 16) * ((nb + 15) / 16));
+  k_gram<E><<<grid, kThreads, 0, s>>>((const E*)A, na, (const E*)B, nb, ng, (W*)part);
   const int no = na * nb;
   k_gram_reduce<W><<<no, kThreads, 0, s>>>((const W*)part, nchunks, scale, (W*)out);
 }
@@ -307,22 +322,32 @@ void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* pa
 }  // namespace
 
 int gram_blocks(size_t ng, size_t* chunk) {
-  // one chunk of points per wavefront
-  size_t c = kGramChunk;
+  // one partial per workgroup of kGramPoints points
+  size_t c = kGramPoints;
   size_t nblk = (ng + c - 1) / c;
   if (nblk < 1) nblk = 1;
   *chunk = c;
   return (int)nblk;
 }
 
+template <typename E>
+static void wacc_impl(const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s) {
+  const unsigned blocks = (unsigned)((ng + kThreads - 1) / kThreads);
+  if (n <= 8)
+    k_wacc<E, 8><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
+  else if (n <= 16)
+    k_wacc<E, 16><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
+  else
+    k_wacc<E, 32><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
+}
+
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_WACC);
-  const unsigned blocks = (unsigned)(((ng + kThreads - 1) / kThreads) * n);
   switch (et) {
-    case ET_C128: k_wacc<C2<double>><<<blocks, kThreads, 0, s>>>((const C2<double>*)phi, (const C2<double>*)v, n, ng, (C2<double>*)w); break;
-    case ET_C64: k_wacc<C2<float>><<<blocks, kThreads, 0, s>>>((const C2<float>*)phi, (const C2<float>*)v, n, ng, (C2<float>*)w); break;
-    case ET_R64: k_wacc<double><<<blocks, kThreads, 0, s>>>((const double*)phi, (const double*)v, n, ng, (double*)w); break;
-    case ET_R32: k_wacc<float><<<blocks, kThreads, 0, s>>>((const float*)phi, (const float*)v, n, ng, (float*)w); break;
+    case ET_C128: wacc_impl<C2<double>>(phi, v, n, ng, w, s); break;
+    case ET_C64: wacc_impl<C2<float>>(phi, v, n, ng, w, s); break;
+    case ET_R64: wacc_impl<double>(phi, v, n, ng, w, s); break;
+    case ET_R32: wacc_impl<float>(phi, v, n, ng, w, s); break;
   }
 }
 
