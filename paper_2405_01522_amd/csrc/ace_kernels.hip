@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
     acc[j] = e_zero<E>();
-    if (j < n) ph[j] = phi[(size_t)j * ng + r];
+    ph[j] = phi[(size_t)(j < n ? j : n - 1) * ng + r];  // unconditional: loads issue together
   }
 #pragma unroll
   for (int b = 0; b < NMAX; ++b) {
@@ -90,8 +90,10 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
   const int k0 = (blockIdx.y / tiles_l) * 16, l0 = (blockIdx.y % tiles_l) * 16;
   const int li = lane & 15, g = lane >> 4;
   const int ka = k0 + li, lb = l0 + li;
-  const E* ra = ka < na ? A + (size_t)ka * ng : nullptr;
-  const E* rb = lb < nb ? B + (size_t)lb * ng : nullptr;
+  // loads are unconditional (clamped row and point) so they issue back to back; values
+  // outside the matrices are zeroed afterwards
+  const E* ra = A + (size_t)(ka < na ? ka : na - 1) * ng;
+  const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
   const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * kGramChunk;
   E av[NQ][4], bv[NQ][4];
 #pragma unroll
@@ -99,8 +101,17 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const size_t r = start + 16 * q + 4 * g + s;
-      av[q][s] = (ra && r < ng) ? ra[r] : e_zero<E>();
-      bv[q][s] = (rb && r < ng) ? rb[r] : e_zero<E>();
+      const size_t rc = r < ng ? r : ng - 1;
+      av[q][s] = ra[rc];
+      bv[q][s] = rb[rc];
+    }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const size_t r = start + 16 * q + 4 * g + s;
+      if (!(ka < na && r < ng)) av[q][s] = e_zero<E>();
+      if (!(lb < nb && r < ng)) bv[q][s] = e_zero<E>();
     }
   gf64x4 rr = {}, ii = {}, ri = {}, ir = {};
 #pragma unroll
@@ -262,8 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_trsm(const E* w, int n, size_t ng,
   if (r >= ng) return;
   E wr[NMAX];
 #pragma unroll
-  for (int i = 0; i < NMAX; ++i)
-    if (i < n) wr[i] = w[(size_t)i * ng + r];
+  for (int i = 0; i < NMAX; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + r];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
     if (k < n) {
@@ -294,8 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
   if (r >= ng) return;
   E xr[NMAX];
 #pragma unroll
-  for (int k = 0; k < NMAX; ++k)
-    if (k < n) xr[k] = xi[(size_t)k * ng + r];
+  for (int k = 0; k < NMAX; ++k) xr[k] = xi[(size_t)(k < n ? k : n - 1) * ng + r];
 #pragma unroll
   for (int vb = 0; vb < kVB; ++vb) {
     const int v = v0 + vb;
