@@ -127,6 +127,46 @@ int tda_coupling(ace_ctx* ctx, const void* phi_occ, int no, const void* phi_virt
                  int delta_M, double* C_out);
 
 /*
+ * Uneven batches of independent systems (the ACE rebuild of Sec. 3.1, Eqs. (11)-(12), for many
+ * molecules at once).  A batch owns one kernel spectrum per distinct (n, h) and groups the
+ * systems into size classes that run concurrently on streams of their own between a fork and
+ * a join on the batch stream (so one call can be captured into a HIP graph once the
+ * workspaces have been sized by an earlier call).
+ */
+typedef struct ace_batch ace_batch;
+
+typedef struct {
+  int n;              /* box edge of this system */
+  double h;           /* spacing (bohr) */
+  int norb;           /* orbitals, 1..ACE_MAX_ORBITALS */
+  const void* phi;    /* [norb][n^3] orbitals (batch dtype), device */
+  void* xi;           /* [norb][n^3] ACE projectors, device, output */
+  double* M;          /* [norb*norb] M (complex interleaved for complex dtypes), device, or NULL */
+  double* ex;         /* E_x, device scalar, or NULL */
+} ace_mol;
+
+int ace_batch_create(int dtype, void* hip_stream, ace_batch** out);
+int ace_batch_destroy(ace_batch* batch);
+int ace_batch_set_stream(ace_batch* batch, void* hip_stream);
+
+/*
+ * Build the ACE operator of every system in mols (host array of nmol entries): the same
+ * results as ace_build on each system.  Returns ACE_ERR_UNSUPPORTED if an edge is not
+ * compiled for the dtype.  Device-side failures are reported per system by ace_batch_status.
+ */
+int ace_build_batched(ace_batch* batch, const ace_mol* mols, int nmol);
+
+/*
+ * Synchronise and report the first device-side failure since the last call: *status, the
+ * system index *mol (host, may be NULL, -1 if none) and *info (host, may be NULL).  Clears.
+ */
+int ace_batch_status(ace_batch* batch, int* status, int* mol, int* info);
+
+/* Event tracing of a batch's launches (same classes as ace_trace_*). */
+int ace_batch_trace_enable(ace_batch* batch, int on);
+int ace_batch_trace_read(ace_batch* batch, int id, double* total_ms, long long* count);
+
+/*
  * Synchronise the context stream and report the device status word: *status (host) receives
  * ACE_OK or the first device-side error recorded since the last call, *info (host, may be
  * NULL) the failing pivot for ACE_ERR_NOT_POSDEF.  The word is then cleared.

@@ -6,6 +6,6 @@ package only marshals torch tensors into it.  Build with
 """
 
 from .api import (  # noqa: F401
-    AceContext, ace_ctx_create, pair_poisson_batched, ace_build, ace_apply,
+    AceContext, AceBatch, ace_ctx_create, ace_build_batched, pair_poisson_batched, ace_build, ace_apply,
     exchange_apply_direct, tda_coupling, ace_ctx_status, size_supported, MAX_ORBITALS,
 )

@@ -33,12 +33,26 @@ SIGNATURES = {
     "tda_coupling": (_I, [_P, _P, _I, _P, _I, _I, _P]),
     "ace_ctx_status": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "ace_strerror": (ctypes.c_char_p, [_I]),
+    "ace_batch_create": (_I, [_I, _P, ctypes.POINTER(_P)]),
+    "ace_batch_destroy": (_I, [_P]),
+    "ace_batch_set_stream": (_I, [_P, _P]),
+    "ace_build_batched": (_I, [_P, _P, _I]),
+    "ace_batch_status": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "ace_batch_trace_enable": (_I, [_P, _I]),
+    "ace_batch_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "ace_trace_enable": (_I, [_P, _I]),
     "ace_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "ace_trace_reset": (_I, [_P]),
     "ace_trace_count": (_I, []),
     "ace_trace_name": (ctypes.c_char_p, [_I]),
 }
+
+
+class AceMol(ctypes.Structure):
+    """Mirror of ace_mol in include/ace.h."""
+    _fields_ = [("n", ctypes.c_int), ("h", ctypes.c_double), ("norb", ctypes.c_int),
+                ("phi", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+                ("M", ctypes.c_void_p), ("ex", ctypes.c_void_p)]
 
 
 class AceError(RuntimeError):

@@ -12,7 +12,7 @@ import ctypes
 
 import torch
 
-from ._lib import check, lib
+from ._lib import AceMol, check, lib
 
 ACE_C128, ACE_C64, ACE_R64, ACE_R32 = 0, 1, 2, 3
 _DTYPES = {torch.complex128: ACE_C128, torch.complex64: ACE_C64,
@@ -177,6 +177,86 @@ class AceContext:
         return st.value, info.value
 
 
+class AceBatch:
+    """Uneven batch of independent systems (each its own box edge, spacing and orbital count)
+    built by one call; size classes run concurrently on streams of their own."""
+
+    def __init__(self, dtype, device=None):
+        self.dtype = dtype
+        self.code = dtype_code(dtype)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(lib().ace_batch_create(self.code, ctypes.c_void_p(self._stream),
+                                         ctypes.byref(handle)), "ace_batch_create")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ace_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        cur = torch.cuda.current_stream(self.device).cuda_stream
+        if cur != self._stream:
+            check(lib().ace_batch_set_stream(self._h, ctypes.c_void_p(cur)), "ace_batch_set_stream")
+            self._stream = cur
+
+    def build(self, systems):
+        """systems: list of dicts with keys h, phi (norb, n, n, n) and optional xi, M, ex
+        tensors (allocated when absent).  Returns the list with xi, M, ex filled in."""
+        arr = (AceMol * len(systems))()
+        for k, sysd in enumerate(systems):
+            phi = sysd["phi"]
+            if phi.dtype != self.dtype or not phi.is_cuda or not phi.is_contiguous() or phi.dim() != 4:
+                raise ValueError("system %d: phi must be a contiguous (norb, n, n, n) %s GPU tensor"
+                                 % (k, self.dtype))
+            norb, n = phi.shape[0], phi.shape[1]
+            if tuple(phi.shape[1:]) != (n, n, n):
+                raise ValueError("system %d: cubic boxes only" % k)
+            if sysd.get("xi") is None:
+                sysd["xi"] = torch.empty_like(phi)
+            if sysd.get("M") is None:
+                sysd["M"] = torch.empty((norb, norb), device=phi.device,
+                                        dtype=torch.complex128 if self.dtype.is_complex else torch.float64)
+            if sysd.get("ex") is None:
+                sysd["ex"] = torch.empty((), dtype=torch.float64, device=phi.device)
+            xi = sysd["xi"]
+            if xi.shape != phi.shape or xi.dtype != phi.dtype or not xi.is_contiguous():
+                raise ValueError("system %d: xi must match phi" % k)
+            arr[k] = AceMol(n, float(sysd["h"]), norb, phi.data_ptr(), xi.data_ptr(),
+                            sysd["M"].data_ptr(), sysd["ex"].data_ptr())
+        self._sync_stream()
+        check(lib().ace_build_batched(self._h, arr, len(systems)), "ace_build_batched")
+        return systems
+
+    def status(self):
+        st, mol, info = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().ace_batch_status(self._h, ctypes.byref(st), ctypes.byref(mol), ctypes.byref(info)),
+              "ace_batch_status")
+        return st.value, mol.value, info.value
+
+    def trace(self, on=True):
+        check(lib().ace_batch_trace_enable(self._h, 1 if on else 0), "ace_batch_trace_enable")
+
+    def trace_read(self):
+        out = {}
+        for i in range(lib().ace_trace_count()):
+            ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+            check(lib().ace_batch_trace_read(self._h, i, ctypes.byref(ms), ctypes.byref(cnt)),
+                  "ace_batch_trace_read")
+            if cnt.value:
+                out[lib().ace_trace_name(i).decode()] = (ms.value, cnt.value)
+        return out
+
+
 # Module-level functions with the C entry-point names.
 def ace_ctx_create(n, h, dtype, device=None):
     return AceContext(n, h, dtype, device)
@@ -204,3 +284,7 @@ def tda_coupling(ctx, phi_occ, phi_virt, delta_m, out=None):
 
 def ace_ctx_status(ctx):
     return ctx.status()
+
+
+def ace_build_batched(batch, systems):
+    return batch.build(systems)

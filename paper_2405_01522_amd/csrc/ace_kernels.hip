@@ -7,6 +7,8 @@
 //   K psi = -xi (xi^H psi dV)                      (Eq. (13), Gram kernel + per-point update)
 // Conjugation follows the complex reading of the real-orbital equations: pair densities are
 // conj(phi_j) phi_i, so v_ij = conj(v_ji) and only pairs j <= i are solved.
+#include <type_traits>
+
 #include "ace_kernels.hpp"
 #include "elem.hpp"
 
@@ -20,13 +22,61 @@ __device__ __forceinline__ size_t pair_index(int a, int b) {  // a <= b
   return (size_t)b * (b + 1) / 2 + a;
 }
 
+// Argument sources: one system passed by value, or many systems read from device memory
+// (index = the grid coordinate that enumerates systems).
+struct OneMol {
+  MolArgs m;
+  __device__ __forceinline__ MolArgs get(int) const { return m; }
+};
+struct ManyMol {
+  const MolArgs* ms;
+  __device__ __forceinline__ MolArgs get(int i) const { return ms[i]; }
+};
+struct GramArgs {
+  const void* A;
+  int na;
+  const void* B;
+  int nb;
+  void* part;
+};
+struct OneGram {
+  GramArgs g;
+  __device__ __forceinline__ GramArgs get(int) const { return g; }
+};
+struct ManyGram {
+  const MolArgs* ms;
+  __device__ __forceinline__ GramArgs get(int i) const {
+    const MolArgs m = ms[i];
+    return {m.phi, m.n, m.w, m.n, m.part};
+  }
+};
+struct RedArgs {
+  const void* part;
+  int no;
+  void* out;
+};
+struct OneRed {
+  RedArgs r;
+  __device__ __forceinline__ RedArgs get(int) const { return r; }
+};
+struct ManyRed {
+  const MolArgs* ms;
+  __device__ __forceinline__ RedArgs get(int i) const {
+    const MolArgs m = ms[i];
+    return {m.part, m.n * m.n, m.mred};
+  }
+};
+
 // W_i(r) = -sum_j phi_j(r) v_ji(r); v holds pair (a<=b) volumes G (*) conj(phi_a) phi_b.
 // One thread per point holds every phi_j(r) and W_i(r) in registers, so each pair volume is
 // read once: v_ab feeds W_b (with phi_a) and, for a != b, W_a (with phi_b and conj(v_ab)).
-template <typename E, int NMAX>
-__global__ __launch_bounds__(kThreads) void k_wacc(const E* __restrict__ phi,
-                                                   const E* __restrict__ v, int n, size_t ng,
-                                                   E* __restrict__ w) {
+template <typename E, int NMAX, typename S>
+__global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng) {
+  const MolArgs m = src.get(blockIdx.y);
+  const E* __restrict__ phi = (const E*)m.phi;
+  const E* __restrict__ v = (const E*)m.v;
+  E* __restrict__ w = (E*)m.w;
+  const int n = m.n;
   const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
   E ph[NMAX], acc[NMAX];
@@ -77,11 +127,15 @@ __device__ __forceinline__ void split_ri(double v, double& r, double& i) { r = v
 template <typename T>
 __device__ __forceinline__ void split_ri(C2<T> v, double& r, double& i) { r = v.r; i = v.i; }
 
-template <typename E>
-__global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int na,
-                                                   const E* __restrict__ B, int nb, size_t ng,
-                                                   typename Elem<E>::wide* __restrict__ part) {
+template <typename E, typename S>
+__global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   typedef typename Elem<E>::wide W;
+  const GramArgs ga = src.get(blockIdx.z);
+  const E* __restrict__ A = (const E*)ga.A;
+  const E* __restrict__ B = (const E*)ga.B;
+  const int na = ga.na, nb = ga.nb;
+  W* __restrict__ part = (W*)ga.part;
+  if ((int)blockIdx.y >= ((na + 15) / 16) * ((nb + 15) / 16)) return;  // tile beyond this system
   constexpr bool CPLX = Elem<E>::cplx;
   constexpr int NQ = kGramChunk / 16;
   __shared__ W red[kGramWaves][256];
@@ -152,11 +206,14 @@ __global__ __launch_bounds__(kThreads) void k_gram(const E* __restrict__ A, int 
 }
 
 // out[o] = scale * sum_b part[o][b]: one block per output, fixed-order tree.
-template <typename W>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(const W* __restrict__ part, int nblk,
-                                                          double scale, W* __restrict__ out) {
+template <typename W, typename S>
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale) {
   __shared__ W red[kThreads];
+  const RedArgs ra = src.get(blockIdx.y);
   const int o = blockIdx.x;
+  if (o >= ra.no) return;
+  const W* __restrict__ part = (const W*)ra.part;
+  W* __restrict__ out = (W*)ra.out;
   W s = W{};
   for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)o * nblk + b]);
   red[threadIdx.x] = s;
@@ -182,10 +239,15 @@ __device__ __forceinline__ C2<double> shfl_w<C2<double>>(C2<double> v, int src) 
 __device__ __forceinline__ double w_from_real(double r, double) { return r; }
 __device__ __forceinline__ C2<double> w_from_real(double r, C2<double>) { return {r, 0.0}; }
 
-template <typename W, int NMAX>
-__global__ __launch_bounds__(64) void k_chol(const W* __restrict__ mred, int n,
-                                             W* __restrict__ m_out, double* __restrict__ ex_out,
-                                             W* __restrict__ linvh, int* __restrict__ status) {
+template <typename W, int NMAX, typename S>
+__global__ __launch_bounds__(64) void k_chol(S src) {
+  const MolArgs ma = src.get(blockIdx.x);
+  const W* __restrict__ mred = (const W*)ma.mred;
+  const int n = ma.n;
+  W* __restrict__ m_out = (W*)ma.m_out;
+  double* __restrict__ ex_out = ma.ex_out;
+  W* __restrict__ linvh = (W*)ma.linvh;
+  int* __restrict__ status = ma.status;
   __shared__ W L[NMAX * NMAX];
   const int i = threadIdx.x;
   const bool row = i < n;
@@ -261,10 +323,13 @@ __global__ __launch_bounds__(64) void k_chol(const W* __restrict__ mred, int n,
 
 // xi_k(r) = sum_{i<=k} W_i(r) (L^{-H})_{ik}; in place allowed (xi may alias W).  L^{-H} is
 // staged in LDS, rounded once to the storage precision.
-template <typename E, int NMAX>
-__global__ __launch_bounds__(kThreads) void k_trsm(const E* w, int n, size_t ng,
-                                                   const typename Elem<E>::wide* __restrict__ linvh,
-                                                   E* xi) {
+template <typename E, int NMAX, typename S>
+__global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
+  const MolArgs ma = src.get(blockIdx.y);
+  const E* w = (const E*)ma.w;  // xi may alias w
+  E* xi = (E*)ma.xi;
+  const int n = ma.n;
+  const typename Elem<E>::wide* __restrict__ linvh = (const typename Elem<E>::wide*)ma.linvh;
   __shared__ E lh[NMAX * NMAX];
   for (int t = threadIdx.x; t < n * n; t += kThreads)
     lh[(t / n) * NMAX + t % n] = e_narrow<E>(linvh[t]);
@@ -318,14 +383,85 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
   }
 }
 
+template <typename E, typename S>
+void gram_impl(S src, int ntiles, int nsys, size_t ng, int nchunks, hipStream_t s) {
+  dim3 grid(nchunks, ntiles, nsys);
+  k_gram<E, S><<<grid, kThreads, 0, s>>>(src, ng);
+}
+
+// dispatch on the storage element type
+template <template <typename> class F, typename... Args>
+void by_elem(int et, Args... args) {
+  switch (et) {
+    case ET_C128: F<C2<double>>::run(args...); break;
+    case ET_C64: F<C2<float>>::run(args...); break;
+    case ET_R64: F<double>::run(args...); break;
+    case ET_R32: F<float>::run(args...); break;
+  }
+}
+
 template <typename E>
-void gram_impl(const void* A, int na, const void* B, int nb, size_t ng, void* part, int nchunks,
-               double scale, void* out, hipStream_t s) {
-  typedef typename Elem<E>::wide W;
-  dim3 grid(nchunks, ((na + 15) / 16) * ((nb + 15) / 16));
-  k_gram<E><<<grid, kThreads, 0, s>>>((const E*)A, na, (const E*)B, nb, ng, (W*)part);
-  const int no = na * nb;
-  k_gram_reduce<W><<<no, kThreads, 0, s>>>((const W*)part, nchunks, scale, (W*)out);
+struct WaccRun {
+  template <typename S>
+  static void run(S src, int nmax, int nsys, size_t ng, hipStream_t s) {
+    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+    if (nmax <= 8)
+      k_wacc<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else if (nmax <= 16)
+      k_wacc<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else
+      k_wacc<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+  }
+};
+
+template <typename E>
+struct TrsmRun {
+  template <typename S>
+  static void run(S src, int nmax, int nsys, size_t ng, hipStream_t s) {
+    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+    if (nmax <= 8)
+      k_trsm<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else if (nmax <= 16)
+      k_trsm<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else
+      k_trsm<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+  }
+};
+
+template <typename E>
+struct GramRun {
+  template <typename SG, typename SR>
+  static void run(SG sg, SR sr, int ntiles, int nout, int nsys, size_t ng, double scale,
+                  hipStream_t s) {
+    typedef typename Elem<E>::wide W;
+    size_t chunk;
+    const int nch = gram_blocks(ng, &chunk);
+    gram_impl<E, SG>(sg, ntiles, nsys, ng, nch, s);
+    dim3 rg(nout, nsys);
+    k_gram_reduce<W, SR><<<rg, kThreads, 0, s>>>(sr, nch, scale);
+  }
+};
+
+template <bool CPLX>
+struct CholRun {
+  template <typename S>
+  static void run(S src, int nmax, int nsys, hipStream_t s) {
+    typedef typename std::conditional<CPLX, C2<double>, double>::type W;
+    if (nmax <= 8)
+      k_chol<W, 8, S><<<nsys, 64, 0, s>>>(src);
+    else if (nmax <= 16)
+      k_chol<W, 16, S><<<nsys, 64, 0, s>>>(src);
+    else
+      k_chol<W, 32, S><<<nsys, 64, 0, s>>>(src);
+  }
+};
+
+template <typename S>
+void chol_any(int et, S src, int nmax, int nsys, hipStream_t s) {
+  if (et == ET_C128 || et == ET_C64)
+    CholRun<true>::run(src, nmax, nsys, s);
+  else
+    CholRun<false>::run(src, nmax, nsys, s);
 }
 
 }  // namespace
@@ -339,82 +475,69 @@ int gram_blocks(size_t ng, size_t* chunk) {
   return (int)nblk;
 }
 
-template <typename E>
-static void wacc_impl(const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s) {
-  const unsigned blocks = (unsigned)((ng + kThreads - 1) / kThreads);
-  if (n <= 8)
-    k_wacc<E, 8><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
-  else if (n <= 16)
-    k_wacc<E, 16><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
-  else
-    k_wacc<E, 32><<<blocks, kThreads, 0, s>>>((const E*)phi, (const E*)v, n, ng, (E*)w);
+static MolArgs single(const void* phi, const void* v, void* w, void* xi, void* mred, void* linvh,
+                      void* m_out, double* ex_out, int* status, int n) {
+  MolArgs m{};
+  m.phi = phi;
+  m.v = v;
+  m.w = w;
+  m.xi = xi;
+  m.mred = mred;
+  m.linvh = linvh;
+  m.m_out = m_out;
+  m.ex_out = ex_out;
+  m.status = status;
+  m.n = n;
+  return m;
 }
 
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_WACC);
-  switch (et) {
-    case ET_C128: wacc_impl<C2<double>>(phi, v, n, ng, w, s); break;
-    case ET_C64: wacc_impl<C2<float>>(phi, v, n, ng, w, s); break;
-    case ET_R64: wacc_impl<double>(phi, v, n, ng, w, s); break;
-    case ET_R32: wacc_impl<float>(phi, v, n, ng, w, s); break;
-  }
+  OneMol src{single(phi, v, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, n)};
+  by_elem<WaccRun>(et, src, n, 1, ng, s);
 }
 
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
                  double scale, void* out, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_GRAM);
-  size_t chunk;
-  const int nch = gram_blocks(ng, &chunk);
-  switch (et) {
-    case ET_C128: gram_impl<C2<double>>(A, na, B, nb, ng, part, nch, scale, out, s); break;
-    case ET_C64: gram_impl<C2<float>>(A, na, B, nb, ng, part, nch, scale, out, s); break;
-    case ET_R64: gram_impl<double>(A, na, B, nb, ng, part, nch, scale, out, s); break;
-    case ET_R32: gram_impl<float>(A, na, B, nb, ng, part, nch, scale, out, s); break;
-  }
+  OneGram sg{GramArgs{A, na, B, nb, part}};
+  OneRed sr{RedArgs{part, na * nb, out}};
+  by_elem<GramRun>(et, sg, sr, ((na + 15) / 16) * ((nb + 15) / 16), na * nb, 1, ng, scale, s);
 }
 
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
                  int* status, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_CHOL);
-  if (et == ET_C128 || et == ET_C64) {
-    typedef C2<double> W;
-    if (n <= 8)
-      k_chol<W, 8><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-    else if (n <= 16)
-      k_chol<W, 16><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-    else
-      k_chol<W, 32><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-  } else {
-    typedef double W;
-    if (n <= 8)
-      k_chol<W, 8><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-    else if (n <= 16)
-      k_chol<W, 16><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-    else
-      k_chol<W, 32><<<1, 64, 0, s>>>((const W*)mred, n, (W*)m_out, ex_out, (W*)linvh, status);
-  }
-}
-
-template <typename E>
-static void trsm_impl(const void* w, int n, size_t ng, const void* linvh, void* xi, hipStream_t s) {
-  typedef typename Elem<E>::wide W;
-  const unsigned blocks = (unsigned)((ng + kThreads - 1) / kThreads);
-  if (n <= 8)
-    k_trsm<E, 8><<<blocks, kThreads, 0, s>>>((const E*)w, n, ng, (const W*)linvh, (E*)xi);
-  else if (n <= 16)
-    k_trsm<E, 16><<<blocks, kThreads, 0, s>>>((const E*)w, n, ng, (const W*)linvh, (E*)xi);
-  else
-    k_trsm<E, 32><<<blocks, kThreads, 0, s>>>((const E*)w, n, ng, (const W*)linvh, (E*)xi);
+  OneMol src{single(nullptr, nullptr, nullptr, nullptr, const_cast<void*>(mred), linvh, m_out,
+                    ex_out, status, n)};
+  chol_any(et, src, n, 1, s);
 }
 
 void launch_trsm(int et, const void* w, int n, size_t ng, const void* linvh, void* xi, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_TRSM);
-  switch (et) {
-    case ET_C128: trsm_impl<C2<double>>(w, n, ng, linvh, xi, s); break;
-    case ET_C64: trsm_impl<C2<float>>(w, n, ng, linvh, xi, s); break;
-    case ET_R64: trsm_impl<double>(w, n, ng, linvh, xi, s); break;
-    case ET_R32: trsm_impl<float>(w, n, ng, linvh, xi, s); break;
+  OneMol src{single(nullptr, nullptr, const_cast<void*>(w), xi, nullptr, const_cast<void*>(linvh),
+                    nullptr, nullptr, nullptr, n)};
+  by_elem<TrsmRun>(et, src, n, 1, ng, s);
+}
+
+void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nmax, size_t ng,
+                              double dv, hipStream_t s, Trace* tr) {
+  ManyMol mm{mols_dev};
+  {
+    TraceScope ts(tr, TR_WACC);
+    by_elem<WaccRun>(et, mm, nmax, nmol, ng, s);
   }
+  {
+    TraceScope ts(tr, TR_GRAM);
+    const int t = (nmax + 15) / 16;
+    by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t * t, nmax * nmax, nmol, ng, dv, s);
+  }
+  {
+    TraceScope ts(tr, TR_CHOL);
+    chol_any(et, mm, nmax, nmol, s);
+  }
+  TraceScope ts(tr, TR_TRSM);
+  by_elem<TrsmRun>(et, mm, nmax, nmol, ng, s);
 }
 
 template <typename E>

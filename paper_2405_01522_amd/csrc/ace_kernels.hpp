@@ -8,6 +8,23 @@
 
 namespace ace {
 
+// One system of an ACE build: orbitals, pair volumes and the workspaces / outputs of the
+// steps after the pair solves.  Several of them (same box edge) can be processed by one
+// launch per step (launch_ace_steps_batched).
+struct MolArgs {
+  const void* phi;   // [n][ng] orbitals
+  const void* v;     // [n(n+1)/2][ng] pair potentials, pair (a<=b) at b(b+1)/2 + a
+  void* w;           // [n][ng] W
+  void* xi;          // [n][ng] output (may alias w)
+  void* part;        // Gram partials [n*n][gram_blocks(ng)] (FP64, complex or real)
+  void* mred;        // [n*n] reduced M (FP64)
+  void* linvh;       // [n*n] L^{-H} (FP64)
+  void* m_out;       // [n*n] M for the caller, or null
+  double* ex_out;    // E_x for the caller, or null
+  int* status;       // [2] device status word of this system
+  int n;             // orbitals
+};
+
 // storage element types (same numbering as the public ace_dtype)
 enum { ET_C128 = 0, ET_C64 = 1, ET_R64 = 2, ET_R32 = 3 };
 
@@ -28,5 +45,10 @@ void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, i
 // Direct exchange accumulation: out_v = -sum_j phi_j v[v*n + j]  (v: [nv][n][ng] pair volumes).
 void launch_direct_acc(int et, const void* phi, int n, const void* v, int nv, size_t ng, void* out,
                        hipStream_t s, Trace* tr);
+
+// W accumulation, M Gram + reduction, Cholesky / E_x and xi for nmol systems of one box edge
+// (ng points) whose MolArgs are in device memory; nmax = largest orbital count among them.
+void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nmax, size_t ng,
+                              double dv, hipStream_t s, Trace* tr);
 
 }  // namespace ace

@@ -52,4 +52,17 @@ void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
                          void* v_out, const void* ghat, const void* tw, hipStream_t s,
                          Trace* tr);
 
+// Pointers of one pair solve: v = G (*) (conj(a) b) (complex), or v = G (*) (a b) (real).
+struct PairPtrs {
+  const void* a;
+  const void* b;
+  void* v;
+};
+
+// Same passes with explicit pointers per pair (pairs of many systems of one box edge in one
+// launch).  items: device array of np entries; real-packed mode pairs items 2p and 2p+1.
+void launch_pair_poisson_ptrs(int n, bool fp64, bool real_packed, const PairPtrs* items, int np,
+                              void* work, const void* ghat, const void* tw, hipStream_t s,
+                              Trace* tr);
+
 }  // namespace ace

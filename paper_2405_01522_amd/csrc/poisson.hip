@@ -47,12 +47,50 @@ __device__ __forceinline__ const C2<T>* stage_twiddles(C2<T>* base, int off,
 }
 
 // ---------------------------------------------------------------------------------------
+// Where pair q's two orbitals and its output volume live.  PairsByIndex: one pair list of
+// (j, i) indices into two orbital arrays and a contiguous output array (one system);
+// PairsByPointer: explicit pointers per pair (many systems batched into one launch).
+struct PairsByIndex {
+  const void* pa;
+  const void* pb;
+  const int* pairs;
+  void* vout;
+  int np;
+  template <typename E>
+  __device__ __forceinline__ const E* a(int q, size_t ng) const {
+    return reinterpret_cast<const E*>(pa) + (size_t)pairs[2 * q] * ng;
+  }
+  template <typename E>
+  __device__ __forceinline__ const E* b(int q, size_t ng) const {
+    return reinterpret_cast<const E*>(pb) + (size_t)pairs[2 * q + 1] * ng;
+  }
+  template <typename E>
+  __device__ __forceinline__ E* v(int q, size_t ng) const {
+    return reinterpret_cast<E*>(vout) + (size_t)q * ng;
+  }
+};
+
+struct PairsByPointer {
+  const PairPtrs* items;
+  int np;
+  template <typename E>
+  __device__ __forceinline__ const E* a(int q, size_t) const {
+    return reinterpret_cast<const E*>(items[q].a);
+  }
+  template <typename E>
+  __device__ __forceinline__ const E* b(int q, size_t) const {
+    return reinterpret_cast<const E*>(items[q].b);
+  }
+  template <typename E>
+  __device__ __forceinline__ E* v(int q, size_t) const {
+    return reinterpret_cast<E*>(items[q].v);
+  }
+};
+
+// ---------------------------------------------------------------------------------------
 // Z-forward pass
-template <typename T, int N, bool RP>
-__global__ __launch_bounds__(kThreads) void k_zfwd(const void* __restrict__ pa_,
-                                                   const void* __restrict__ pb_,
-                                                   const int* __restrict__ pairs, int np,
-                                                   C2<T>* __restrict__ work,
+template <typename T, int N, bool RP, typename R>
+__global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ work,
                                                    const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
@@ -69,15 +107,15 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(const void* __restrict__ pa_,
   const T *ra0 = nullptr, *rb0 = nullptr, *ra1 = nullptr, *rb1 = nullptr;
   if constexpr (RP) {
     const int q0 = 2 * p, q1 = 2 * p + 1;
-    ra0 = reinterpret_cast<const T*>(pa_) + (size_t)pairs[2 * q0] * NG + plane;
-    rb0 = reinterpret_cast<const T*>(pb_) + (size_t)pairs[2 * q0 + 1] * NG + plane;
-    if (q1 < np) {
-      ra1 = reinterpret_cast<const T*>(pa_) + (size_t)pairs[2 * q1] * NG + plane;
-      rb1 = reinterpret_cast<const T*>(pb_) + (size_t)pairs[2 * q1 + 1] * NG + plane;
+    ra0 = res.template a<T>(q0, NG) + plane;
+    rb0 = res.template b<T>(q0, NG) + plane;
+    if (q1 < res.np) {
+      ra1 = res.template a<T>(q1, NG) + plane;
+      rb1 = res.template b<T>(q1, NG) + plane;
     }
   } else {
-    ca = reinterpret_cast<const C2<T>*>(pa_) + (size_t)pairs[2 * p] * NG + plane;
-    cb = reinterpret_cast<const C2<T>*>(pb_) + (size_t)pairs[2 * p + 1] * NG + plane;
+    ca = res.template a<C2<T>>(p, NG) + plane;
+    cb = res.template b<C2<T>>(p, NG) + plane;
   }
 
   for (int it = threadIdx.x; it < N * P2; it += kThreads) {
@@ -215,9 +253,8 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
 
 // ---------------------------------------------------------------------------------------
 // Z-inverse pass
-template <typename T, int N, bool RP>
-__global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ work,
-                                                   void* __restrict__ vout_, int np,
+template <typename T, int N, bool RP, typename R>
+__global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ work, R res,
                                                    const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
@@ -245,16 +282,17 @@ __global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ wor
     dft_out_half<T, P1, 1>(v);
     const size_t base = ((size_t)x * N + y) * N + n2;
     if constexpr (RP) {
-      T* o0 = reinterpret_cast<T*>(vout_) + (size_t)(2 * p) * NG + base;
-      const bool has1 = (2 * p + 1) < np;
-      T* o1 = reinterpret_cast<T*>(vout_) + (size_t)(2 * p + 1) * NG + base;
+      T* o0 = res.template v<T>(2 * p, NG) + base;
+      const bool has1 = (2 * p + 1) < res.np;
 #pragma unroll
-      for (int n1 = 0; n1 < H1; ++n1) {
-        o0[n1 * P2] = v[n1].r;
-        if (has1) o1[n1 * P2] = v[n1].i;
+      for (int n1 = 0; n1 < H1; ++n1) o0[n1 * P2] = v[n1].r;
+      if (has1) {
+        T* o1 = res.template v<T>(2 * p + 1, NG) + base;
+#pragma unroll
+        for (int n1 = 0; n1 < H1; ++n1) o1[n1 * P2] = v[n1].i;
       }
     } else {
-      C2<T>* o = reinterpret_cast<C2<T>*>(vout_) + (size_t)p * NG + base;
+      C2<T>* o = res.template v<C2<T>>(p, NG) + base;
 #pragma unroll
       for (int n1 = 0; n1 < H1; ++n1) o[n1 * P2] = v[n1];
     }
@@ -320,11 +358,12 @@ void allow_lds(K kernel, size_t bytes) {
                                          (int)bytes);
 }
 
-template <typename T, int N>
-void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int np, void* work,
-                 void* vout, const void* ghat, const void* tw, hipStream_t s, Trace* tr) {
+template <typename T, int N, typename R>
+void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, hipStream_t s,
+                 Trace* tr) {
   typedef Plan<N> PL;
   constexpr int P = PL::P;
+  const int np = res.np;
   const int items = rp ? (np + 1) / 2 : np;
   if (items <= 0) return;
   const size_t lds_z = ((size_t)N * (P + 1) + P) * sizeof(C2<T>);
@@ -333,20 +372,20 @@ void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int 
   const C2<T>* t = reinterpret_cast<const C2<T>*>(tw);
   const T* gh = reinterpret_cast<const T*>(ghat);
   if (rp) {
-    allow_lds(k_zfwd<T, N, true>, lds_z);
-    allow_lds(k_zinv<T, N, true>, lds_z);
+    allow_lds(k_zfwd<T, N, true, R>, lds_z);
+    allow_lds(k_zinv<T, N, true, R>, lds_z);
   } else {
-    allow_lds(k_zfwd<T, N, false>, lds_z);
-    allow_lds(k_zinv<T, N, false>, lds_z);
+    allow_lds(k_zfwd<T, N, false, R>, lds_z);
+    allow_lds(k_zinv<T, N, false, R>, lds_z);
   }
   allow_lds(k_xy<T, N>, lds_xy);
   dim3 gz(N, items), gxy(P, items);
   {
     TraceScope ts(tr, TR_ZFWD);
     if (rp)
-      k_zfwd<T, N, true><<<gz, kThreads, lds_z, s>>>(pa, pb, pairs, np, w, t);
+      k_zfwd<T, N, true, R><<<gz, kThreads, lds_z, s>>>(res, w, t);
     else
-      k_zfwd<T, N, false><<<gz, kThreads, lds_z, s>>>(pa, pb, pairs, np, w, t);
+      k_zfwd<T, N, false, R><<<gz, kThreads, lds_z, s>>>(res, w, t);
   }
   {
     TraceScope ts(tr, TR_XY);
@@ -355,9 +394,9 @@ void run_poisson(bool rp, const void* pa, const void* pb, const int* pairs, int 
   {
     TraceScope ts(tr, TR_ZINV);
     if (rp)
-      k_zinv<T, N, true><<<gz, kThreads, lds_z, s>>>(w, vout, np, t);
+      k_zinv<T, N, true, R><<<gz, kThreads, lds_z, s>>>(w, res, t);
     else
-      k_zinv<T, N, false><<<gz, kThreads, lds_z, s>>>(w, vout, np, t);
+      k_zinv<T, N, false, R><<<gz, kThreads, lds_z, s>>>(w, res, t);
   }
 }
 
@@ -410,22 +449,18 @@ void launch_kernel_setup(int n, double h, double c0, const double* cosw, double*
   k_ghat_final<<<blocks, 256, 0, s>>>(tmp1, ghat64, ghat32, scale, total);
 }
 
-void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
-                         const void* phi_b, const int* pairs_dev, int np, void* work,
-                         void* v_out, const void* ghat, const void* tw, hipStream_t s,
-                         Trace* tr) {
-#define ACE_CASE(NN)                                                                          \
-  case NN:                                                                                    \
-    if constexpr (fits<double, NN>()) {                                                       \
-      if (fp64) {                                                                             \
-        run_poisson<double, NN>(real_packed, phi_a, phi_b, pairs_dev, np, work, v_out, ghat, \
-                                tw, s, tr);                                                   \
-        return;                                                                               \
-      }                                                                                       \
-    }                                                                                         \
-    if (!fp64)                                                                                \
-      run_poisson<float, NN>(real_packed, phi_a, phi_b, pairs_dev, np, work, v_out, ghat, tw, \
-                             s, tr);                                                              \
+template <typename R>
+static void dispatch_poisson(int n, bool fp64, bool real_packed, R res, void* work,
+                             const void* ghat, const void* tw, hipStream_t s, Trace* tr) {
+#define ACE_CASE(NN)                                                                 \
+  case NN:                                                                           \
+    if constexpr (fits<double, NN>()) {                                              \
+      if (fp64) {                                                                    \
+        run_poisson<double, NN, R>(real_packed, res, work, ghat, tw, s, tr);         \
+        return;                                                                      \
+      }                                                                              \
+    }                                                                                \
+    if (!fp64) run_poisson<float, NN, R>(real_packed, res, work, ghat, tw, s, tr);   \
     return;
   switch (n) {
     ACE_SIZES(ACE_CASE)
@@ -433,6 +468,21 @@ void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
       return;
   }
 #undef ACE_CASE
+}
+
+void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
+                         const void* phi_b, const int* pairs_dev, int np, void* work,
+                         void* v_out, const void* ghat, const void* tw, hipStream_t s,
+                         Trace* tr) {
+  PairsByIndex res{phi_a, phi_b, pairs_dev, v_out, np};
+  dispatch_poisson(n, fp64, real_packed, res, work, ghat, tw, s, tr);
+}
+
+void launch_pair_poisson_ptrs(int n, bool fp64, bool real_packed, const PairPtrs* items, int np,
+                              void* work, const void* ghat, const void* tw, hipStream_t s,
+                              Trace* tr) {
+  PairsByPointer res{items, np};
+  dispatch_poisson(n, fp64, real_packed, res, work, ghat, tw, s, tr);
 }
 
 }  // namespace ace
