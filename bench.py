@@ -125,6 +125,49 @@ def run_gpu(mol, dtype, steps, warmup, trace, graph=True):
     return res
 
 
+def run_batched(mols, dtype, steps, warmup):
+    """Uneven batch (one call builds ACE for every system), graph-captured and replayed."""
+    import torch
+    import paper_2405_01522_amd as ace
+    import synth
+
+    single = dtype == torch.complex64
+    dev = torch.device("cuda", 0)
+    systems = [{"h": m.h, "phi": torch.from_numpy(synth.to_precision(m.phi, single)).to(dev)}
+               for m in mols]
+    b = ace.AceBatch(dtype, dev)
+    for _ in range(max(1, warmup)):
+        b.build(systems)
+    torch.cuda.synchronize()
+    st, mol, info = b.status()
+    if st != 0:
+        raise RuntimeError("batched build: device status %d (system %d, info %d)" % (st, mol, info))
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        b.build(systems)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.build(systems)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
+    del g
+    b.close()
+    npairs = sum(m.phi.shape[0] * (m.phi.shape[0] + 1) // 2 for m in mols)
+    return dict(ms_per_build=graph_ms, eager_ms_per_build=eager_ms, pair_solves=npairs,
+                pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols))
+
+
 def cpu_baseline(mol, budget_s=20.0):
     """The FP64 oracle, timed on the host cores on a bounded sample of the same workload:
     whole ACE builds (36 pair solves each) plus applications to the 32 vectors, repeated
@@ -161,6 +204,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -221,6 +265,12 @@ def main(argv=None):
                            "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * pairs_per_launch / (avg_ms * 1e-3) / 1e9}
         out["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in kt.items()}
         out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
+
+    if not a.no_batched:
+        bt = run_batched(synth.config4(), torch.complex64, min(a.steps, 10), 2)
+        out["batched_uneven"] = {"workload": "64 systems, edges {32..64} step 8, h=0.25, 2-16 complex "
+                                             "orbitals (seed 104), one graph-captured call",
+                                 "dtype": "f32", **bt}
 
     if not a.no_cpu_baseline:
         cb = cpu_baseline(mol)
