@@ -107,8 +107,8 @@ __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng) {
 // lane / 16) reads A_{k0+i} and B_{l0+i} at points r0 + 4g + s of every 16-point group), then
 // issues v_mfma_f64_16x16x4f64 with the points as the contraction index.  Operands are
 // converted to FP64 in registers: products of FP32 inputs are exact in FP64 and the sums
-// carry FP64 rounding only, whatever the storage precision.  Complex products are four real
-// contractions: conj(a) b = (ar br + ai bi) + i (ar bi - ai br).  The four wavefront tiles
+// carry FP64 rounding only, whatever the storage precision.  Complex products take three
+// real contractions (Gauss's three-multiplication form of conj(a) b).  The four wavefront tiles
 // are summed in LDS in a fixed order; one FP64 partial per workgroup: part[o][block].
 // Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A[i][k] in lane i + 16k,
 // B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4.
@@ -167,7 +167,9 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
       if (!(ka < na && r < ng)) av[q][s] = e_zero<E>();
       if (!(lb < nb && r < ng)) bv[q][s] = e_zero<E>();
     }
-  gf64x4 rr = {}, ii = {}, ri = {}, ir = {};
+  // conj(a) b with c = ar, d = -ai, e = br, f = bi: three real contractions (Gauss)
+  //   t1 = e (c + d), t2 = c (f - e), t3 = d (e + f);  re = t1 - t3, im = t1 + t2
+  gf64x4 t1 = {}, t2 = {}, t3 = {};
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -175,11 +177,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
       double ar, ai, br, bi;
       split_ri(av[q][s], ar, ai);
       split_ri(bv[q][s], br, bi);
-      rr = mma64(ar, br, rr);
       if constexpr (CPLX) {
-        ii = mma64(ai, bi, ii);
-        ri = mma64(ar, bi, ri);
-        ir = mma64(ai, br, ir);
+        t1 = mma64(ar - ai, br, t1);
+        t2 = mma64(ar, bi - br, t2);
+        t3 = mma64(-ai, br + bi, t3);
+      } else {
+        t1 = mma64(ar, br, t1);
       }
     }
 #pragma unroll
@@ -187,10 +190,10 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
     const int t = (g + 4 * e) * 16 + li;  // tile element (row g + 4e, column li)
     W v;
     if constexpr (CPLX) {
-      v.r = rr[e] + ii[e];
-      v.i = ri[e] - ir[e];
+      v.r = t1[e] - t3[e];
+      v.i = t1[e] + t2[e];
     } else {
-      v = rr[e];
+      v = t1[e];
     }
     red[wave][t] = v;
   }
@@ -271,22 +274,28 @@ __global__ __launch_bounds__(64) void k_chol(S src) {
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if (i == 0 && ex_out) *ex_out = 0.5 * e;
   const bool any_bad = __any(bad);
+  // right-looking factorisation; the pivot and column j are broadcast through LDS (one
+  // wavefront, so the barriers are cheap), 1/L_jj is kept for the inverse below
+  __shared__ W colj[NMAX];
+  __shared__ double piv_s, dinv[NMAX];
   int fail = -1;
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
     if (j < n) {
-      const double piv = __shfl(e_re(a[j]), j, 64);
+      if (i == j) piv_s = e_re(a[j]);
+      __syncthreads();
+      const double piv = piv_s;
       if (!(piv > 0.0) && fail < 0) fail = j;
       const double d = piv > 0.0 ? sqrt(piv) : 1.0;
-      const W lij = (i > j) ? e_scale(a[j], 1.0 / d) : (i == j ? w_from_real(d, W{}) : W{});
+      const double invd = 1.0 / d;
+      const W lij = (i > j) ? e_scale(a[j], invd) : (i == j ? w_from_real(d, W{}) : W{});
       a[j] = lij;
+      if (row) colj[i] = lij;
+      if (i == j) dinv[j] = invd;
+      __syncthreads();
 #pragma unroll
-      for (int k = j + 1; k < NMAX; ++k) {
-        if (k < n) {
-          const W lkj = shfl_w(lij, k);
-          a[k] = e_sub(a[k], e_mul(lij, e_conj(lkj)));
-        }
-      }
+      for (int k = j + 1; k < NMAX; ++k)
+        if (k < n) a[k] = e_sub(a[k], e_mul(lij, e_conj(colj[k])));
     }
   }
   if (row) {
@@ -307,7 +316,7 @@ __global__ __launch_bounds__(64) void k_chol(S src) {
 #pragma unroll
         for (int k = 0; k < r; ++k)
           if (k >= i) s = e_sub(s, e_mul(L[r * NMAX + k], x[k]));
-        x[r] = e_scale(s, 1.0 / e_re(L[r * NMAX + r]));
+        x[r] = e_scale(s, dinv[r]);
       }
     }
     // L^{-H}[c][k] = conj(X[k][c])
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
 
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
 // groups of kVB vectors); the group's slice of Z is staged in LDS in the storage precision.
-constexpr int kVB = 8;
+constexpr int kVB = 16;
 
 template <typename E, int NMAX>
 __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi, int n, size_t ng,

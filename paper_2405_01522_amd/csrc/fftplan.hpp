@@ -19,7 +19,12 @@ constexpr bool small_primes_only(int n) {
   return n == 1;
 }
 
+// ACE_PLAN_P2_EIGHT selects the transposed split P = (P/8) * 8 (larger first factor).
+#ifndef ACE_PLAN_P2_EIGHT
+#define ACE_PLAN_P2_EIGHT 0
+#endif
 constexpr int plan_p1(int P) {
+  if (ACE_PLAN_P2_EIGHT && P >= 32 && P % 16 == 0 && P / 8 <= 16) return P / 8;
   if (P >= 32 && P % 8 == 0) return 8;
   for (int d = 4; d < P; d += 2)
     if (P % d == 0 && P / d >= 2) return d;
