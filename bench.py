@@ -168,6 +168,54 @@ def run_batched(mols, dtype, steps, warmup):
                 pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols))
 
 
+def run_tda(mol, steps, warmup):
+    """TDA coupling block (real FP32 orbitals): ov + oo pair solves and the MFMA contractions,
+    graph-captured and replayed; the contraction time comes from the library's event tracer."""
+    import torch
+    import paper_2405_01522_amd as ace
+    import synth
+
+    dev = torch.device("cuda", 0)
+    occ = torch.from_numpy(synth.to_precision(mol.phi, True)).to(dev)
+    virt = torch.from_numpy(synth.to_precision(mol.phi_virt, True)).to(dev)
+    no, nv = occ.shape[0], virt.shape[0]
+    ctx = ace.AceContext(mol.n, mol.h, torch.float32, dev)
+    c = torch.empty((no * nv, no * nv), dtype=torch.float64, device=dev)
+    for _ in range(max(1, warmup)):
+        ctx.tda_coupling(occ, virt, 2, c)
+    torch.cuda.synchronize()
+    ctx.trace_reset()
+    ctx.trace(True)
+    ctx.tda_coupling(occ, virt, 2, c)
+    ctx.trace(False)
+    kt = ctx.trace_read()
+    stream = torch.cuda.current_stream(dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.tda_coupling(occ, virt, 2, c)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del g
+    ctx.close()
+    nov, noo = no * nv, no * (no + 1) // 2
+    t = (nov + 127) // 128
+    # contraction FLOPs as launched: upper 128-tiles of the symmetric ov block + the oo x vv block
+    flops = 2.0 * mol.n ** 3 * (t * (t + 1) // 2 * 128 * 128 + noo * nv * nv)
+    gemm_ms = kt.get("tda_gemm", (float("nan"), 1))[0]
+    return dict(ms_per_block=ms, pair_solves=nov + noo,
+                pair_solves_per_s=(nov + noo) / (ms * 1e-3),
+                gemm_ms=gemm_ms, gemm_tflops=flops / (gemm_ms * 1e-3) / 1e12,
+                gemm_frac_fp32_mfma=flops / (gemm_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                kernel_ms={k: v[0] for k, v in kt.items()})
+
+
 def cpu_baseline(mol, budget_s=20.0):
     """The FP64 oracle, timed on the host cores on a bounded sample of the same workload:
     whole ACE builds (36 pair solves each) plus applications to the 32 vectors, repeated
@@ -205,6 +253,7 @@ def main(argv=None):
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tda", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -271,6 +320,13 @@ def main(argv=None):
         out["batched_uneven"] = {"workload": "64 systems, edges {32..64} step 8, h=0.25, 2-16 complex "
                                              "orbitals (seed 104), one graph-captured call",
                                  "dtype": "f32", **bt}
+
+    if not a.no_tda:
+        td = run_tda(synth.config3(), min(a.steps, 10), 2)
+        out["tda_block"] = {"workload": "64^3 box h=0.2 padded 128^3; 16 occupied + 32 virtual real "
+                                        "orbitals (seed 103); 512 ov + 136 oo pair solves, 512x512 "
+                                        "singlet coupling block; one graph-captured call",
+                            "dtype": "f32 (FP64 split-K sums)", **td}
 
     if not a.no_cpu_baseline:
         cb = cpu_baseline(mol)

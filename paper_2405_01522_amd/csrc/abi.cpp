@@ -38,6 +38,57 @@ size_t elem_bytes(int dt) {
 bool is_fp64(int dt) { return dt == ACE_C128 || dt == ACE_R64; }
 bool is_cplx(int dt) { return dt == ACE_C128 || dt == ACE_C64; }
 
+struct Blob {
+  Buf dev;
+  std::vector<unsigned char> cache;
+  unsigned char* pinned = nullptr;
+  size_t pinned_cap = 0;
+};
+
+int ensure_on(hipStream_t s, Buf& b, size_t bytes) {
+  if (bytes <= b.cap) return ACE_OK;
+  if (b.p) {
+    if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return ACE_ERR_OOM;
+  }
+  b.cap = want;
+  return ACE_OK;
+}
+
+// Copy host bytes to the blob's device buffer on stream s, unless identical to the last upload.
+int upload_blob(hipStream_t s, Blob& b, const void* host, size_t bytes) {
+  if (b.cache.size() == bytes && std::memcmp(b.cache.data(), host, bytes) == 0) return ACE_OK;
+  int rc = ensure_on(s, b.dev, bytes);
+  if (rc) return rc;
+  if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;  // staging may be in flight
+  if (b.pinned_cap < bytes) {
+    if (b.pinned) (void)hipHostFree(b.pinned);
+    b.pinned = nullptr;
+    b.pinned_cap = 0;
+    if (hipHostMalloc((void**)&b.pinned, bytes) != hipSuccess) return ACE_ERR_OOM;
+    b.pinned_cap = bytes;
+  }
+  std::memcpy(b.pinned, host, bytes);
+  if (hipMemcpyAsync(b.dev.p, b.pinned, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  b.cache.assign((const unsigned char*)host, (const unsigned char*)host + bytes);
+  return ACE_OK;
+}
+
+void free_blob(Blob& b) {
+  if (b.dev.p) (void)hipFree(b.dev.p);
+  if (b.pinned) (void)hipHostFree(b.pinned);
+  b = Blob();
+}
+
 }  // namespace
 
 // Event tracer: one event pair per traced launch group, pooled events, totals per kernel class.
@@ -120,6 +171,7 @@ struct ace_ctx {
   void* tw = nullptr;        // P twiddles exp(-2 pi i m / P) in the compute precision
   int* status = nullptr;     // device: [code, info]
   Buf work, vbuf, wbuf, part, small, pairs, tda;
+  Blob tda_items;                // pair pointers of the TDA solves
   std::vector<int> pairs_cached;
   int* pinned_pairs = nullptr;
   size_t pinned_cap = 0;
@@ -292,6 +344,7 @@ int ace_ctx_destroy(ace_ctx* c) {
   if (c->gpos) (void)hipFree(c->gpos);
   if (c->status) (void)hipFree(c->status);
   if (c->pinned_pairs) (void)hipHostFree(c->pinned_pairs);
+  free_blob(c->tda_items);
   delete c;
   return ACE_OK;
 }
@@ -404,30 +457,46 @@ int tda_coupling(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, 
   if (delta_M != 0 && delta_M != 2) return ACE_ERR_INVALID;
   if (is_cplx(c->dtype)) return ACE_ERR_UNSUPPORTED;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
-  const int nov = no * nv, noo = no * (no + 1) / 2;
-  // pair list: ov pairs (j, b) -> j*nv + b (phi_a = occ, phi_b = virt), then oo pairs (a<=b)
-  std::vector<int> pov(2 * (size_t)nov), poo(2 * (size_t)noo);
-  for (int j = 0; j < no; ++j)
-    for (int b = 0; b < nv; ++b) {
-      pov[2 * ((size_t)j * nv + b)] = j;
-      pov[2 * ((size_t)j * nv + b) + 1] = b;
-    }
-  for (int b = 0; b < no; ++b)
-    for (int a = 0; a <= b; ++a) {
-      const int p = b * (b + 1) / 2 + a;
-      poo[2 * p] = a;
-      poo[2 * p + 1] = b;
-    }
-  const size_t vbytes = eb * ng * (size_t)(nov + noo);
+  const int nov = no * nv, noo = no * (no + 1) / 2, np = nov + noo;
+  const size_t vbytes = eb * ng * (size_t)np;
   int rc = ensure(c, c->vbuf, vbytes);
   if (rc) return rc;
   char* v_ov = (char*)c->vbuf.p;
   char* v_oo = v_ov + eb * ng * (size_t)nov;
-  rc = upload_pairs(c, pov.data(), nov);
-  if (!rc) rc = run_pairs(c, phi_occ, phi_virt, (const int*)c->pairs.p, nov, v_ov);
-  if (!rc) rc = upload_pairs(c, poo.data(), noo);
-  if (!rc) rc = run_pairs(c, phi_occ, phi_occ, (const int*)c->pairs.p, noo, v_oo);
+  // one list of pair pointers: ov pairs (j, b) at row j*nv + b, then occupied pairs (a <= b)
+  std::vector<PairPtrs> items((size_t)np);
+  for (int j = 0; j < no; ++j)
+    for (int b = 0; b < nv; ++b) {
+      PairPtrs& t = items[(size_t)j * nv + b];
+      t.a = (const char*)phi_occ + eb * ng * j;
+      t.b = (const char*)phi_virt + eb * ng * b;
+      t.v = v_ov + eb * ng * ((size_t)j * nv + b);
+    }
+  for (int b = 0; b < no; ++b)
+    for (int a = 0; a <= b; ++a) {
+      const size_t q = (size_t)b * (b + 1) / 2 + a;
+      PairPtrs& t = items[nov + q];
+      t.a = (const char*)phi_occ + eb * ng * a;
+      t.b = (const char*)phi_occ + eb * ng * b;
+      t.v = v_oo + eb * ng * q;
+    }
+  rc = upload_blob(c->stream, c->tda_items, items.data(), sizeof(PairPtrs) * items.size());
   if (rc) return rc;
+  {
+    const bool fp64 = is_fp64(c->dtype);
+    const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
+    const size_t nit = ((size_t)np + 1) / 2;  // real: two pairs per complex FFT
+    const size_t batch = std::max<size_t>(1, std::min<size_t>(nit, (size_t(1) << 30) / per_item));
+    rc = ensure(c, c->work, per_item * batch);
+    if (rc) return rc;
+    const PairPtrs* dev = (const PairPtrs*)c->tda_items.dev.p;
+    for (size_t i0 = 0; i0 < nit; i0 += batch) {
+      const size_t ni = std::min(batch, nit - i0);
+      const size_t p0 = 2 * i0, npb = std::min(2 * ni, (size_t)np - p0);
+      launch_pair_poisson_ptrs(c->n, fp64, true, dev + p0, (int)npb, c->work.p, c->gpos, c->tw,
+                               c->stream, c->tr());
+    }
+  }
   TdaWork tw;
   rc = ensure(c, c->tda, tda_workspace_bytes(no, nv, ng, is_fp64(c->dtype), &tw));
   if (rc) return rc;
@@ -508,57 +577,6 @@ const char* ace_strerror(int code) {
 // fork and a join event on the caller's stream, so the whole call is capturable in one graph.
 
 namespace {
-
-struct Blob {
-  Buf dev;
-  std::vector<unsigned char> cache;
-  unsigned char* pinned = nullptr;
-  size_t pinned_cap = 0;
-};
-
-int ensure_on(hipStream_t s, Buf& b, size_t bytes) {
-  if (bytes <= b.cap) return ACE_OK;
-  if (b.p) {
-    if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;
-    (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
-  }
-  size_t want = bytes + bytes / 8;
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    return ACE_ERR_OOM;
-  }
-  b.cap = want;
-  return ACE_OK;
-}
-
-// Copy host bytes to the blob's device buffer on stream s, unless identical to the last upload.
-int upload_blob(hipStream_t s, Blob& b, const void* host, size_t bytes) {
-  if (b.cache.size() == bytes && std::memcmp(b.cache.data(), host, bytes) == 0) return ACE_OK;
-  int rc = ensure_on(s, b.dev, bytes);
-  if (rc) return rc;
-  if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;  // staging may be in flight
-  if (b.pinned_cap < bytes) {
-    if (b.pinned) (void)hipHostFree(b.pinned);
-    b.pinned = nullptr;
-    b.pinned_cap = 0;
-    if (hipHostMalloc((void**)&b.pinned, bytes) != hipSuccess) return ACE_ERR_OOM;
-    b.pinned_cap = bytes;
-  }
-  std::memcpy(b.pinned, host, bytes);
-  if (hipMemcpyAsync(b.dev.p, b.pinned, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-    return ACE_ERR_HIP;
-  b.cache.assign((const unsigned char*)host, (const unsigned char*)host + bytes);
-  return ACE_OK;
-}
-
-void free_blob(Blob& b) {
-  if (b.dev.p) (void)hipFree(b.dev.p);
-  if (b.pinned) (void)hipHostFree(b.pinned);
-  b = Blob();
-}
 
 struct BatchClass {
   int n = 0;

@@ -419,3 +419,26 @@ def test_config4_batched_full_size(c4):
         xi, _, ex = ctx.ace_build(systems[k]["phi"])
         torch.cuda.synchronize()
         assert torch.equal(xi, systems[k]["xi"]) and torch.equal(ex, systems[k]["ex"]), k
+
+
+def test_tda_graph_replays_match_eager():
+    ace = _ace()
+    m = synth.small_real(29, 16, 0.4, 3, 6)
+    ctx = ace.AceContext(m.n, m.h, torch.float32)
+    occ = _t(synth.to_precision(m.phi, True), torch.float32)
+    virt = _t(synth.to_precision(m.phi_virt, True), torch.float32)
+    c = torch.empty((18, 18), dtype=torch.float64, device=DEV)
+    ctx.tda_coupling(occ, virt, 2, c)
+    torch.cuda.synchronize()
+    ref = c.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.tda_coupling(occ, virt, 2, c)
+    for rep in range(3):
+        c.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(c, ref), rep
+        ctx.tda_coupling(occ, virt, 0, c)     # eager work in between (triplet block)
+        torch.cuda.synchronize()
+    del g
