@@ -96,22 +96,77 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(Op<T> A, int M, Op<T> B, i
 }
 
 // ---------------------------------------------------------------------------------------
-// FP32 contraction on the matrix cores: part[z][m][n] = sum_{k in split z} A(m,k) B(n,k).
-// Block tile 128 x 128, 4 waves of 64 x 64, v_mfma_f32_16x16x4f32 (each wave 4 x 4 MFMA
-// tiles).  Operand tiles of 128 rows x 32 points are staged through LDS (row stride 33 words,
-// conflict-free fragment reads); generated operands (products of two orbitals) are formed
-// while staging.  Lane layout of the 16x16x4 instruction: A[i][k] in lane i + 16k,
-// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), element i % 4.
-constexpr int MT = 128, KT = 32, KS = KT + 1;
+// FP32-input contraction on the matrix cores with split BF16 operands ("bf16x3"):
+// part[z][m][n] = sum_{k in split z} A(m,k) B(n,k), each FP32 operand split as x = hi + lo
+// (hi = RNE bf16(x), lo = RNE bf16(x - hi)) and A B ~ Ahi Bhi + Ahi Blo + Alo Bhi, accumulated
+// in FP32 by v_mfma_f32_16x16x32_bf16 (relative error of one product ~2^-16, the dropped
+// Alo Blo term).  Block tile 128 x 128, 4 waves of 64 x 64 (4 x 4 MFMA tiles each); operand
+// tiles of 128 rows x 64 points are staged through LDS as hi / lo BF16 rows of stride 72
+// (16-byte aligned rows; one 16-byte fragment read per lane), with coalesced row-segment
+// loads.  Generated operands (products of two orbitals) are formed in FP32 while staging.  Lane layout of the 16x16x32 instruction:
+// A[i][k] in lane i + 16 (k / 8), element k % 8 (B likewise with j); D[i][j] in lane
+// j + 16 (i / 4), element i % 4 (output layout checked on gfx950).
+constexpr int MT = 128, KB = 64, LB = KB + 8;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Stage one operand tile (128 rows x 64 points from point kt) as hi / lo BF16 rows.  Sixteen
+// consecutive lanes read one row (4 consecutive points each, one 16-byte load when VEC), so
+// every load instruction covers four 256-byte row segments.  Loads are unconditional (row and
+// point clamped); rows >= M and points >= k1 are zeroed.
+template <bool VEC>
+__device__ __forceinline__ void stage_tile(const Op<float>& o, int m0, int M, size_t kt,
+                                           size_t k1, size_t ng, __bf16* H, __bf16* L) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int c4 = (threadIdx.x & 15) * 4;
+  const size_t k = kt + c4;
+#pragma unroll
+  for (int pass = 0; pass < MT / 16; ++pass) {
+    const int r = pass * 16 + (threadIdx.x >> 4);
+    const int m = m0 + r;
+    const bool valid = m < M;
+    const int mc = valid ? m : M - 1;
+    const float* p = o.q ? o.p + (size_t)(mc / o.div) * ng : o.p + (size_t)mc * ng;
+    const float* q = o.q ? o.q + (size_t)(mc % o.div) * ng : nullptr;
+    float x[4];
+    if constexpr (VEC) {
+      const size_t kc = k + 3 < ng ? k : ng - 4;
+      const float4 a = *reinterpret_cast<const float4*>(p + kc);
+      x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+      if (q) {
+        const float4 b = *reinterpret_cast<const float4*>(q + kc);
+        x[0] *= b.x; x[1] *= b.y; x[2] *= b.z; x[3] *= b.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const size_t kc = k + e < ng ? k + e : ng - 1;
+        x[e] = q ? p[kc] * q[kc] : p[kc];
+      }
+    }
+    bf16x4 h, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float v = (valid && k + e < k1) ? x[e] : 0.f;
+      const __bf16 vh = (__bf16)v;
+      h[e] = vh;
+      l[e] = (__bf16)(v - (float)vh);
+    }
+    *reinterpret_cast<bf16x4*>(H + r * LB + c4) = h;
+    *reinterpret_cast<bf16x4*>(L + r * LB + c4) = l;
+  }
+}
 
 // tri != 0: M == N and the result is symmetric; blockIdx.x enumerates only the tiles (bx, by)
 // with bx <= by (blockIdx.y unused) and the lower tiles are never computed.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<float> B, int N,
                                                       size_t ng, size_t kchunk,
                                                       float* __restrict__ part, int tri) {
-  __shared__ float As[MT * KS];
-  __shared__ float Bs[MT * KS];
+  __shared__ __align__(16) __bf16 Ah[MT * LB];
+  __shared__ __align__(16) __bf16 Al[MT * LB];
+  __shared__ __align__(16) __bf16 Bh[MT * LB];
+  __shared__ __align__(16) __bf16 Bl[MT * LB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // wave's 64 x 64 quadrant
   int bx = blockIdx.x, by = blockIdx.y;
@@ -131,32 +186,32 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int li = lane & 15, lk = lane >> 4;
-  for (size_t kt = k0; kt < k1; kt += KT) {
-    // stage: 128 rows x 32 points per operand, 16 elements per thread
-#pragma unroll 4
-    for (int e = threadIdx.x; e < MT * KT; e += 256) {
-      const int r = e / KT, kk = e % KT;
-      const size_t k = kt + kk;
-      const bool kin = k < k1;
-      const int m = m0 + r, n = n0 + r;
-      As[r * KS + kk] = (m < M && kin) ? op_load(A, m, k, ng) : 0.f;
-      Bs[r * KS + kk] = (n < N && kin) ? op_load(B, n, k, ng) : 0.f;
-    }
+  const int li = lane & 15, lg = lane >> 4;
+  for (size_t kt = k0; kt < k1; kt += KB) {
+    stage_tile<VEC>(A, m0, M, kt, k1, ng, Ah, Al);
+    stage_tile<VEC>(B, n0, N, kt, k1, ng, Bh, Bl);
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < KT; ks += 4) {
-      float af[4], bf[4];
+    for (int ks = 0; ks < KB; ks += 32) {
+      bf16x8 bh[4], bl[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        af[t] = As[(wr * 64 + t * 16 + li) * KS + ks + lk];
-        bf[t] = Bs[(wc * 64 + t * 16 + li) * KS + ks + lk];
+        const int co = (wc * 64 + t * 16 + li) * LB + ks + 8 * lg;
+        bh[t] = *reinterpret_cast<const bf16x8*>(Bh + co);
+        bl[t] = *reinterpret_cast<const bf16x8*>(Bl + co);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        const int ro = (wr * 64 + i * 16 + li) * LB + ks + 8 * lg;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ah + ro);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(Al + ro);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
@@ -167,14 +222,12 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wr * 64 + i * 16 + 4 * lk + r;
+        const int m = m0 + wr * 64 + i * 16 + 4 * lg + r;
         const int n = n0 + wc * 64 + j * 16 + li;
         if (m < M && n < N) dst[(size_t)m * N + n] = acc[i][j][r];
       }
 }
 
-// ncols > 0: row-major ncols-wide matrix whose tiles below the diagonal were not computed
-// (skipped here too).
 __global__ void k_split_reduce_f32(const float* __restrict__ part, int nsplit, size_t count,
                                    double scale, double* __restrict__ out, int ncols) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
@@ -245,9 +298,15 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
     {
       TraceScope ts(tr, TR_TDA_GEMM);
       dim3 gj(tj * (tj + 1) / 2, 1, w.nsplit);  // upper tiles only: CJ is symmetric
-      k_gemm_nt_mfma<<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
+      if (ng % 4 == 0)
+        k_gemm_nt_mfma<true><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
+      else
+        k_gemm_nt_mfma<false><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
       dim3 gk((noo + MT - 1) / MT, (nvv + MT - 1) / MT, w.nsplit);
-      k_gemm_nt_mfma<<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
+      if (ng % 4 == 0)
+        k_gemm_nt_mfma<true><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
+      else
+        k_gemm_nt_mfma<false><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
     }
     TraceScope ts(tr, TR_TDA_REDUCE);
     k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj, nov);
