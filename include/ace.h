@@ -167,6 +167,48 @@ int ace_batch_trace_enable(ace_batch* batch, int on);
 int ace_batch_trace_read(ace_batch* batch, int id, double* total_ms, long long* count);
 
 /*
+ * Tamm-Dancoff excitations (Sec. 2: A X = omega X, A = diag(eps_a - eps_i) + C, Eq. (7)): the
+ * nstates (1..16) lowest eigenpairs by a block Davidson iteration on the device.
+ * C: (no*nv)^2 FP64 device (from tda_coupling); eps_occ[no], eps_virt[nv]: host;
+ * tol: residual norm |A x - omega x| for convergence; max_iter: iteration cap;
+ * omega_out[nstates] device; X_out [nstates][no*nv] device (unit eigenvectors) or NULL;
+ * *iterations (host, may be NULL): iterations used, negative if not converged.
+ * Synchronises the context stream.
+ */
+int tda_excitations(ace_ctx* ctx, const double* C, const double* eps_occ, int no,
+                    const double* eps_virt, int nv, int nstates, double tol, int max_iter,
+                    double* omega_out, double* X_out, int* iterations);
+
+/*
+ * Transition dipoles and oscillator strengths of TDA states (Eqs. (8)-(9), atomic units):
+ * d_k = sum_ia <i| r |a> X_k,ia on the context grid, f_k = 2/3 omega_k |d_k|^2.  Real dtypes.
+ * phi_occ [no][N^3], phi_virt [nv][N^3]; X [nstates][no*nv] and omega [nstates] FP64 device;
+ * f_out [nstates] device; d_out [nstates][3] device or NULL.  Synchronises the stream.
+ */
+int tda_oscillator_strengths(ace_ctx* ctx, const void* phi_occ, int no, const void* phi_virt,
+                             int nv, const double* X, const double* omega, int nstates,
+                             double* f_out, double* d_out);
+
+/*
+ * Strength function (Eq. (10)) with each delta broadened to a normalised Lorentzian of
+ * half-width gamma: S_out[i] = sum_k f_k gamma / (pi ((w_i - omega_k)^2 + gamma^2)),
+ * w_i = w0 + i dw, i < nw.  All arrays FP64 device; hip_stream may be NULL.
+ */
+int strength_function(const double* omega, const double* f, int nstates, double w0, double dw,
+                      int nw, double gamma, double* S_out, void* hip_stream);
+
+/*
+ * Small dense FP64 helpers used by the eigensolver drivers (device arrays, row-major):
+ *   dense_gemm: C = alpha op(A) op(B) + beta C, op(X) = X (t = 0) or X^T (t = 1), C is M x N;
+ *   sym_eig_small: eigenvalues (ascending, w[n]) and eigenvectors (columns of V) of the
+ *   symmetric part of A, n <= 64, by parallel-order Jacobi rotations in one workgroup.
+ */
+int dense_gemm(int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+               const double* B, int ldb, double beta, double* C, int ldc, void* hip_stream);
+int sym_eig_small(int n, const double* A, int lda, double* w, double* V, int ldv,
+                  void* hip_stream);
+
+/*
  * Synchronise the context stream and report the device status word: *status (host) receives
  * ACE_OK or the first device-side error recorded since the last call, *info (host, may be
  * NULL) the failing pivot for ACE_ERR_NOT_POSDEF.  The word is then cleared.

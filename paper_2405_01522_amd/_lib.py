@@ -40,6 +40,11 @@ SIGNATURES = {
     "ace_batch_status": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "ace_batch_trace_enable": (_I, [_P, _I]),
     "ace_batch_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
+    "tda_excitations": (_I, [_P, _P, _P, _I, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),
+    "tda_oscillator_strengths": (_I, [_P, _P, _I, _P, _I, _P, _P, _I, _P, _P]),
+    "strength_function": (_I, [_P, _P, _I, _D, _D, _I, _D, _P, _P]),
+    "dense_gemm": (_I, [_I, _I, _I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _P]),
+    "sym_eig_small": (_I, [_I, _P, _I, _P, _P, _I, _P]),
     "ace_trace_enable": (_I, [_P, _I]),
     "ace_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "ace_trace_reset": (_I, [_P]),

@@ -153,6 +153,43 @@ class AceContext:
                                  ctypes.c_void_p(out.data_ptr())), "tda_coupling")
         return out
 
+    def tda_excitations(self, c, eps_occ, eps_virt, nstates, tol=1e-8, max_iter=200):
+        """Lowest nstates TDA eigenpairs of diag(eps_a - eps_i) + C (C from tda_coupling).
+        Returns (omega, X, iterations) with omega (nstates,), X (nstates, no*nv) FP64 tensors."""
+        import numpy as np
+        eo = np.ascontiguousarray(eps_occ, dtype=np.float64)
+        ev = np.ascontiguousarray(eps_virt, dtype=np.float64)
+        nov = eo.size * ev.size
+        if not (c.is_cuda and c.dtype == torch.float64 and c.shape == (nov, nov) and c.is_contiguous()):
+            raise ValueError("c must be the (no*nv, no*nv) FP64 GPU coupling block")
+        omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
+        x = torch.empty((nstates, nov), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int()
+        self._sync_stream()
+        check(lib().tda_excitations(self._h, ctypes.c_void_p(c.data_ptr()),
+                                    eo.ctypes.data_as(ctypes.c_void_p), eo.size,
+                                    ev.ctypes.data_as(ctypes.c_void_p), ev.size, int(nstates),
+                                    float(tol), int(max_iter), ctypes.c_void_p(omega.data_ptr()),
+                                    ctypes.c_void_p(x.data_ptr()), ctypes.byref(it)),
+              "tda_excitations")
+        return omega, x, it.value
+
+    def tda_oscillator_strengths(self, phi_occ, phi_virt, x, omega):
+        """(f, d): oscillator strengths (k,) and transition dipoles (k, 3) of TDA states."""
+        k = omega.shape[0]
+        f = torch.empty(k, dtype=torch.float64, device=self.device)
+        d = torch.empty((k, 3), dtype=torch.float64, device=self.device)
+        po = self._vol(phi_occ, "phi_occ")
+        pv = self._vol(phi_virt, "phi_virt")
+        self._sync_stream()
+        check(lib().tda_oscillator_strengths(self._h, po, phi_occ.shape[0], pv, phi_virt.shape[0],
+                                             ctypes.c_void_p(x.data_ptr()),
+                                             ctypes.c_void_p(omega.data_ptr()), k,
+                                             ctypes.c_void_p(f.data_ptr()),
+                                             ctypes.c_void_p(d.data_ptr())),
+              "tda_oscillator_strengths")
+        return f, d
+
     def trace(self, on=True):
         """Enable / disable event timing of the library's kernel classes."""
         check(lib().ace_trace_enable(self._h, 1 if on else 0), "ace_trace_enable")
@@ -255,6 +292,40 @@ class AceBatch:
             if cnt.value:
                 out[lib().ace_trace_name(i).decode()] = (ms.value, cnt.value)
         return out
+
+
+def strength_function(omega, f, w0, dw, nw, gamma):
+    """S(w) on w = w0 + i dw (i < nw), Lorentzian half-width gamma (Eq. (10)); GPU tensors."""
+    out = torch.empty(nw, dtype=torch.float64, device=omega.device)
+    check(lib().strength_function(ctypes.c_void_p(omega.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                  omega.shape[0], float(w0), float(dw), int(nw), float(gamma),
+                                  ctypes.c_void_p(out.data_ptr()), _stream_handle()),
+          "strength_function")
+    return out
+
+
+def dense_gemm(a, b, ta=False, tb=False, alpha=1.0, beta=0.0, out=None):
+    """C = alpha op(a) op(b) + beta C on FP64 GPU matrices (row-major, contiguous)."""
+    m = a.shape[1] if ta else a.shape[0]
+    k = a.shape[0] if ta else a.shape[1]
+    n = b.shape[0] if tb else b.shape[1]
+    if out is None:
+        out = torch.zeros((m, n), dtype=torch.float64, device=a.device)
+    check(lib().dense_gemm(int(ta), int(tb), m, n, k, float(alpha), ctypes.c_void_p(a.data_ptr()),
+                           a.shape[1], ctypes.c_void_p(b.data_ptr()), b.shape[1], float(beta),
+                           ctypes.c_void_p(out.data_ptr()), n, _stream_handle()), "dense_gemm")
+    return out
+
+
+def sym_eig_small(a):
+    """(w, V) of a symmetric FP64 GPU matrix of order <= 64 (Jacobi, one workgroup)."""
+    n = a.shape[0]
+    w = torch.empty(n, dtype=torch.float64, device=a.device)
+    v = torch.empty((n, n), dtype=torch.float64, device=a.device)
+    check(lib().sym_eig_small(n, ctypes.c_void_p(a.data_ptr()), a.shape[1],
+                              ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(v.data_ptr()), n,
+                              _stream_handle()), "sym_eig_small")
+    return w, v
 
 
 # Module-level functions with the C entry-point names.

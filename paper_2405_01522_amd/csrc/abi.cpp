@@ -821,3 +821,176 @@ int ace_batch_trace_read(ace_batch* b, int id, double* total_ms, long long* coun
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Tamm-Dancoff excitations (Sec. 2: A X = omega X with A = diag(eps_a - eps_i) + C) by a
+// block Davidson iteration on the device: subspace products and Rayleigh-Ritz with the small
+// dense kernels of linalg.hip, diagonal (eps_a - eps_i - theta) correction, canonical
+// orthonormalisation of each new block.  The host only steers (residual norms, block sizes).
+
+#include "linalg.hpp"
+
+namespace {
+
+struct DevBuf {
+  double* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t n) {
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return ACE_ERR_OOM;
+    }
+    return ACE_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int sym_eig_small(int n, const double* A, int lda, double* w, double* V, int ldv, void* stream) {
+  if (n < 1 || n > kJacobiMax || !A || !w || !V || lda < n || ldv < n) return ACE_ERR_INVALID;
+  launch_jacobi(n, A, lda, w, V, ldv, 60, 1e-15, (hipStream_t)stream);
+  return hip_check(hipGetLastError());
+}
+
+int dense_gemm(int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+               const double* B, int ldb, double beta, double* C, int ldc, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return ACE_ERR_INVALID;
+  launch_dgemm(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
+  return hip_check(hipGetLastError());
+}
+
+int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
+                    const double* eps_virt, int nv, int nstates, double tol, int max_iter,
+                    double* omega_out, double* X_out, int* iterations) {
+  if (!c || !C || !eps_occ || !eps_virt || !omega_out || no < 1 || nv < 1) return ACE_ERR_INVALID;
+  const int n = no * nv, k = nstates;
+  if (k < 1 || k > 16 || k > n || !(tol > 0.0) || max_iter < 1) return ACE_ERR_INVALID;
+  hipStream_t s = c->stream;
+  const int mmax = std::min(n, std::min(kJacobiMax, std::max(4 * k, 2 * k + 8)));
+  std::vector<double> d(n);
+  for (int i = 0; i < no; ++i)
+    for (int a = 0; a < nv; ++a) d[(size_t)i * nv + a] = eps_virt[a] - eps_occ[i];
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
+  std::vector<double> v0((size_t)k * n, 0.0);
+  for (int j = 0; j < k; ++j) v0[(size_t)j * n + order[j]] = 1.0;
+  DevBuf A, dd, V, AV, H, th, S, X, AX, R, T, G, nrm, Sm, lam, U, Y, sc;
+  int rc = ACE_OK;
+  for (auto pr : {std::make_pair(&A, (size_t)n * n), std::make_pair(&dd, (size_t)n),
+                  std::make_pair(&V, (size_t)mmax * n), std::make_pair(&AV, (size_t)mmax * n),
+                  std::make_pair(&H, (size_t)mmax * mmax), std::make_pair(&th, (size_t)mmax),
+                  std::make_pair(&S, (size_t)mmax * mmax), std::make_pair(&X, (size_t)k * n),
+                  std::make_pair(&AX, (size_t)k * n), std::make_pair(&R, (size_t)k * n),
+                  std::make_pair(&T, (size_t)k * n), std::make_pair(&G, (size_t)mmax * k),
+                  std::make_pair(&nrm, (size_t)k), std::make_pair(&Sm, (size_t)k * k),
+                  std::make_pair(&lam, (size_t)k), std::make_pair(&U, (size_t)k * k),
+                  std::make_pair(&Y, (size_t)k * n), std::make_pair(&sc, (size_t)k)})
+    if (!rc) rc = pr.first->alloc(pr.second);
+  if (rc) return rc;
+  if (hipMemcpyAsync(dd.p, d.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(V.p, v0.data(), sizeof(double) * v0.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  launch_add_diag(C, dd.p, n, A.p, s);
+  launch_dgemm(0, 1, k, n, n, 1.0, V.p, n, A.p, n, 0.0, AV.p, n, s);
+  int m = k, it = 0;
+  bool done = false;
+  std::vector<double> h_n(k), h_l(k);
+  for (it = 1; it <= max_iter && !done; ++it) {
+    launch_dgemm(0, 1, m, m, n, 1.0, V.p, n, AV.p, n, 0.0, H.p, m, s);
+    launch_jacobi(m, H.p, m, th.p, S.p, m, 60, 1e-15, s);
+    launch_dgemm(1, 0, k, n, m, 1.0, S.p, m, V.p, n, 0.0, X.p, n, s);
+    launch_dgemm(1, 0, k, n, m, 1.0, S.p, m, AV.p, n, 0.0, AX.p, n, s);
+    launch_residual(X.p, AX.p, th.p, n, k, R.p, nrm.p, s);
+    if (hipMemcpyAsync(h_n.data(), nrm.p, sizeof(double) * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return ACE_ERR_HIP;
+    double worst = 0.0;
+    for (int j = 0; j < k; ++j) worst = std::max(worst, std::sqrt(h_n[j]));
+    if (worst < tol) {
+      done = true;
+      break;
+    }
+    if (m + k > mmax) {  // restart from the current Ritz vectors
+      if (hipMemcpyAsync(V.p, X.p, sizeof(double) * k * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(AV.p, AX.p, sizeof(double) * k * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return ACE_ERR_HIP;
+      m = k;
+      continue;
+    }
+    launch_dav_precond(R.p, dd.p, th.p, n, k, T.p, s);
+    for (int pass = 0; pass < 2; ++pass) {  // project out the subspace, twice
+      launch_dgemm(0, 1, m, k, n, 1.0, V.p, n, T.p, n, 0.0, G.p, k, s);
+      launch_dgemm(1, 0, k, n, m, -1.0, G.p, k, V.p, n, 1.0, T.p, n, s);
+    }
+    // canonical orthonormalisation of the new block: T T^T = U diag(l) U^T, Y = l^{-1/2} U^T T
+    launch_dgemm(0, 1, k, k, n, 1.0, T.p, n, T.p, n, 0.0, Sm.p, k, s);
+    launch_jacobi(k, Sm.p, k, lam.p, U.p, k, 60, 1e-15, s);
+    if (hipMemcpyAsync(h_l.data(), lam.p, sizeof(double) * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return ACE_ERR_HIP;
+    const double lmax = h_l[k - 1];
+    std::vector<double> scale(k, 0.0);
+    int first = k;
+    for (int j = k - 1; j >= 0; --j)
+      if (h_l[j] > 1e-12 * std::max(lmax, 1e-300) && h_l[j] > 1e-24) {
+        scale[j] = 1.0 / std::sqrt(h_l[j]);
+        first = j;
+      }
+    const int kk = k - first;
+    if (kk == 0) break;  // no new direction: the subspace is exhausted
+    launch_dgemm(1, 0, k, n, k, 1.0, U.p, k, T.p, n, 0.0, Y.p, n, s);
+    if (hipMemcpyAsync(sc.p, scale.data(), sizeof(double) * k, hipMemcpyHostToDevice, s) != hipSuccess)
+      return ACE_ERR_HIP;
+    launch_scale_rows(Y.p, sc.p, n, k, s);
+    if (hipMemcpyAsync(V.p + (size_t)m * n, Y.p + (size_t)first * n, sizeof(double) * kk * n,
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return ACE_ERR_HIP;
+    launch_dgemm(0, 1, kk, n, n, 1.0, V.p + (size_t)m * n, n, A.p, n, 0.0, AV.p + (size_t)m * n, n, s);
+    m += kk;
+    if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;  // host vectors reused
+  }
+  if (hipMemcpyAsync(omega_out, th.p, sizeof(double) * k, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  if (X_out && hipMemcpyAsync(X_out, X.p, sizeof(double) * k * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;
+  if (iterations) *iterations = done ? it : -it;
+  return hip_check(hipGetLastError());
+}
+
+int tda_oscillator_strengths(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, int nv,
+                             const double* X, const double* omega, int nstates, double* f_out,
+                             double* d_out) {
+  if (!c || !phi_occ || !phi_virt || !X || !omega || !f_out || no < 1 || nv < 1 || nstates < 1)
+    return ACE_ERR_INVALID;
+  if (is_cplx(c->dtype)) return ACE_ERR_UNSUPPORTED;
+  const int nov = no * nv;
+  DevBuf D, dk;
+  int rc = D.alloc((size_t)3 * nov);
+  if (!rc) rc = dk.alloc((size_t)3 * nstates);
+  if (rc) return rc;
+  launch_dipoles(is_fp64(c->dtype), phi_occ, no, phi_virt, nv, c->n, c->h, D.p, c->stream);
+  // d_k[c] = sum_ia X_k[ia] D[c][ia]
+  launch_dgemm(0, 1, nstates, 3, nov, 1.0, X, nov, D.p, nov, 0.0, dk.p, 3, c->stream);
+  launch_oscillator(omega, dk.p, nstates, f_out, c->stream);
+  if (d_out && hipMemcpyAsync(d_out, dk.p, sizeof(double) * 3 * nstates, hipMemcpyDeviceToDevice,
+                              c->stream) != hipSuccess)
+    return ACE_ERR_HIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return ACE_ERR_HIP;  // scratch freed on return
+  return hip_check(hipGetLastError());
+}
+
+int strength_function(const double* omega, const double* f, int nstates, double w0, double dw,
+                      int nw, double gamma, double* S_out, void* stream) {
+  if (!omega || !f || !S_out || nstates < 1 || nw < 1 || !(gamma > 0.0)) return ACE_ERR_INVALID;
+  launch_strength(omega, f, nstates, w0, dw, nw, gamma, S_out, (hipStream_t)stream);
+  return hip_check(hipGetLastError());
+}
+
+}  // extern "C"

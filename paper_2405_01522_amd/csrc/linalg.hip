@@ -1,0 +1,256 @@
+// Small dense FP64 linear algebra used by the eigensolver drivers built on top of the ACE
+// engine (subspace Rayleigh-Ritz of the SCF eigensolver, Davidson for the Tamm-Dancoff
+// problem): a tiled GEMM with transpose flags and a one-workgroup parallel-order Jacobi
+// eigensolver for symmetric matrices of order <= 64.
+#include <hip/hip_runtime.h>
+
+#include "linalg.hpp"
+
+namespace ace {
+
+namespace {
+
+// C = alpha op(A) op(B) + beta C, row-major; op(X) = X or X^T.  64 x 64 tiles, 256 threads,
+// 4 x 4 outputs per thread, K staged 16 at a time through LDS.
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(256) void k_dgemm(int ta, int tb, int M, int N, int K, double alpha,
+                                               const double* __restrict__ A, int lda,
+                                               const double* __restrict__ B, int ldb,
+                                               double beta, double* __restrict__ C, int ldc) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = threadIdx.x; e < GT * GK; e += 256) {
+      const int r = e / GK, kk = e % GK;  // tile row r, depth kk
+      const int m = m0 + r, n = n0 + r, k = k0 + kk;
+      double av = 0.0, bv = 0.0;
+      if (m < M && k < K) av = ta ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+      if (n < N && k < K) bv = tb ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+      As[kk][r] = av;
+      Bs[kk][r] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (m < M && n < N) {
+        double* c = C + (size_t)m * ldc + n;
+        *c = alpha * acc[i][j] + (beta == 0.0 ? 0.0 : beta * *c);
+      }
+    }
+}
+
+// Symmetric eigendecomposition by the cyclic Jacobi method in round-robin (tournament)
+// order: each round rotates n/2 disjoint index pairs at once (row rotations, barrier, column
+// rotations).  One workgroup; matrix and eigenvectors in LDS.  Output: w ascending,
+// V[i][k] = component i of eigenvector k (row-major, leading dimension ldv).
+constexpr int JMAX = 64;
+
+__global__ __launch_bounds__(256) void k_jacobi(int n, const double* __restrict__ Ain, int lda,
+                                                double* __restrict__ w, double* __restrict__ V,
+                                                int ldv, int max_sweeps, double tol) {
+  __shared__ double a[JMAX][JMAX + 1];
+  __shared__ double v[JMAX][JMAX + 1];
+  __shared__ double cs[JMAX / 2], sn[JMAX / 2];
+  __shared__ int pp[JMAX / 2], qq[JMAX / 2];
+  __shared__ double red[256];
+  __shared__ int rank_s[JMAX];
+  const int m = n + (n & 1);  // even order; a padding index acts as an isolated zero row
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e % m;
+    double x = 0.0;
+    if (i < n && j < n) x = 0.5 * (Ain[(size_t)i * lda + j] + Ain[(size_t)j * lda + i]);
+    a[i][j] = x;
+    v[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // off-diagonal and total norms
+    double off = 0.0, tot = 0.0;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = e / m, j = e % m;
+      const double x = a[i][j] * a[i][j];
+      tot += x;
+      if (i != j) off += x;
+    }
+    red[threadIdx.x] = off;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    const double offn = red[0];
+    __syncthreads();
+    red[threadIdx.x] = tot;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    const double totn = red[0];
+    __syncthreads();
+    if (offn <= tol * tol * totn || offn == 0.0) break;
+    for (int round = 0; round < m - 1; ++round) {
+      // tournament pairing: position 0 fixed, the others rotate
+      if ((int)threadIdx.x < m / 2) {
+        const int k = threadIdx.x;
+        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
+        int p = at(k), q = at(m - 1 - k);
+        if (p > q) { const int t = p; p = q; q = t; }
+        pp[k] = p;
+        qq[k] = q;
+        const double apq = a[p][q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+        }
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {
+        const int k = e / m, j = e % m;
+        const int p = pp[k], q = qq[k];
+        const double c = cs[k], s = sn[k];
+        const double x = a[p][j], y = a[q][j];
+        a[p][j] = c * x - s * y;
+        a[q][j] = s * x + c * y;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {
+        const int k = e / m, i = e % m;
+        const int p = pp[k], q = qq[k];
+        const double c = cs[k], s = sn[k];
+        const double x = a[i][p], y = a[i][q];
+        a[i][p] = c * x - s * y;
+        a[i][q] = s * x + c * y;
+        const double vx = v[i][p], vy = v[i][q];
+        v[i][p] = c * vx - s * vy;
+        v[i][q] = s * vx + c * vy;
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order: rank of each eigenvalue (ties broken by index)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int r = 0;
+    for (int j = 0; j < n; ++j)
+      if (a[j][j] < a[i][i] || (a[j][j] == a[i][i] && j < i)) ++r;
+    rank_s[i] = r;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, k = e % n;  // component i of eigenvector k (unsorted)
+    V[(size_t)i * ldv + rank_s[k]] = v[i][k];
+  }
+  for (int k = threadIdx.x; k < n; k += blockDim.x) w[rank_s[k]] = a[k][k];
+}
+
+// A = C + diag(d) (copy); n x n row-major
+__global__ void k_add_diag(const double* __restrict__ C, const double* __restrict__ d, int n,
+                           double* __restrict__ A) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    A[e] = C[e] + (i == j ? d[i] : 0.0);
+  }
+}
+
+// R_j = AX_j - theta_j X_j and the squared norms |R_j|^2 (one block per row j)
+__global__ void k_residual(const double* __restrict__ X, const double* __restrict__ AX,
+                           const double* __restrict__ theta, int n, double* __restrict__ R,
+                           double* __restrict__ norm2) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = AX[(size_t)j * n + i] - theta[j] * X[(size_t)j * n + i];
+    R[(size_t)j * n + i] = r;
+    s += r * r;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norm2[j] = red[0];
+}
+
+// Davidson correction T_j = R_j / (theta_j - d) (denominator kept away from zero)
+__global__ void k_dav_precond(const double* __restrict__ R, const double* __restrict__ d,
+                              const double* __restrict__ theta, int n, int k,
+                              double* __restrict__ T) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * k;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / n), i = (int)(e % n);
+    double den = theta[j] - d[i];
+    if (fabs(den) < 1e-6) den = den < 0.0 ? -1e-6 : 1e-6;
+    T[e] = R[e] / den;
+  }
+}
+
+// rows of Y scaled: Y_j *= s_j
+__global__ void k_scale_rows(double* __restrict__ Y, const double* __restrict__ s, int n, int k) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * k;
+       e += (size_t)gridDim.x * blockDim.x)
+    Y[e] *= s[e / n];
+}
+
+}  // namespace
+
+void launch_add_diag(const double* C, const double* d, int n, double* A, hipStream_t s) {
+  k_add_diag<<<256, 256, 0, s>>>(C, d, n, A);
+}
+
+void launch_residual(const double* X, const double* AX, const double* theta, int n, int k,
+                     double* R, double* norm2, hipStream_t s) {
+  k_residual<<<k, 256, 0, s>>>(X, AX, theta, n, R, norm2);
+}
+
+void launch_dav_precond(const double* R, const double* d, const double* theta, int n, int k,
+                        double* T, hipStream_t s) {
+  k_dav_precond<<<256, 256, 0, s>>>(R, d, theta, n, k, T);
+}
+
+void launch_scale_rows(double* Y, const double* sc, int n, int k, hipStream_t s) {
+  k_scale_rows<<<256, 256, 0, s>>>(Y, sc, n, k);
+}
+
+void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+                  const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+  k_dgemm<<<grid, 256, 0, s>>>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
+                   int max_sweeps, double tol, hipStream_t s) {
+  k_jacobi<<<1, 256, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol);
+}
+
+}  // namespace ace

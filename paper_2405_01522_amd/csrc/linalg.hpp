@@ -1,0 +1,26 @@
+// Small dense FP64 linear algebra (linalg.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ace {
+
+constexpr int kJacobiMax = 64;  // largest order of the one-workgroup Jacobi eigensolver
+
+// C = alpha op(A) op(B) + beta C (row-major; ta / tb select the transpose)
+void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const double* A, int lda,
+                  const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
+
+// eigenvalues ascending in w[n], eigenvectors in the columns of V (ld ldv); n <= kJacobiMax
+void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
+                   int max_sweeps, double tol, hipStream_t s);
+
+// Davidson helpers (rows of length n are vectors)
+void launch_add_diag(const double* C, const double* d, int n, double* A, hipStream_t s);
+void launch_residual(const double* X, const double* AX, const double* theta, int n, int k,
+                     double* R, double* norm2, hipStream_t s);
+void launch_dav_precond(const double* R, const double* d, const double* theta, int n, int k,
+                        double* T, hipStream_t s);
+void launch_scale_rows(double* Y, const double* sc, int n, int k, hipStream_t s);
+
+}  // namespace ace

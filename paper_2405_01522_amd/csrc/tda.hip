@@ -328,7 +328,81 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
   k_tda_assemble<<<rbj, 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out, 0);
 }
 
+// D[c][i*nv + a] = dV sum_r phi_i(r) x_c(r) phi_a(r), x_c = (k_c - (n-1)/2) h: one block per
+// (i, a), fixed-order tree reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dipoles(const T* __restrict__ occ, const T* __restrict__ virt,
+                                                 int nv, int n, double h, double* __restrict__ D,
+                                                 int nov) {
+  __shared__ double red[3][256];
+  const int i = blockIdx.x / nv, a = blockIdx.x % nv;
+  const size_t ng = (size_t)n * n * n;
+  const T* pi = occ + (size_t)i * ng;
+  const T* pa = virt + (size_t)a * ng;
+  const double c0 = 0.5 * (n - 1);
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (size_t r = threadIdx.x; r < ng; r += blockDim.x) {
+    const double w = (double)pi[r] * (double)pa[r];
+    const int z = (int)(r % n), y = (int)((r / n) % n), x = (int)(r / ((size_t)n * n));
+    sx += w * (x - c0);
+    sy += w * (y - c0);
+    sz += w * (z - c0);
+  }
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = sy;
+  red[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) D[(size_t)threadIdx.x * nov + blockIdx.x] = red[threadIdx.x][0] * h * h * h * h;
+}
+
+// f_k = 2/3 omega_k |d_k|^2  (d: [k][3])
+__global__ void k_oscillator(const double* __restrict__ omega, const double* __restrict__ d, int k,
+                             double* __restrict__ f) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) {
+    const double dx = d[3 * j], dy = d[3 * j + 1], dz = d[3 * j + 2];
+    f[j] = 2.0 / 3.0 * omega[j] * (dx * dx + dy * dy + dz * dz);
+  }
+}
+
+// S(w) = sum_k f_k gamma / (pi ((w - omega_k)^2 + gamma^2)),  w = w0 + i dw
+__global__ void k_strength(const double* __restrict__ omega, const double* __restrict__ f, int k,
+                           double w0, double dw, int nw, double gamma, double* __restrict__ S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw) return;
+  const double w = w0 + i * dw;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double x = w - omega[j];
+    s += f[j] * gamma / (3.14159265358979323846 * (x * x + gamma * gamma));
+  }
+  S[i] = s;
+}
+
 }  // namespace
+
+void launch_dipoles(bool fp64, const void* occ, int no, const void* virt, int nv, int n, double h,
+                    double* D, hipStream_t s) {
+  const int nov = no * nv;
+  if (fp64)
+    k_dipoles<double><<<nov, 256, 0, s>>>((const double*)occ, (const double*)virt, nv, n, h, D, nov);
+  else
+    k_dipoles<float><<<nov, 256, 0, s>>>((const float*)occ, (const float*)virt, nv, n, h, D, nov);
+}
+
+void launch_oscillator(const double* omega, const double* d, int k, double* f, hipStream_t s) {
+  k_oscillator<<<(k + 63) / 64, 64, 0, s>>>(omega, d, k, f);
+}
+
+void launch_strength(const double* omega, const double* f, int k, double w0, double dw, int nw,
+                     double gamma, double* S, hipStream_t s) {
+  k_strength<<<(nw + 255) / 256, 256, 0, s>>>(omega, f, k, w0, dw, nw, gamma, S);
+}
 
 size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
   const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2, nvv = (size_t)nv * nv;

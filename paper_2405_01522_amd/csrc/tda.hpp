@@ -22,4 +22,13 @@ void launch_tda(bool fp64, const void* occ, int no, const void* virt, int nv, co
                 const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
                 double* c_out, hipStream_t s, Trace* tr);
 
+// D[c][i*nv + a] = <i| x_c |a> (c = x, y, z) on the box grid of edge n, spacing h
+void launch_dipoles(bool fp64, const void* occ, int no, const void* virt, int nv, int n, double h,
+                    double* D, hipStream_t s);
+// f_k = 2/3 omega_k |d_k|^2
+void launch_oscillator(const double* omega, const double* d, int k, double* f, hipStream_t s);
+// S(w_i) = sum_k f_k L_gamma(w_i - omega_k), w_i = w0 + i dw
+void launch_strength(const double* omega, const double* f, int k, double w0, double dw, int nw,
+                     double gamma, double* S, hipStream_t s);
+
 }  // namespace ace

@@ -1,0 +1,99 @@
+"""GPU parity of the Tamm-Dancoff eigen-solution and spectrum (paper Sec. 2, Eqs. (7)-(10)) and of
+the small dense helpers they use, against the FP64 oracle and numpy's LAPACK routines."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid, tda
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _ace():
+    import paper_2405_01522_amd as ace
+    return ace
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 64])
+def test_sym_eig_small(n):
+    ace = _ace()
+    rng = np.random.default_rng(n)
+    a = rng.normal(size=(n, n))
+    a = a + a.T
+    w, v = ace.sym_eig_small(torch.from_numpy(a).to(DEV))
+    w, v = w.cpu().numpy(), v.cpu().numpy()
+    wr = np.linalg.eigvalsh(a)
+    assert np.max(np.abs(w - wr)) < 1e-12 * max(1.0, np.max(np.abs(wr)))
+    assert np.max(np.abs(a @ v - v * w[None, :])) < 1e-11 * max(1.0, np.max(np.abs(wr)))
+    assert np.max(np.abs(v.T @ v - np.eye(n))) < 1e-12
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_dense_gemm(ta, tb):
+    ace = _ace()
+    rng = np.random.default_rng(3 + 2 * ta + tb)
+    m, n, k = 70, 45, 130
+    a = rng.normal(size=(k, m) if ta else (m, k))
+    b = rng.normal(size=(n, k) if tb else (k, n))
+    c0 = rng.normal(size=(m, n))
+    ref = 0.7 * ((a.T if ta else a) @ (b.T if tb else b)) - 0.3 * c0
+    out = torch.from_numpy(c0.copy()).to(DEV)
+    got = ace.dense_gemm(torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV), ta, tb, 0.7, -0.3, out)
+    assert np.max(np.abs(got.cpu().numpy() - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.fixture(scope="module")
+def mid():
+    m = synth.small_real(23, 24, 0.3, 4, 8)
+    return m, tda.coupling_block(m.phi, m.phi_virt, m.h, 2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tda_states_and_spectrum(mid, prec):
+    """Lowest TDA states (Davidson), oscillator strengths and the broadened spectrum vs the
+    oracle's dense eigendecomposition: 1e-9 eV (FP64 storage) / 1e-4 eV (FP32 storage)."""
+    ace = _ace()
+    m, cref = mid
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    single = prec == "fp32"
+    ctx = ace.AceContext(m.n, m.h, dt)
+    occ = torch.from_numpy(synth.to_precision(m.phi, single)).to(DEV)
+    virt = torch.from_numpy(synth.to_precision(m.phi_virt, single)).to(DEV)
+    c = ctx.tda_coupling(occ, virt, 2)
+    k = 6
+    omega, x, it = ctx.tda_excitations(c, m.eps_occ, m.eps_virt, k, tol=1e-9)
+    assert it > 0
+    w_ref, x_ref = tda.excitations(tda.tda_matrix(cref, m.eps_occ, m.eps_virt))
+    ev = 27.211386245988
+    tol_ev = 1e-9 if prec == "fp64" else 1e-4
+    assert np.max(np.abs(omega.cpu().numpy() - w_ref[:k])) * ev < tol_ev
+    # oscillator strengths (vectors unique up to sign for these non-degenerate states)
+    f, d = ctx.tda_oscillator_strengths(occ, virt, x, omega)
+    mesh = np.meshgrid(grid.coords(m.n, m.h), grid.coords(m.n, m.h), grid.coords(m.n, m.h), indexing="ij")
+    dip = tda.dipole_elements(m.phi, m.phi_virt, m.h, mesh)
+    f_ref = tda.oscillator_strengths(w_ref[:k], x_ref[:, :k], dip)
+    ftol = 1e-8 if prec == "fp64" else 2e-4
+    assert np.max(np.abs(f.cpu().numpy() - f_ref)) < ftol * max(1e-3, np.max(np.abs(f_ref)))
+    s = ace.strength_function(omega, f, 0.0, 0.01, 400, 0.0005)
+    s_ref = tda.strength_function(np.arange(400) * 0.01, w_ref[:k], f_ref, 0.0005)
+    assert np.max(np.abs(s.cpu().numpy() - s_ref)) < max(1e-6, ftol) * max(1.0, np.max(np.abs(s_ref))) * 50
+
+
+def test_tda_states_config3():
+    """Full 64^3 / 16 + 32 block: the Davidson states equal the dense eigendecomposition of the
+    same GPU block (numpy LAPACK), and the lowest excitation is positive."""
+    ace = _ace()
+    m = synth.config3()
+    ctx = ace.AceContext(m.n, m.h, torch.float32)
+    occ = torch.from_numpy(synth.to_precision(m.phi, True)).to(DEV)
+    virt = torch.from_numpy(synth.to_precision(m.phi_virt, True)).to(DEV)
+    c = ctx.tda_coupling(occ, virt, 2)
+    omega, x, it = ctx.tda_excitations(c, m.eps_occ, m.eps_virt, 8, tol=1e-8)
+    assert it > 0
+    a = tda.tda_matrix(c.cpu().numpy(), m.eps_occ, m.eps_virt)
+    w_ref = np.linalg.eigvalsh(a)[:8]
+    assert np.max(np.abs(omega.cpu().numpy() - w_ref)) < 1e-10
+    assert w_ref[0] > 0.0
