@@ -18,6 +18,10 @@ Everything here is written for a reader holding the paper (Panta & Strubbe,
 * ``tda``      -- two-electron integrals and the RHF Tamm-Dancoff A matrix, Eq. (7) and
                   the TDA paragraph of Sec. 2; eigenvalues, dipoles, oscillator strengths
                   (Eqs. (8)-(10)).
+* ``scf``      -- closed-shell HF ground state on the grid: Eq. (1) with linear mixing of
+                  states (Eq. (14)) and the relative density error stop (Eq. (15)).
+* ``convnet``  -- a three-layer 3-D convolutional network (forward, exact gradients) used
+                  as a learned eigensolver preconditioner; not from the paper.
 
 All arithmetic is float64 / complex128.  Library primitives used as steps: numpy/scipy
 FFT, matmul, Cholesky, triangular solve, Hermitian eigensolver.
@@ -25,4 +29,4 @@ FFT, matmul, Cholesky, triangular solve, Hermitian eigensolver.
 Parity status per function is stated in each module docstring.
 """
 
-from . import grid, poisson, exchange, tda  # noqa: F401
+from . import grid, poisson, exchange, tda, scf, convnet  # noqa: F401
