@@ -231,6 +231,139 @@ int ace_trace_reset(ace_ctx* ctx);
 int ace_trace_count(void);
 const char* ace_trace_name(int id);
 
+/* ---------------------------------------------------------------------------------------
+ * Closed-shell Hartree-Fock ground state (Eq. (1)) on the isolated grid, real orbitals
+ * (contexts of dtype ACE_R64 or ACE_R32; others return ACE_ERR_UNSUPPORTED).
+ *
+ * The paper's Hamiltonian needs pseudopotentials that are not part of this library; these
+ * pieces are fixed here:
+ *   T       = -1/2 Laplacian by fourth-order central differences on each axis,
+ *             (-f(x-2h) + 16 f(x-h) - 30 f(x) + 16 f(x+h) - f(x+2h)) / (12 h^2), orbitals
+ *             zero outside the box;
+ *   V_ext   = any local potential the caller passes (one grid volume);
+ *   rho     = 2 sum_i phi_i^2 (n doubly occupied orbitals, normalised sum phi^2 dV = 1);
+ *   v_H     = dV G (*) rho with the Poisson kernel above;
+ *   K       = the exchange operator of Eq. (2) over the occupied spatial orbitals, applied
+ *             through ACE (Eqs. (11)-(13)) rebuilt every SCF iteration (Sec. 3.1);
+ *   E       = 2 sum_i <phi_i|T + V_ext|phi_i> + 1/2 int rho v_H + sum_i <phi_i|K phi_i>.
+ * ------------------------------------------------------------------------------------- */
+
+/* out_v = (accumulate ? out_v : 0) + T psi_v + v_local psi_v, v < nv (v_local may be NULL). */
+int fock_local_apply(ace_ctx* ctx, const void* v_local, const void* psi, int nv, int accumulate,
+                     void* out);
+
+/* rho = 2 sum_{i<k} phi_i^2 (Eq. (1)'s closed-shell density). */
+int scf_density(ace_ctx* ctx, const void* phi, int k, void* rho);
+
+/* Hartree potential v_H = dV G (*) rho (one isolated Poisson solve, Sec. 3.1).  Allocates a
+ * scratch volume and synchronises the stream. */
+int hartree_potential(ace_ctx* ctx, const void* rho, void* v_h);
+
+/* Kinetic preconditioner z ~ (T + shift)^{-1} r for nv vectors: z_0 = r / (d + shift) with
+ * d = 15 / (4 h^2) the diagonal of T, then sweeps - 1 damped-Jacobi steps
+ * z <- z + omega (r - (T + shift) z) / (d + shift).  sweeps >= 1, 0 < omega < 2.
+ * Synchronises the stream. */
+int kinetic_precondition(ace_ctx* ctx, const void* r, int nv, double shift, int sweeps,
+                         double omega, void* z);
+
+/* ---- learned preconditioner: a 3-D convolutional network (not from the paper) ----------
+ * x (1 channel) -> conv 3x3x3 (8) -> ReLU -> conv 3x3x3 (8) -> ReLU -> conv 3x3x3 (1), zero
+ * padding.  Weights BF16 (rounded from FP32 masters), activations and sums FP32.
+ * Parameters (FP32, ACE_NET_PARAMS values): [w0 8x1x27][b0 8][w1 8x8x27][b1 8][w2 1x8x27][b2 1],
+ * w[out][in][t] acting on the input at offset (t/9 - 1, (t/3)%3 - 1, t%3 - 1). */
+#define ACE_NET_PARAMS 2177
+typedef struct ace_convnet ace_convnet;
+
+int convnet_create(void* hip_stream, ace_convnet** out);  /* parameters zero */
+int convnet_destroy(ace_convnet* net);
+/* params (host, ACE_NET_PARAMS FP32): set the masters, round the compute copy to BF16, reset
+ * Adam.  Synchronises. */
+int convnet_set_params(ace_convnet* net, const float* params);
+/* params (host): the masters (rounded = 0) or the BF16-rounded compute copy (rounded = 1). */
+int convnet_get_params(ace_convnet* net, float* params, int rounded);
+/* y[b] = net(x[b]) for nb FP32 volumes of edge n (device). */
+int convnet_forward(ace_convnet* net, int n, const float* x, int nb, float* y);
+/* Loss L = 1/2 sum (net(x) - t)^2 / (nb n^3) and its gradient with respect to the BF16
+ * compute weights; *loss and grad[ACE_NET_PARAMS] are host (either may be NULL). */
+int convnet_gradient(ace_convnet* net, int n, const float* x, const float* t, int nb,
+                     double* loss, float* grad);
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the loss above
+ * over `count` (input, target) volume pairs (device).  flags & ACE_TRAIN_RANDOM: each step
+ * draws `batch` pairs (SplitMix64 of seed, step and slot) with random sign; otherwise batch
+ * must equal count and every step uses all pairs in order.  loss_hist (host, steps, may be
+ * NULL) receives the loss of each step before its update.  Synchronises. */
+#define ACE_TRAIN_RANDOM 1
+int convnet_train(ace_convnet* net, int n, const float* inputs, const float* targets, int count,
+                  int steps, int batch, double lr, unsigned long long seed, int flags,
+                  double* loss_hist);
+
+/* ---- block eigensolver and SCF -------------------------------------------------------- */
+enum { ACE_PRECOND_NONE = 0, ACE_PRECOND_KINETIC = 1, ACE_PRECOND_NET = 2 };
+
+typedef struct ace_eig_opts {
+  int max_steps;     /* eigensolver steps (per SCF iteration in scf_run) */
+  double tol;        /* stop when every residual |F x - lambda x| (dV norm) < tol (0: off) */
+  int precond;       /* ACE_PRECOND_* */
+  double shift;      /* kinetic preconditioner shift (hartree) */
+  int sweeps;        /* kinetic preconditioner Jacobi sweeps (>= 1) */
+  double omega;      /* kinetic preconditioner damping (0 < omega < 2) */
+  ace_convnet* net;  /* learned preconditioner (ACE_PRECOND_NET) */
+} ace_eig_opts;
+
+/*
+ * k lowest eigenpairs of F = T + v_local (+ K_ACE with nxi vectors xi, Eq. (13), if nxi > 0)
+ * by LOBPCG: Rayleigh-Ritz over [X, M R, P] (current vectors, preconditioned residuals,
+ * previous directions; P is left out when 3k > 64), canonical orthonormalisation in FP64.
+ * The non-self-consistent run with a fixed Hamiltonian of Sec. 3.1.
+ * phi: k start vectors, overwritten by the Ritz vectors (dV-orthonormal); eigval, resnorm
+ * (host, k, may be NULL); *steps (host, may be NULL) = steps taken.  Synchronises.
+ */
+int fock_lowest_states(ace_ctx* ctx, const void* v_local, const void* xi, int nxi, void* phi,
+                       int k, const ace_eig_opts* opts, double* eigval, double* resnorm,
+                       int* steps);
+
+/* Energy terms of k doubly occupied orbitals: energy[5] (host) = total, kinetic, external,
+ * Hartree, exchange (see above).  Synchronises. */
+int scf_energies(ace_ctx* ctx, const void* v_ext, const void* phi, int k, double* energy);
+
+typedef struct ace_scf_opts {
+  ace_eig_opts eig;  /* eigensolver per iteration; eig.tol also enters the stop test */
+  double alpha;      /* states mixing q_{N+1} = alpha q_{N-1} + (1 - alpha) q_N, Eq. (14) */
+  double tol;        /* relative density error stop, Eq. (15) */
+  int max_iter;
+  float* rec_in;     /* optional (device, rec_cap volumes, ACE_R32 only): residuals / RMS */
+  float* rec_tgt;    /* optional: the current vectors / RMS of their residuals */
+  int rec_cap;
+} ace_scf_opts;
+
+typedef struct ace_scf_result {
+  double energy[5];      /* as scf_energies, of the returned orbitals */
+  double density_error;  /* Eq. (15) of the last iteration */
+  double max_residual;   /* largest eigensolver residual of the last iteration */
+  int iterations;
+  int eig_steps;         /* eigensolver steps over all iterations */
+  int converged;
+  int rec_count;         /* recorded (residual, vector) pairs */
+} ace_scf_result;
+
+/*
+ * Closed-shell HF SCF from the k orbitals phi (device, overwritten).  Each iteration:
+ * rho_in and v_H from phi, ACE rebuilt from phi, eig.max_steps eigensolver steps from phi,
+ * the new set rotated onto the old (orthogonal Procrustes), the density error of Eq. (15)
+ * between the two densities, then the states mixed by Eq. (14) and re-orthonormalised
+ * (Loewdin).  Stops when the error is below tol and every residual below eig.tol; phi then
+ * holds the rotated new set, else the last mixed set.  res (host) and eigval (host, k) /
+ * err_hist (host, max_iter), which may be NULL, receive the results.  Synchronises.
+ */
+int scf_run(ace_ctx* ctx, const void* v_ext, void* phi, int k, const ace_scf_opts* opts,
+            ace_scf_result* res, double* eigval, double* err_hist);
+
+/* Training targets of the learned preconditioner from converged orbitals phi (k):
+ * tgt_v <- Phi (Phi^T tgt_v dV) - tgt_v for count FP32 volumes (ACE_R32 contexts), i.e.
+ * the correction that takes a recorded vector onto the converged occupied space.
+ * Synchronises. */
+int precond_targets(ace_ctx* ctx, const void* phi, int k, float* tgt, int count);
+
 /* Static message for a return code. */
 const char* ace_strerror(int code);
 

@@ -78,6 +78,42 @@ def backward(params, cache, y, t):
     return grads
 
 
+def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, bias-corrected moments) of a list of arrays, in place of
+    copies: returns the new parameter list; ``state`` holds t and the moment arrays."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    if "m" not in state:
+        state["m"] = [np.zeros_like(p) for p in params]
+        state["v"] = [np.zeros_like(p) for p in params]
+    out = []
+    for i, (p, g) in enumerate(zip(params, grads)):
+        state["m"][i] = b1 * state["m"][i] + (1.0 - b1) * g
+        state["v"][i] = b2 * state["v"][i] + (1.0 - b2) * g * g
+        mh = state["m"][i] / (1.0 - b1 ** t)
+        vh = state["v"][i] / (1.0 - b2 ** t)
+        out.append(p - lr * mh / (np.sqrt(vh) + eps))
+    return out
+
+
+def flatten(params):
+    """Parameters as one vector in the order [w0, b0, w1, b1, w2, b2]."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params])
+
+
+def unflatten(vec):
+    out = []
+    pos = 0
+    for ci, co in LAYERS:
+        nw = co * ci * 27
+        w = np.asarray(vec[pos:pos + nw], dtype=np.float64).reshape(co, ci, 3, 3, 3)
+        pos += nw
+        b = np.asarray(vec[pos:pos + co], dtype=np.float64)
+        pos += co
+        out.append((w, b))
+    return out
+
+
 def init_params(rng, scale=0.2):
     return [(rng.normal(scale=scale / np.sqrt(27 * ci), size=(co, ci, 3, 3, 3)),
              np.zeros(co)) for ci, co in LAYERS]

@@ -59,6 +59,22 @@ def kinetic(f, h):
     return -0.5 * laplacian(f, h)
 
 
+def kinetic_diagonal(h):
+    """Diagonal element of T: 1/2 * 3 axes * 5/2 / h^2."""
+    return 0.5 * 3.0 * 2.5 / (h * h)
+
+
+def kinetic_precondition(r, h, shift, sweeps, omega):
+    """Approximate (T + shift)^{-1} r: z = r / (d + shift), then sweeps - 1 damped-Jacobi steps
+    z <- z + omega (r - (T + shift) z) / (d + shift) (d = diagonal of T).  Not from the paper:
+    the plain preconditioner the learned one is compared with."""
+    d = kinetic_diagonal(h) + shift
+    z = r / d
+    for _ in range(sweeps - 1):
+        z = z + omega * (r - (kinetic(z, h) + shift * z)) / d
+    return z
+
+
 def external_potential(n, h, centres, charges, sigma):
     x = grid.coords(n, h)
     v = np.zeros((n, n, n))

@@ -50,7 +50,26 @@ SIGNATURES = {
     "ace_trace_reset": (_I, [_P]),
     "ace_trace_count": (_I, []),
     "ace_trace_name": (ctypes.c_char_p, [_I]),
+    "fock_local_apply": (_I, [_P, _P, _P, _I, _I, _P]),
+    "scf_density": (_I, [_P, _P, _I, _P]),
+    "hartree_potential": (_I, [_P, _P, _P]),
+    "kinetic_precondition": (_I, [_P, _P, _I, _D, _I, _D, _P]),
+    "fock_lowest_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(_I)]),
+    "scf_energies": (_I, [_P, _P, _P, _I, _P]),
+    "scf_run": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
+    "precond_targets": (_I, [_P, _P, _I, _P, _I]),
+    "convnet_create": (_I, [_P, ctypes.POINTER(_P)]),
+    "convnet_destroy": (_I, [_P]),
+    "convnet_set_params": (_I, [_P, _P]),
+    "convnet_get_params": (_I, [_P, _P, _I]),
+    "convnet_forward": (_I, [_P, _I, _P, _I, _P]),
+    "convnet_gradient": (_I, [_P, _I, _P, _P, _I, _P, _P]),
+    "convnet_train": (_I, [_P, _I, _P, _P, _I, _I, _I, _D, ctypes.c_ulonglong, _I, _P]),
 }
+
+NET_PARAMS = 2177
+PRECOND_NONE, PRECOND_KINETIC, PRECOND_NET = 0, 1, 2
+TRAIN_RANDOM = 1
 
 
 class AceMol(ctypes.Structure):
@@ -58,6 +77,28 @@ class AceMol(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("h", ctypes.c_double), ("norb", ctypes.c_int),
                 ("phi", ctypes.c_void_p), ("xi", ctypes.c_void_p),
                 ("M", ctypes.c_void_p), ("ex", ctypes.c_void_p)]
+
+
+class AceEigOpts(ctypes.Structure):
+    """Mirror of ace_eig_opts."""
+    _fields_ = [("max_steps", ctypes.c_int), ("tol", ctypes.c_double), ("precond", ctypes.c_int),
+                ("shift", ctypes.c_double), ("sweeps", ctypes.c_int), ("omega", ctypes.c_double),
+                ("net", ctypes.c_void_p)]
+
+
+class AceScfOpts(ctypes.Structure):
+    """Mirror of ace_scf_opts."""
+    _fields_ = [("eig", AceEigOpts), ("alpha", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("rec_in", ctypes.c_void_p),
+                ("rec_tgt", ctypes.c_void_p), ("rec_cap", ctypes.c_int)]
+
+
+class AceScfResult(ctypes.Structure):
+    """Mirror of ace_scf_result."""
+    _fields_ = [("energy", ctypes.c_double * 5), ("density_error", ctypes.c_double),
+                ("max_residual", ctypes.c_double), ("iterations", ctypes.c_int),
+                ("eig_steps", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rec_count", ctypes.c_int)]
 
 
 class AceError(RuntimeError):

@@ -12,7 +12,8 @@ import ctypes
 
 import torch
 
-from ._lib import AceMol, check, lib
+from ._lib import (AceEigOpts, AceMol, AceScfOpts, AceScfResult, NET_PARAMS, PRECOND_KINETIC,
+                   PRECOND_NET, PRECOND_NONE, TRAIN_RANDOM, check, lib)
 
 ACE_C128, ACE_C64, ACE_R64, ACE_R32 = 0, 1, 2, 3
 _DTYPES = {torch.complex128: ACE_C128, torch.complex64: ACE_C64,
@@ -190,6 +191,114 @@ class AceContext:
               "tda_oscillator_strengths")
         return f, d
 
+    # -- closed-shell SCF pieces (real contexts) ----------------------------------------------
+    def _ptr(self, t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    def fock_local_apply(self, v_local, psi, out=None, accumulate=False):
+        """out = [out +] T psi + v_local psi (v_local: (1, N, N, N) or None)."""
+        if out is None:
+            out = self._empty(psi.shape[0])
+        p = self._vol(psi, "psi")
+        v = self._vol(v_local, "v_local", 1) if v_local is not None else None
+        o = self._vol(out, "out", psi.shape[0])
+        self._sync_stream()
+        check(lib().fock_local_apply(self._h, v, p, psi.shape[0], int(bool(accumulate)), o),
+              "fock_local_apply")
+        return out
+
+    def scf_density(self, phi, out=None):
+        if out is None:
+            out = self._empty(1)
+        check(lib().scf_density(self._h, self._vol(phi, "phi"), phi.shape[0],
+                                self._vol(out, "rho", 1)), "scf_density")
+        return out
+
+    def hartree_potential(self, rho, out=None):
+        if out is None:
+            out = self._empty(1)
+        self._sync_stream()
+        check(lib().hartree_potential(self._h, self._vol(rho, "rho", 1), self._vol(out, "v_h", 1)),
+              "hartree_potential")
+        return out
+
+    def kinetic_precondition(self, r, shift=1.0, sweeps=4, omega=0.8, out=None):
+        if out is None:
+            out = self._empty(r.shape[0])
+        self._sync_stream()
+        check(lib().kinetic_precondition(self._h, self._vol(r, "r"), r.shape[0], float(shift),
+                                         int(sweeps), float(omega), self._vol(out, "z", r.shape[0])),
+              "kinetic_precondition")
+        return out
+
+    def fock_lowest_states(self, v_local, phi, xi=None, opts=None):
+        """LOBPCG for the lowest phi.shape[0] states of T + v_local (+ K_ACE[xi]); phi is
+        overwritten by the Ritz vectors.  Returns (eigenvalues, residual norms, steps)."""
+        import numpy as np
+        k = phi.shape[0]
+        o = opts if opts is not None else eig_opts()
+        ev = np.zeros(k)
+        rn = np.zeros(k)
+        st = ctypes.c_int()
+        self._sync_stream()
+        check(lib().fock_lowest_states(self._h, self._vol(v_local, "v_local", 1),
+                                       self._vol(xi, "xi") if xi is not None else None,
+                                       xi.shape[0] if xi is not None else 0,
+                                       self._vol(phi, "phi"), k, ctypes.byref(o),
+                                       ev.ctypes.data_as(ctypes.c_void_p),
+                                       rn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)),
+              "fock_lowest_states")
+        return ev, rn, st.value
+
+    def scf_energies(self, v_ext, phi):
+        """dict(total, kinetic, external, hartree, exchange) of doubly occupied orbitals."""
+        import numpy as np
+        e = np.zeros(5)
+        self._sync_stream()
+        check(lib().scf_energies(self._h, self._vol(v_ext, "v_ext", 1), self._vol(phi, "phi"),
+                                 phi.shape[0], e.ctypes.data_as(ctypes.c_void_p)), "scf_energies")
+        return dict(zip(ENERGY_TERMS, e.tolist()))
+
+    def scf_run(self, v_ext, phi, opts=None, record=None):
+        """Closed-shell HF SCF from phi (overwritten).  record: optional pair of FP32 GPU
+        tensors (cap, N, N, N) receiving (normalised residual, normalised vector) pairs.
+        Returns a dict with energies, eigenvalues, iterations, density-error history, ..."""
+        import numpy as np
+        k = phi.shape[0]
+        o = opts if opts is not None else scf_opts()
+        if record is not None:
+            rin, rtg = record
+            for t in (rin, rtg):
+                if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or \
+                        tuple(t.shape[1:]) != (self.n,) * 3:
+                    raise ValueError("record tensors must be contiguous FP32 (cap, N, N, N)")
+            o.rec_in, o.rec_tgt, o.rec_cap = rin.data_ptr(), rtg.data_ptr(), min(rin.shape[0], rtg.shape[0])
+        else:
+            o.rec_in, o.rec_tgt, o.rec_cap = None, None, 0
+        res = AceScfResult()
+        ev = np.zeros(k)
+        hist = np.zeros(o.max_iter)
+        self._sync_stream()
+        check(lib().scf_run(self._h, self._vol(v_ext, "v_ext", 1), self._vol(phi, "phi"), k,
+                            ctypes.byref(o), ctypes.byref(res), ev.ctypes.data_as(ctypes.c_void_p),
+                            hist.ctypes.data_as(ctypes.c_void_p)), "scf_run")
+        out = dict(zip(ENERGY_TERMS, list(res.energy)))
+        out.update(eigenvalues=ev, iterations=res.iterations, eig_steps=res.eig_steps,
+                   converged=bool(res.converged), density_error=res.density_error,
+                   max_residual=res.max_residual, rec_count=res.rec_count,
+                   history=hist[:res.iterations].copy())
+        return out
+
+    def precond_targets(self, phi, tgt, count=None):
+        """tgt[v] <- Phi (Phi^T tgt[v] dV) - tgt[v] for the first `count` FP32 volumes."""
+        count = tgt.shape[0] if count is None else int(count)
+        if tgt.dtype != torch.float32 or not tgt.is_contiguous():
+            raise ValueError("tgt must be contiguous FP32")
+        self._sync_stream()
+        check(lib().precond_targets(self._h, self._vol(phi, "phi"), phi.shape[0],
+                                    ctypes.c_void_p(tgt.data_ptr()), count), "precond_targets")
+        return tgt
+
     def trace(self, on=True):
         """Enable / disable event timing of the library's kernel classes."""
         check(lib().ace_trace_enable(self._h, 1 if on else 0), "ace_trace_enable")
@@ -292,6 +401,96 @@ class AceBatch:
             if cnt.value:
                 out[lib().ace_trace_name(i).decode()] = (ms.value, cnt.value)
         return out
+
+
+ENERGY_TERMS = ("total", "kinetic", "external", "hartree", "exchange")
+
+
+def eig_opts(max_steps=50, tol=1e-6, precond="kinetic", shift=1.0, sweeps=4, omega=0.8, net=None):
+    """ace_eig_opts; precond is "none", "kinetic" or "net" (then pass a ConvNet)."""
+    code = {"none": PRECOND_NONE, "kinetic": PRECOND_KINETIC, "net": PRECOND_NET}[precond]
+    return AceEigOpts(int(max_steps), float(tol), code, float(shift), int(sweeps), float(omega),
+                      net._h if net is not None else None)
+
+
+def scf_opts(alpha=0.3, tol=1e-6, max_iter=100, eig=None):
+    """ace_scf_opts (states mixing alpha, Eq. (14); density error stop tol, Eq. (15))."""
+    return AceScfOpts(eig if eig is not None else eig_opts(max_steps=3),
+                      float(alpha), float(tol), int(max_iter), None, None, 0)
+
+
+class ConvNet:
+    """The learned preconditioner network (three 3x3x3 convolutions, BF16 weights); its
+    parameters live on the device.  Calls run on the stream current at creation."""
+
+    def __init__(self, params=None, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().convnet_create(_stream_handle(), ctypes.byref(handle)), "convnet_create")
+        self._h = handle
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().convnet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if a.size != NET_PARAMS:
+            raise ValueError("expected %d parameters" % NET_PARAMS)
+        check(lib().convnet_set_params(self._h, a.ctypes.data_as(ctypes.c_void_p)), "convnet_set_params")
+
+    def get_params(self, rounded=False):
+        import numpy as np
+        a = np.zeros(NET_PARAMS, dtype=np.float32)
+        check(lib().convnet_get_params(self._h, a.ctypes.data_as(ctypes.c_void_p), int(bool(rounded))),
+              "convnet_get_params")
+        return a
+
+    @staticmethod
+    def _vols(t, name):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4 or \
+                not (t.shape[1] == t.shape[2] == t.shape[3]):
+            raise ValueError("%s must be a contiguous FP32 GPU tensor (count, N, N, N)" % name)
+        return ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, x, out=None):
+        if out is None:
+            out = torch.empty_like(x)
+        check(lib().convnet_forward(self._h, x.shape[1], self._vols(x, "x"), x.shape[0],
+                                    self._vols(out, "y")), "convnet_forward")
+        return out
+
+    def gradient(self, x, t):
+        """(loss, gradient (NET_PARAMS,) numpy FP32) of 1/2 mean (net(x) - t)^2."""
+        import numpy as np
+        g = np.zeros(NET_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        check(lib().convnet_gradient(self._h, x.shape[1], self._vols(x, "x"), self._vols(t, "t"),
+                                     x.shape[0], ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p)),
+              "convnet_gradient")
+        return loss.value, g
+
+    def train(self, inputs, targets, steps, batch, lr, seed=0, random=True, count=None):
+        """Adam steps on (inputs, targets) pairs; returns the per-step losses (numpy)."""
+        import numpy as np
+        count = inputs.shape[0] if count is None else int(count)
+        hist = np.zeros(int(steps))
+        check(lib().convnet_train(self._h, inputs.shape[1], self._vols(inputs, "inputs"),
+                                  self._vols(targets, "targets"), count, int(steps), int(batch),
+                                  float(lr), int(seed) & ((1 << 64) - 1), TRAIN_RANDOM if random else 0,
+                                  hist.ctypes.data_as(ctypes.c_void_p)), "convnet_train")
+        return hist
 
 
 def strength_function(omega, f, w0, dw, nw, gamma):

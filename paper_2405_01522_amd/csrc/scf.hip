@@ -1,0 +1,496 @@
+// Grid kernels of the closed-shell SCF driver (paper Eq. (1) with the readings stated in
+// scf.hpp): the local Fock part (fourth-order finite-difference kinetic energy plus a local
+// potential), densities, the damped-Jacobi kinetic preconditioner, block combinations of
+// grid vectors, and the one-workgroup FP64 steps of the block eigensolver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "scf.hpp"
+
+namespace ace {
+
+namespace {
+
+constexpr int kT = 256;
+
+// Fourth-order central second difference on one axis: (-1/12, 4/3, -5/2, 4/3, -1/12) / h^2.
+// T = -1/2 Laplacian: centre 3 * 5/4 / h^2, first neighbours -2/3 / h^2, second 1/24 / h^2.
+struct Fd4 {
+  double c0, c1, c2;
+  explicit Fd4(double h) {
+    const double ih2 = 1.0 / (h * h);
+    c0 = 3.75 * ih2;
+    c1 = -2.0 / 3.0 * ih2;
+    c2 = 1.0 / 24.0 * ih2;
+  }
+};
+
+// value of x at (coordinate + off) along an axis of stride `stride`, zero outside the box;
+// the load itself is always in bounds (clamped to the centre point)
+template <typename T>
+__device__ __forceinline__ T nb(const T* __restrict__ xv, size_t r, int coord, int n,
+                                long long stride, int off) {
+  const int q = coord + off;
+  const bool ok = (unsigned)q < (unsigned)n;
+  const T v = xv[ok ? (long long)r + off * stride : (long long)r];
+  return ok ? v : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T kinetic_at(const T* __restrict__ xv, size_t r, int n, T c0, T c1,
+                                        T c2) {
+  const int iz = (int)(r % n), iy = (int)((r / n) % n), ix = (int)(r / ((size_t)n * n));
+  const long long sy = n, sx = (long long)n * n;
+  const T n1 = nb(xv, r, iz, n, 1, -1) + nb(xv, r, iz, n, 1, 1) + nb(xv, r, iy, n, sy, -1) +
+               nb(xv, r, iy, n, sy, 1) + nb(xv, r, ix, n, sx, -1) + nb(xv, r, ix, n, sx, 1);
+  const T n2 = nb(xv, r, iz, n, 1, -2) + nb(xv, r, iz, n, 1, 2) + nb(xv, r, iy, n, sy, -2) +
+               nb(xv, r, iy, n, sy, 2) + nb(xv, r, ix, n, sx, -2) + nb(xv, r, ix, n, sx, 2);
+  return c0 * xv[r] + c1 * n1 + c2 * n2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_fock_local(const T* __restrict__ x, int n, size_t ng,
+                                                   T c0, T c1, T c2, const T* __restrict__ vloc,
+                                                   int acc, T* __restrict__ y) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  const size_t off = (size_t)blockIdx.y * ng;
+  const T* xv = x + off;
+  T s = kinetic_at(xv, r, n, c0, c1, c2);
+  if (vloc) s += vloc[r] * xv[r];
+  if (acc) s += y[off + r];
+  y[off + r] = s;
+}
+
+// one damped-Jacobi step for (T + shift) z = r; first: z = r / (d + shift)
+template <typename T>
+__global__ __launch_bounds__(kT) void k_jacobi_sweep(const T* __restrict__ rr, const T* __restrict__ zin,
+                                                     T* __restrict__ zout, int n, size_t ng, T c0,
+                                                     T c1, T c2, T shift, T omega, int first) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  const size_t off = (size_t)blockIdx.y * ng;
+  const T inv = T(1) / (c0 + shift);
+  if (first) {
+    zout[off + r] = rr[off + r] * inv;
+    return;
+  }
+  const T* zv = zin + off;
+  const T az = kinetic_at(zv, r, n, c0, c1, c2) + shift * zv[r];
+  zout[off + r] = zv[r] + omega * (rr[off + r] - az) * inv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_density(const T* __restrict__ x, int k, size_t ng,
+                                                T* __restrict__ rho) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  T s = T(0);
+  for (int i = 0; i < k; ++i) {
+    const T v = x[(size_t)i * ng + r];
+    s += v * v;
+  }
+  rho[r] = T(2) * s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_axpby(const T* __restrict__ a, const T* __restrict__ b,
+                                              T alpha, T beta, size_t count, T* __restrict__ out) {
+  for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < count; e += (size_t)gridDim.x * kT)
+    out[e] = b ? alpha * a[e] + beta * b[e] : alpha * a[e];
+}
+
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_abs_part(const T* __restrict__ a, const T* __restrict__ b,
+                                                 size_t count, double* __restrict__ part) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < count; e += (size_t)gridDim.x * kT)
+    s += fabs((double)a[e] - (double)b[e]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_sum_parts(const double* __restrict__ part, int np,
+                                                  double scale, double* __restrict__ out) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += kT) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = scale * s;
+}
+
+// out_j(r) = sum_i C[i][j] V_i(r); coefficients staged in LDS in the grid precision
+template <typename T, int KO>
+__global__ __launch_bounds__(kT) void k_combine(const T* __restrict__ V, int mb, size_t ng,
+                                                const double* __restrict__ C, int ldc, int kout,
+                                                T* __restrict__ out) {
+  __shared__ T cs[kCombineMax * KO];
+  for (int t = threadIdx.x; t < mb * KO; t += kT) {
+    const int i = t / KO, j = t % KO;
+    cs[t] = j < kout ? (T)C[(size_t)i * ldc + j] : T(0);
+  }
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  T acc[KO];
+#pragma unroll
+  for (int j = 0; j < KO; ++j) acc[j] = T(0);
+  int i = 0;
+  for (; i + 4 <= mb; i += 4) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = V[(size_t)(i + u) * ng + r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < KO; ++j) acc[j] += cs[(i + u) * KO + j] * v[u];
+  }
+  for (; i < mb; ++i) {
+    const T v = V[(size_t)i * ng + r];
+#pragma unroll
+    for (int j = 0; j < KO; ++j) acc[j] += cs[i * KO + j] * v;
+  }
+#pragma unroll
+  for (int j = 0; j < KO; ++j)
+    if (j < kout) out[(size_t)j * ng + r] = acc[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_residual_grid(const T* __restrict__ X, const T* __restrict__ HX,
+                                                      const double* __restrict__ lam, size_t ng,
+                                                      T* __restrict__ R) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  const size_t off = (size_t)blockIdx.y * ng + r;
+  R[off] = HX[off] - (T)lam[blockIdx.y] * X[off];
+}
+
+constexpr int kPVB = 16;  // vectors per block of the complement projection
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kT) void k_project_complement(const T* __restrict__ phi, int k,
+                                                           const double* __restrict__ z, int nv,
+                                                           size_t ng, T* __restrict__ io) {
+  __shared__ T zs[KMAX * kPVB];
+  const int v0 = blockIdx.y * kPVB;
+  for (int t = threadIdx.x; t < k * kPVB; t += kT) {
+    const int i = t / kPVB, vb = t % kPVB;
+    zs[t] = (v0 + vb < nv) ? (T)z[(size_t)i * nv + v0 + vb] : T(0);
+  }
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  T p[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) p[i] = phi[(size_t)(i < k ? i : k - 1) * ng + r];
+  for (int vb = 0; vb < kPVB && v0 + vb < nv; ++vb) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < k) s += p[i] * zs[i * kPVB + vb];
+    const size_t o = (size_t)(v0 + vb) * ng + r;
+    io[o] = s - io[o];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scale_to_f32(const T* __restrict__ src,
+                                                     const double* __restrict__ scale, size_t ng,
+                                                     float* __restrict__ dst) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  const size_t o = (size_t)blockIdx.y * ng + r;
+  dst[o] = (float)((double)src[o] * scale[blockIdx.y]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_fill(T value, size_t count, T* __restrict__ dst) {
+  for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < count; e += (size_t)gridDim.x * kT)
+    dst[e] = value;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_from_f32(const float* __restrict__ src, size_t count,
+                                                 T* __restrict__ dst) {
+  for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < count; e += (size_t)gridDim.x * kT)
+    dst[e] = (T)src[e];
+}
+
+__global__ void k_inv_rms(const double* __restrict__ G, int ld, int nv, double ng,
+                          double* __restrict__ scale) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) scale[v] = 1.0 / sqrt(fmax(G[(size_t)v * ld + v] / ng, 1e-300));
+}
+
+// ---- one-workgroup FP64 steps ----
+
+__global__ __launch_bounds__(kT) void k_sym_scale(const double* __restrict__ S,
+                                                  const double* __restrict__ G, int m,
+                                                  double* __restrict__ Ss, double* __restrict__ Gs,
+                                                  double* __restrict__ D) {
+  __shared__ double d[kCombineMax];
+  for (int i = threadIdx.x; i < m; i += kT) {
+    const double sii = S[(size_t)i * m + i];
+    d[i] = sii > 0.0 ? 1.0 / sqrt(sii) : 0.0;
+    D[i] = d[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += kT) {
+    const int i = e / m, j = e % m;
+    const double f = d[i] * d[j];
+    Ss[e] = 0.5 * (S[e] + S[(size_t)j * m + i]) * f;
+    Gs[e] = 0.5 * (G[e] + G[(size_t)j * m + i]) * f;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_canon(const double* __restrict__ w,
+                                              const double* __restrict__ U, int m, double rel,
+                                              double* __restrict__ T) {
+  const double wmax = w[m - 1];
+  for (int e = threadIdx.x; e < m * m; e += kT) {
+    const int j = e % m;
+    const double wj = w[j];
+    T[e] = (wj > rel * wmax && wj > 0.0) ? U[e] / sqrt(wj) : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_drop_diag(double* __restrict__ A, int m,
+                                                  const double* __restrict__ w, double rel) {
+  __shared__ double red[kT];
+  double rowmax = 0.0;
+  for (int i = threadIdx.x; i < m; i += kT) {
+    double s = 0.0;
+    for (int l = 0; l < m; ++l) s += fabs(A[(size_t)i * m + l]);
+    rowmax = fmax(rowmax, s);
+  }
+  red[threadIdx.x] = rowmax;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double bound = 1.0 + red[0];
+  const double wmax = w[m - 1];
+  for (int j = threadIdx.x; j < m; j += kT)
+    if (!(w[j] > rel * wmax && w[j] > 0.0)) A[(size_t)j * m + j] = bound;
+}
+
+__global__ __launch_bounds__(kT) void k_inv_sqrt_eig(const double* __restrict__ w,
+                                                     const double* __restrict__ U, int m,
+                                                     double* __restrict__ out) {
+  __shared__ double f[kCombineMax];
+  for (int k = threadIdx.x; k < m; k += kT) f[k] = w[k] > 0.0 ? 1.0 / sqrt(w[k]) : 0.0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += kT) {
+    const int i = e / m, j = e % m;
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += U[(size_t)i * m + k] * f[k] * U[(size_t)j * m + k];
+    out[e] = s;
+  }
+}
+
+__global__ void k_scale_coeff_rows(double* __restrict__ C, int ldc, const double* __restrict__ D,
+                                   int m, int k) {
+  for (int e = threadIdx.x; e < m * k; e += blockDim.x) C[(size_t)(e / k) * ldc + e % k] *= D[e / k];
+}
+
+__global__ void k_zero_rows(double* __restrict__ C, int ldc, int r, int k) {
+  for (int e = threadIdx.x; e < r * k; e += blockDim.x) C[(size_t)(e / k) * ldc + e % k] = 0.0;
+}
+
+__global__ void k_diag(const double* __restrict__ A, int ld, int m, double* __restrict__ out) {
+  for (int j = threadIdx.x; j < m; j += blockDim.x) out[j] = A[(size_t)j * ld + j];
+}
+
+unsigned grid_blocks(size_t ng) { return (unsigned)((ng + kT - 1) / kT); }
+
+}  // namespace
+
+void launch_fock_local(bool fp64, const void* x, int nv, int n, double h, const void* vloc,
+                       int acc, void* y, hipStream_t s) {
+  const size_t ng = (size_t)n * n * n;
+  const Fd4 f(h);
+  dim3 grid(grid_blocks(ng), nv);
+  if (fp64)
+    k_fock_local<double><<<grid, kT, 0, s>>>((const double*)x, n, ng, f.c0, f.c1, f.c2,
+                                             (const double*)vloc, acc, (double*)y);
+  else
+    k_fock_local<float><<<grid, kT, 0, s>>>((const float*)x, n, ng, (float)f.c0, (float)f.c1,
+                                            (float)f.c2, (const float*)vloc, acc, (float*)y);
+}
+
+void launch_precond_kinetic(bool fp64, const void* r, int nv, int n, double h, double shift,
+                            int sweeps, double omega, void* z, void* tmp, hipStream_t s) {
+  const size_t ng = (size_t)n * n * n;
+  const Fd4 f(h);
+  dim3 grid(grid_blocks(ng), nv);
+  // the last sweep must land in z: start in z if the number of later sweeps is even
+  void* bufs[2] = {z, tmp};
+  int cur = ((sweeps - 1) % 2 == 0) ? 0 : 1;
+  for (int t = 0; t < sweeps; ++t) {
+    const void* zin = bufs[cur];
+    void* zout = t == 0 ? bufs[cur] : bufs[cur ^ 1];
+    if (t > 0) cur ^= 1;
+    if (fp64)
+      k_jacobi_sweep<double><<<grid, kT, 0, s>>>((const double*)r, (const double*)zin,
+                                                 (double*)zout, n, ng, f.c0, f.c1, f.c2, shift,
+                                                 omega, t == 0);
+    else
+      k_jacobi_sweep<float><<<grid, kT, 0, s>>>((const float*)r, (const float*)zin, (float*)zout,
+                                                n, ng, (float)f.c0, (float)f.c1, (float)f.c2,
+                                                (float)shift, (float)omega, t == 0);
+  }
+}
+
+void launch_density(bool fp64, const void* x, int k, size_t ng, void* rho, hipStream_t s) {
+  if (fp64)
+    k_density<double><<<grid_blocks(ng), kT, 0, s>>>((const double*)x, k, ng, (double*)rho);
+  else
+    k_density<float><<<grid_blocks(ng), kT, 0, s>>>((const float*)x, k, ng, (float*)rho);
+}
+
+void launch_axpby(bool fp64, const void* a, const void* b, double alpha, double beta,
+                  size_t count, void* out, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<size_t>(4096, (count + kT - 1) / kT);
+  if (fp64)
+    k_axpby<double><<<nb, kT, 0, s>>>((const double*)a, (const double*)b, alpha, beta, count,
+                                      (double*)out);
+  else
+    k_axpby<float><<<nb, kT, 0, s>>>((const float*)a, (const float*)b, (float)alpha, (float)beta,
+                                     count, (float*)out);
+}
+
+void launch_abs_diff_sum(bool fp64, const void* a, const void* b, size_t count, double scale,
+                         double* part, double* out, hipStream_t s) {
+  if (fp64)
+    k_abs_part<double><<<kAbsParts, kT, 0, s>>>((const double*)a, (const double*)b, count, part);
+  else
+    k_abs_part<float><<<kAbsParts, kT, 0, s>>>((const float*)a, (const float*)b, count, part);
+  k_sum_parts<<<1, kT, 0, s>>>(part, kAbsParts, scale, out);
+}
+
+template <typename T>
+static void combine_impl(const void* V, int mb, size_t ng, const double* C, int ldc, int kout,
+                         void* out, hipStream_t s) {
+  const unsigned g = grid_blocks(ng);
+  if (kout <= 8)
+    k_combine<T, 8><<<g, kT, 0, s>>>((const T*)V, mb, ng, C, ldc, kout, (T*)out);
+  else if (kout <= 16)
+    k_combine<T, 16><<<g, kT, 0, s>>>((const T*)V, mb, ng, C, ldc, kout, (T*)out);
+  else
+    k_combine<T, 32><<<g, kT, 0, s>>>((const T*)V, mb, ng, C, ldc, kout, (T*)out);
+}
+
+void launch_combine(bool fp64, const void* V, int mb, size_t ng, const double* C, int ldc,
+                    int kout, void* out, hipStream_t s) {
+  if (fp64)
+    combine_impl<double>(V, mb, ng, C, ldc, kout, out, s);
+  else
+    combine_impl<float>(V, mb, ng, C, ldc, kout, out, s);
+}
+
+void launch_residual_grid(bool fp64, const void* X, const void* HX, const double* lam, int k,
+                          size_t ng, void* R, hipStream_t s) {
+  dim3 grid(grid_blocks(ng), k);
+  if (fp64)
+    k_residual_grid<double><<<grid, kT, 0, s>>>((const double*)X, (const double*)HX, lam, ng,
+                                                (double*)R);
+  else
+    k_residual_grid<float><<<grid, kT, 0, s>>>((const float*)X, (const float*)HX, lam, ng,
+                                               (float*)R);
+}
+
+void launch_project_complement(bool fp64, const void* phi, int k, const double* z, int nv,
+                               size_t ng, void* inout, hipStream_t s) {
+  dim3 grid(grid_blocks(ng), (nv + kPVB - 1) / kPVB);
+  if (fp64) {
+    if (k <= 16)
+      k_project_complement<double, 16><<<grid, kT, 0, s>>>((const double*)phi, k, z, nv, ng,
+                                                           (double*)inout);
+    else
+      k_project_complement<double, 32><<<grid, kT, 0, s>>>((const double*)phi, k, z, nv, ng,
+                                                           (double*)inout);
+  } else {
+    if (k <= 16)
+      k_project_complement<float, 16><<<grid, kT, 0, s>>>((const float*)phi, k, z, nv, ng,
+                                                          (float*)inout);
+    else
+      k_project_complement<float, 32><<<grid, kT, 0, s>>>((const float*)phi, k, z, nv, ng,
+                                                          (float*)inout);
+  }
+}
+
+void launch_scale_to_f32(bool fp64, const void* src, const double* scale, int nv, size_t ng,
+                         float* dst, hipStream_t s) {
+  dim3 grid(grid_blocks(ng), nv);
+  if (fp64)
+    k_scale_to_f32<double><<<grid, kT, 0, s>>>((const double*)src, scale, ng, dst);
+  else
+    k_scale_to_f32<float><<<grid, kT, 0, s>>>((const float*)src, scale, ng, dst);
+}
+
+void launch_fill(bool fp64, double value, size_t count, void* dst, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<size_t>(4096, (count + kT - 1) / kT);
+  if (fp64)
+    k_fill<double><<<nb, kT, 0, s>>>(value, count, (double*)dst);
+  else
+    k_fill<float><<<nb, kT, 0, s>>>((float)value, count, (float*)dst);
+}
+
+void launch_from_f32(bool fp64, const float* src, size_t count, void* dst, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<size_t>(4096, (count + kT - 1) / kT);
+  if (fp64)
+    k_from_f32<double><<<nb, kT, 0, s>>>(src, count, (double*)dst);
+  else
+    k_from_f32<float><<<nb, kT, 0, s>>>(src, count, (float*)dst);
+}
+
+void launch_inv_rms(const double* G, int ld, int nv, double ng, double* scale, hipStream_t s) {
+  k_inv_rms<<<(nv + 63) / 64, 64, 0, s>>>(G, ld, nv, ng, scale);
+}
+
+void launch_sym_scale(const double* S, const double* G, int m, double* Ss, double* Gs,
+                      double* D, hipStream_t s) {
+  k_sym_scale<<<1, kT, 0, s>>>(S, G, m, Ss, Gs, D);
+}
+
+void launch_canon(const double* w, const double* U, int m, double rel, double* T, hipStream_t s) {
+  k_canon<<<1, kT, 0, s>>>(w, U, m, rel, T);
+}
+
+void launch_drop_diag(double* A, int m, const double* w, double rel, hipStream_t s) {
+  k_drop_diag<<<1, kT, 0, s>>>(A, m, w, rel);
+}
+
+void launch_inv_sqrt_from_eig(const double* w, const double* U, int m, double* out,
+                              hipStream_t s) {
+  k_inv_sqrt_eig<<<1, kT, 0, s>>>(w, U, m, out);
+}
+
+void launch_scale_coeff_rows(double* C, int ldc, const double* D, int m, int k, hipStream_t s) {
+  k_scale_coeff_rows<<<1, kT, 0, s>>>(C, ldc, D, m, k);
+}
+
+void launch_zero_rows(double* C, int ldc, int r, int k, hipStream_t s) {
+  if (r > 0) k_zero_rows<<<1, kT, 0, s>>>(C, ldc, r, k);
+}
+
+void launch_diag(const double* A, int ld, int m, double* out, hipStream_t s) {
+  k_diag<<<1, 64, 0, s>>>(A, ld, m, out);
+}
+
+}  // namespace ace

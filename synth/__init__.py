@@ -165,3 +165,69 @@ def small_real(seed, n, h, n_occ, n_virt):
     eps_occ = np.sort(rng.uniform(-1.5, -1.0, size=n_occ))
     eps_virt = np.sort(rng.uniform(0.0, 0.5, size=n_virt))
     return Molecule(n, h, occ, None, virt, eps_occ, eps_virt)
+
+
+# ---- synthetic closed-shell systems for the SCF (no pseudopotentials are available) ----------
+
+@dataclass
+class ScfSystem:
+    n: int
+    h: float
+    centres: np.ndarray        # (atoms, 3) bohr
+    charges: np.ndarray        # (atoms,)
+    sigma: float               # smearing length of the soft nuclei, bohr
+    v_ext: np.ndarray          # (n, n, n) float64 local potential
+    guess: np.ndarray          # (k, n, n, n) float64 orthonormal starting orbitals
+    meta: dict = field(default_factory=dict)
+
+
+def soft_coulomb(n, h, centres, charges, sigma):
+    """V(r) = -sum_A Z_A erf(|r - R_A| / sigma) / |r - R_A|, the value -2 Z_A / (sigma sqrt pi)
+    at r = R_A: the synthetic nuclei of the SCF inputs."""
+    from scipy.special import erf
+    x = coords(n, h)
+    v = np.zeros((n, n, n))
+    for c, z in zip(centres, charges):
+        r = np.sqrt((x - c[0])[:, None, None] ** 2 + (x - c[1])[None, :, None] ** 2
+                    + (x - c[2])[None, None, :] ** 2)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            val = erf(r / sigma) / r
+        val[r == 0] = 2.0 / (sigma * np.sqrt(np.pi))
+        v -= z * val
+    return v
+
+
+def scf_system(seed, n, h, k, centres=None, charges=None, n_atoms=4, sigma=0.6, span=None,
+               min_sep=1.2):
+    """A neutral closed-shell system with k doubly occupied orbitals: soft nuclei (charges
+    summing to 2k) and a Gaussian s/p starting guess centred on them (orthonormalised)."""
+    rng = np.random.default_rng(seed)
+    if centres is None:
+        span = 0.18 * n * h if span is None else span
+        pts = []
+        while len(pts) < n_atoms:
+            p = rng.uniform(-span, span, size=3)
+            if all(np.linalg.norm(p - q) >= min_sep for q in pts):
+                pts.append(p)
+        centres = np.array(pts)
+        base = np.full(n_atoms, (2 * k) // n_atoms, dtype=float)
+        base[: (2 * k) % n_atoms] += 1.0
+        charges = base
+    centres = np.asarray(centres, dtype=float)
+    charges = np.asarray(charges, dtype=float)
+    v = soft_coulomb(n, h, centres, charges, sigma)
+    guess = gaussian_orbitals(rng, n, h, k, (0.6, 1.5), list(centres), False)
+    return ScfSystem(n, h, centres, charges, sigma, v, guess)
+
+
+def scf_small(seed=201):
+    """16^3, h 0.4: two soft nuclei of charge 3 (4 electrons, 2 orbitals)."""
+    return scf_system(seed, 16, 0.4, 2, centres=[(-0.6, 0.0, 0.0), (0.6, 0.2, 0.0)],
+                      charges=[3.0, 3.0], sigma=0.8)
+
+
+def config5(seed=105, n=64, h=0.2, k=16, n_atoms=8):
+    """64^3, h 0.2, 16 doubly occupied orbitals on 8 soft nuclei of charge 4 (C5)."""
+    s = scf_system(seed, n, h, k, n_atoms=n_atoms, sigma=0.5, span=2.6, min_sep=1.6)
+    s.meta["name"] = "C5"
+    return s

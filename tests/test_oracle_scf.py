@@ -124,3 +124,41 @@ def test_conv_gradients_finite_difference():
     pm = list(params); pm[1] = (params[1][0], bm)
     num = (convnet.loss(convnet.forward(pp, x)[0], t) - convnet.loss(convnet.forward(pm, x)[0], t)) / (2 * eps)
     assert grads[1][1][3] == pytest.approx(num, rel=1e-5, abs=1e-10)
+
+
+def test_kinetic_precondition_converges_to_shifted_solve():
+    n, h, shift = 12, 0.5, 1.0
+    # the diagonal used by the preconditioner is the operator's own diagonal element
+    delta = np.zeros((n, n, n))
+    delta[6, 5, 4] = 1.0
+    assert scf.kinetic(delta, h)[6, 5, 4] == pytest.approx(scf.kinetic_diagonal(h), rel=1e-14)
+    rng = np.random.default_rng(3)
+    r = rng.normal(size=(n, n, n))
+    z = scf.kinetic_precondition(r, h, shift, 3000, 0.8)
+    res = scf.kinetic(z, h) + shift * z - r
+    assert np.max(np.abs(res)) < 1e-8 * np.max(np.abs(r))
+    # one sweep: the diagonal (Jacobi) scaling alone
+    assert np.allclose(scf.kinetic_precondition(r, h, shift, 1, 0.8),
+                       r / (scf.kinetic_diagonal(h) + shift), rtol=0, atol=0)
+
+
+def test_adam_constant_gradient_moves_by_lr_sign():
+    # with a constant gradient the bias-corrected moments are g and g^2 exactly, so every
+    # step moves each parameter by lr * g / (|g| + eps)
+    g = [np.array([2.0, -0.5, 1e-3]), np.array([[-3.0]])]
+    p = [np.zeros(3), np.zeros((1, 1))]
+    st = {}
+    for _ in range(5):
+        p = convnet.adam_step(p, g, st, lr=0.01)
+    assert np.allclose(p[0], -5 * 0.01 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-12)
+    assert np.allclose(p[1], [[0.05]], rtol=1e-12)
+
+
+def test_param_flatten_roundtrip_and_count():
+    rng = np.random.default_rng(5)
+    params = convnet.init_params(rng)
+    vec = convnet.flatten(params)
+    assert vec.size == 2177
+    back = convnet.unflatten(vec)
+    for (w, b), (w2, b2) in zip(params, back):
+        assert np.array_equal(w, w2) and np.array_equal(b, b2)
