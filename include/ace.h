@@ -298,6 +298,9 @@ int convnet_train(ace_convnet* net, int n, const float* inputs, const float* tar
                   double* loss_hist);
 
 /* ---- block eigensolver and SCF -------------------------------------------------------- */
+/* Preconditioners: NONE (residuals as they are), KINETIC (see kinetic_precondition), NET (the
+ * network's output on the RMS-normalised residuals as a block of its own beside the kinetic
+ * block, so the kinetic directions remain available as the fallback; needs 3k <= 64). */
 enum { ACE_PRECOND_NONE = 0, ACE_PRECOND_KINETIC = 1, ACE_PRECOND_NET = 2 };
 
 typedef struct ace_eig_opts {
@@ -312,8 +315,9 @@ typedef struct ace_eig_opts {
 
 /*
  * k lowest eigenpairs of F = T + v_local (+ K_ACE with nxi vectors xi, Eq. (13), if nxi > 0)
- * by LOBPCG: Rayleigh-Ritz over [X, M R, P] (current vectors, preconditioned residuals,
- * previous directions; P is left out when 3k > 64), canonical orthonormalisation in FP64.
+ * by LOBPCG: Rayleigh-Ritz over [X, M R, P] (current vectors, preconditioned residuals --
+ * two blocks with ACE_PRECOND_NET --, previous directions; P is left out when the order would
+ * pass 64), canonical orthonormalisation in FP64.
  * The non-self-consistent run with a fixed Hamiltonian of Sec. 3.1.
  * phi: k start vectors, overwritten by the Ritz vectors (dV-orthonormal); eigval, resnorm
  * (host, k, may be NULL); *steps (host, may be NULL) = steps taken.  Synchronises.

@@ -15,7 +15,7 @@ Hamiltonian uses these readings (the same ones the GPU driver uses):
 * E = 2 sum_i <phi_i| T + V_ext |phi_i> + 1/2 int rho v_H + sum_i <phi_i|K|phi_i>.
 
 The solver: each iteration diagonalises the Fock operator built from the current orbitals
-(Lanczos, scipy ``eigsh``), rotates the new occupied set to the old one (orthogonal Procrustes,
+(Lanczos, scipy ``eigsh``, from a fixed random start vector), rotates the new occupied set to the old one (orthogonal Procrustes,
 so that states can be mixed), mixes q_{N+1} = alpha q_{N-1} + (1 - alpha) q_N, re-orthonormalises
 (Loewdin) and stops when the relative density error (Eq. (15)) falls below ``tol``.
 
@@ -144,12 +144,14 @@ def scf(phi0, v_ext, h, alpha=0.3, tol=1e-9, max_iter=200):
     dv = h ** 3
     ne = 2.0 * k
     phi = loewdin(phi0, h)
+    # Krylov start with no spatial symmetry (a symmetric start would confine Lanczos to one
+    # symmetry sector of the Fock operator and could miss lower states of another)
+    v0 = np.random.default_rng(12345).normal(size=n ** 3)
     hist = []
     for it in range(max_iter):
         rho_in = density(phi)
         vloc = v_ext + poisson.fft(rho_in, h, khat)
-        w, new = lowest_states(lambda f: fock_apply(f, phi, vloc, h, khat), n, k, h,
-                               v0=phi[0].reshape(-1))
+        w, new = lowest_states(lambda f: fock_apply(f, phi, vloc, h, khat), n, k, h, v0=v0)
         # rotate the new occupied set onto the old one (orthogonal Procrustes), then mix
         ov = (new.reshape(k, -1) @ phi.reshape(k, -1).T) * dv
         u, _, vt = np.linalg.svd(ov)

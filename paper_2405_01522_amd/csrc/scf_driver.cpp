@@ -65,7 +65,7 @@ struct Eig {
   ace_ctx* c = nullptr;
   bool fp64 = false;
   size_t ng = 0, eb = 0;
-  int n = 0, k = 0, mmax = 0;
+  int n = 0, k = 0, mmax = 0, nw = 1;
   double h = 0, dv = 0;
   hipStream_t s = nullptr;
   Mem V, HV, V2, HV2, R, tmp, nin, nout;
@@ -82,7 +82,13 @@ struct Eig {
     dv = h * h * h;
     eb = fp64 ? 8 : 4;
     s = c->stream;
-    mmax = (3 * k <= kCombineMax && 3 * k <= kJacobiMax) ? 3 * k : 2 * k;
+    // basis blocks: X, one preconditioned-residual block per preconditioner (the learned
+    // one is used beside the kinetic one, which stays as the fallback direction), and the
+    // previous search directions P when the Rayleigh-Ritz order allows
+    nw = want_net ? 2 : 1;
+    const int lim = std::min(kCombineMax, kJacobiMax);
+    if ((1 + nw) * k > lim) return ACE_ERR_UNSUPPORTED;
+    mmax = (2 + nw) * k <= lim ? (2 + nw) * k : (1 + nw) * k;
     const size_t vec = eb * ng;
     int rc = ACE_OK;
     for (Mem* m : {&V, &HV, &V2, &HV2})
@@ -140,24 +146,20 @@ struct Eig {
     launch_scale_coeff_rows(Cm.d(), k, D.d(), m, k, s);
   }
 
-  // z = M r for the k residuals in R (scale = inverse RMS of each residual)
+  // preconditioned residual blocks from the k residuals in R (scale = their inverse RMS):
+  // z[0:k] = kinetic (or plain copy), z[k:2k] = learned network when nw == 2
   int precondition(const ace_eig_opts* o, void* z) {
-    switch (o->precond) {
-      case ACE_PRECOND_NONE:
-        return hip_check(hipMemcpyAsync(z, R.p, eb * ng * k, hipMemcpyDeviceToDevice, s));
-      case ACE_PRECOND_KINETIC:
-        launch_precond_kinetic(fp64, R.p, k, n, h, o->shift, o->sweeps, o->omega, z, tmp.p, s);
-        return ACE_OK;
-      case ACE_PRECOND_NET: {
-        launch_scale_to_f32(fp64, R.p, scale.d(), k, ng, nin.f(), s);
-        float* y = fp64 ? nout.f() : (float*)z;
-        int rc = convnet_apply_internal(o->net, n, nin.f(), k, y, s);
-        if (rc) return rc;
-        if (fp64) launch_from_f32(true, nout.f(), ng * k, z, s);
-        return ACE_OK;
-      }
-    }
-    return ACE_ERR_INVALID;
+    if (o->precond == ACE_PRECOND_NONE)
+      return hip_check(hipMemcpyAsync(z, R.p, eb * ng * k, hipMemcpyDeviceToDevice, s));
+    launch_precond_kinetic(fp64, R.p, k, n, h, o->shift, o->sweeps, o->omega, z, tmp.p, s);
+    if (o->precond != ACE_PRECOND_NET) return ACE_OK;
+    void* zn = (char*)z + eb * ng * (size_t)k;
+    launch_scale_to_f32(fp64, R.p, scale.d(), k, ng, nin.f(), s);
+    float* y = fp64 ? nout.f() : (float*)zn;
+    int rc = convnet_apply_internal(o->net, n, nin.f(), k, y, s);
+    if (rc) return rc;
+    if (fp64) launch_from_f32(true, nout.f(), ng * k, zn, s);
+    return ACE_OK;
   }
 
   // residuals of the current Ritz pairs (V[0:k], th) into R; norms to h_rd (host, dV norm)
@@ -207,17 +209,18 @@ struct Eig {
       }
       if (*maxres < o->tol || steps >= o->max_steps) break;
       rc = precondition(o, vec(V, k));
-      if (!rc) rc = fock(vloc, xi, nxi, vec(V, k), k, vec(HV, k));
+      if (!rc) rc = fock(vloc, xi, nxi, vec(V, k), nw * k, vec(HV, k));
       if (rc) return rc;
-      const int m = (haveP && mmax == 3 * k) ? 3 * k : 2 * k;
+      const int pb = (1 + nw) * k;  // first vector of the P block
+      const int m = (haveP && mmax > pb) ? mmax : pb;
       gram(V.p, m, V.p, m, dv, S.d());
       gram(V.p, m, HV.p, m, dv, G.d());
       rr(m);
       launch_combine(fp64, V.p, m, ng, Cm.d(), k, k, V2.p, s);
       launch_combine(fp64, HV.p, m, ng, Cm.d(), k, k, HV2.p, s);
-      if (mmax == 3 * k) {  // new search directions: the non-X part of the update
-        launch_combine(fp64, vec(V, k), m - k, ng, Cm.d() + (size_t)k * k, k, k, vec(V2, 2 * k), s);
-        launch_combine(fp64, vec(HV, k), m - k, ng, Cm.d() + (size_t)k * k, k, k, vec(HV2, 2 * k), s);
+      if (mmax > pb) {  // new search directions: the non-X part of the update
+        launch_combine(fp64, vec(V, k), m - k, ng, Cm.d() + (size_t)k * k, k, k, vec(V2, pb), s);
+        launch_combine(fp64, vec(HV, k), m - k, ng, Cm.d() + (size_t)k * k, k, k, vec(HV2, pb), s);
         haveP = true;
       }
       std::swap(V.p, V2.p);
@@ -232,7 +235,7 @@ struct Eig {
 
 int check_eig_opts(const ace_ctx* c, const ace_eig_opts* o) {
   if (!o || o->max_steps < 0 || !(o->tol >= 0.0)) return ACE_ERR_INVALID;
-  if (o->precond == ACE_PRECOND_KINETIC &&
+  if (o->precond != ACE_PRECOND_NONE &&
       (o->sweeps < 1 || !(o->shift > -1e300) || !(o->omega > 0.0) || !(o->omega < 2.0)))
     return ACE_ERR_INVALID;
   if (o->precond == ACE_PRECOND_NET && !o->net) return ACE_ERR_INVALID;
