@@ -216,6 +216,124 @@ def run_tda(mol, steps, warmup):
                 kernel_ms={k: v[0] for k, v in kt.items()})
 
 
+def _scf_start(s, k, seed):
+    """Seeded random starting vectors (Gaussian envelope), orthonormalised in FP64."""
+    import synth
+    rng = np.random.default_rng(seed)
+    x = synth.coords(s.n, s.h)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    raw = rng.normal(size=(k, s.n, s.n, s.n)) * np.exp(-0.08 * r2)
+    return synth.mgs(raw, s.h ** 3)
+
+
+def run_scf(train_seeds=(1051, 1052, 1053, 1054, 1055), eval_seed=105, pairs=10000,
+            train_steps=2000, batch=8, lr=2e-3, oracle_check=True):
+    """C5: closed-shell HF SCF (64^3, h 0.2, 16 doubly occupied orbitals, ACE rebuilt every
+    iteration, states mixing 0.3, 3 LOBPCG steps per iteration) with the plain kinetic
+    preconditioner and with the learned network beside it, after training the network on
+    (residual, correction) pairs recorded from plain runs on other seeded systems."""
+    import torch
+    import paper_2405_01522_amd as ace
+    import synth
+
+    dev = torch.device("cuda", 0)
+    dt = torch.float32
+    k = 16
+    ctx = ace.AceContext(64, 0.2, dt, dev)
+    tensor = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)
+    eig_kin = ace.eig_opts(max_steps=3, tol=1e-4)
+    scf_kw = dict(alpha=0.3, tol=1e-6, max_iter=300)
+
+    def core(s, seed):
+        phi = tensor(_scf_start(s, k, seed))
+        ctx.fock_lowest_states(tensor(s.v_ext[None]), phi, opts=ace.eig_opts(max_steps=300, tol=1e-3))
+        return phi
+
+    # 1. training pairs from plain runs
+    per = pairs // len(train_seeds)
+    rin = torch.empty((per * len(train_seeds), 64, 64, 64), dtype=dt, device=dev)
+    rtg = torch.empty_like(rin)
+    count, runs = 0, []
+    t0 = time.perf_counter()
+    for seed in train_seeds:
+        s = synth.config5(seed)
+        phi = core(s, seed)
+        r = ctx.scf_run(tensor(s.v_ext[None]), phi, ace.scf_opts(eig=eig_kin, **scf_kw),
+                        record=(rin[count:count + per], rtg[count:count + per]), record_stride=4)
+        ctx.precond_targets(phi, rtg[count:count + r["rec_count"]], r["rec_count"])
+        count += r["rec_count"]
+        runs.append(dict(seed=seed, iterations=r["iterations"], converged=r["converged"],
+                         recorded=r["rec_count"]))
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    # 2. training (random minibatches with sign flips)
+    rng = np.random.default_rng(7)
+    init = np.concatenate([np.concatenate([rng.normal(scale=0.3 / np.sqrt(27 * ci), size=co * ci * 27),
+                                           np.zeros(co)]) for ci, co in ((1, 8), (8, 8), (8, 1))])
+    net = ace.ConvNet(init.astype(np.float32), dev)
+    t0 = time.perf_counter()
+    hist = net.train(rin[:count].contiguous() if count < rin.shape[0] else rin,
+                     rtg[:count].contiguous() if count < rtg.shape[0] else rtg,
+                     steps=train_steps, batch=batch, lr=lr, seed=11)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    y = net.forward(rin[:64].contiguous())
+    fit = float(((y - rtg[:64]) ** 2).sum() / (rtg[:64] ** 2).sum())
+    del rin, rtg
+    # 3. held-out system: SCF with each preconditioner from the same start
+    s = synth.config5(eval_seed)
+    v = tensor(s.v_ext[None])
+    start = core(s, eval_seed)
+    out = {}
+    finals = {}
+    for name, eo in (("kinetic", eig_kin),
+                     ("learned", ace.eig_opts(max_steps=3, tol=1e-4, precond="net", net=net))):
+        phi = start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.scf_run(v, phi, ace.scf_opts(eig=eo, **scf_kw))
+        torch.cuda.synchronize()
+        out[name] = dict(seconds=time.perf_counter() - t0, iterations=r["iterations"],
+                         eig_steps=r["eig_steps"], converged=r["converged"],
+                         energy=r["total"], terms={t: r[t] for t in ace.ENERGY_TERMS[1:]},
+                         density_error=r["density_error"])
+        finals[name] = phi
+    # 4. eigensolver alone on the converged Hamiltonian (non-self-consistent run): steps from
+    # the core guess to residuals below 1e-4 with each preconditioner
+    phi_c = finals["kinetic"]
+    vloc = v + ctx.hartree_potential(ctx.scf_density(phi_c))
+    xi, _, _ = ctx.ace_build(phi_c)
+    eig_only = {}
+    for name, eo in (("kinetic", ace.eig_opts(max_steps=500, tol=1e-4)),
+                     ("learned", ace.eig_opts(max_steps=500, tol=1e-4, precond="net", net=net))):
+        phi = start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, rn, st = ctx.fock_lowest_states(vloc, phi, xi=xi, opts=eo)
+        torch.cuda.synchronize()
+        eig_only[name] = dict(steps=st, seconds=time.perf_counter() - t0, max_residual=float(rn.max()))
+    res = dict(workload="C5: 64^3 box h=0.2 bohr, 16 doubly occupied orbitals, 8 soft nuclei "
+                        "(seed %d); ACE rebuilt each SCF iteration; states mixing 0.3; "
+                        "stop at density error 1e-6 and residuals 1e-4" % eval_seed,
+               dtype="f32 grid (FP64 Gram / Rayleigh-Ritz / Cholesky)",
+               training=dict(systems=runs, pairs=count, collect_s=t_collect, steps=train_steps,
+                             batch=batch, lr=lr, seconds=t_train, loss_first=float(hist[:10].mean()),
+                             loss_last=float(hist[-50:].mean()), rel_mse_first64=fit),
+               scf=out, eig_only_converged_hamiltonian=eig_only,
+               energy_diff_learned_vs_kinetic=abs(out["learned"]["energy"] - out["kinetic"]["energy"]))
+    if oracle_check:
+        from oracle import poisson, scf as oscf
+        p = finals["kinetic"].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        eo = oscf.energies(p, s.v_ext, s.h, poisson.kernel_hat(s.n, s.h))
+        res["oracle_energy_of_gpu_orbitals"] = dict(total=eo["total"],
+                                                    abs_diff=abs(eo["total"] - out["kinetic"]["energy"]),
+                                                    seconds=time.perf_counter() - t0)
+    net.close()
+    ctx.close()
+    return res
+
+
 def cpu_baseline(mol, budget_s=20.0):
     """The FP64 oracle, timed on the host cores on a bounded sample of the same workload:
     whole ACE builds (36 pair solves each) plus applications to the 32 vectors, repeated
@@ -254,6 +372,8 @@ def main(argv=None):
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-tda", action="store_true")
+    ap.add_argument("--no-scf", action="store_true")
+    ap.add_argument("--no-scf-oracle", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -327,6 +447,9 @@ def main(argv=None):
                                         "orbitals (seed 103); 512 ov + 136 oo pair solves, 512x512 "
                                         "singlet coupling block; one graph-captured call",
                             "dtype": "f32 (FP64 split-K sums)", **td}
+
+    if not a.no_scf:
+        out["scf_learned_preconditioner"] = run_scf(oracle_check=not a.no_scf_oracle)
 
     if not a.no_cpu_baseline:
         cb = cpu_baseline(mol)

@@ -338,6 +338,7 @@ typedef struct ace_scf_opts {
   float* rec_in;     /* optional (device, rec_cap volumes, ACE_R32 only): residuals / RMS */
   float* rec_tgt;    /* optional: the current vectors / RMS of their residuals */
   int rec_cap;
+  int rec_stride;    /* record the residual block of every rec_stride-th evaluation (>= 1) */
 } ace_scf_opts;
 
 typedef struct ace_scf_result {
@@ -364,8 +365,8 @@ int scf_run(ace_ctx* ctx, const void* v_ext, void* phi, int k, const ace_scf_opt
 
 /* Training targets of the learned preconditioner from converged orbitals phi (k):
  * tgt_v <- Phi (Phi^T tgt_v dV) - tgt_v for count FP32 volumes (ACE_R32 contexts), i.e.
- * the correction that takes a recorded vector onto the converged occupied space.
- * Synchronises. */
+ * the correction that takes a recorded vector onto the converged occupied space, then
+ * scaled to unit RMS (the eigensolver uses only its direction).  Synchronises. */
 int precond_targets(ace_ctx* ctx, const void* phi, int k, float* tgt, int count);
 
 /* Static message for a return code. */

@@ -90,7 +90,8 @@ class AceScfOpts(ctypes.Structure):
     """Mirror of ace_scf_opts."""
     _fields_ = [("eig", AceEigOpts), ("alpha", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("rec_in", ctypes.c_void_p),
-                ("rec_tgt", ctypes.c_void_p), ("rec_cap", ctypes.c_int)]
+                ("rec_tgt", ctypes.c_void_p), ("rec_cap", ctypes.c_int),
+                ("rec_stride", ctypes.c_int)]
 
 
 class AceScfResult(ctypes.Structure):

@@ -259,7 +259,7 @@ class AceContext:
                                  phi.shape[0], e.ctypes.data_as(ctypes.c_void_p)), "scf_energies")
         return dict(zip(ENERGY_TERMS, e.tolist()))
 
-    def scf_run(self, v_ext, phi, opts=None, record=None):
+    def scf_run(self, v_ext, phi, opts=None, record=None, record_stride=1):
         """Closed-shell HF SCF from phi (overwritten).  record: optional pair of FP32 GPU
         tensors (cap, N, N, N) receiving (normalised residual, normalised vector) pairs.
         Returns a dict with energies, eigenvalues, iterations, density-error history, ..."""
@@ -273,8 +273,9 @@ class AceContext:
                         tuple(t.shape[1:]) != (self.n,) * 3:
                     raise ValueError("record tensors must be contiguous FP32 (cap, N, N, N)")
             o.rec_in, o.rec_tgt, o.rec_cap = rin.data_ptr(), rtg.data_ptr(), min(rin.shape[0], rtg.shape[0])
+            o.rec_stride = int(record_stride)
         else:
-            o.rec_in, o.rec_tgt, o.rec_cap = None, None, 0
+            o.rec_in, o.rec_tgt, o.rec_cap, o.rec_stride = None, None, 0, 1
         res = AceScfResult()
         ev = np.zeros(k)
         hist = np.zeros(o.max_iter)
@@ -416,7 +417,7 @@ def eig_opts(max_steps=50, tol=1e-6, precond="kinetic", shift=1.0, sweeps=4, ome
 def scf_opts(alpha=0.3, tol=1e-6, max_iter=100, eig=None):
     """ace_scf_opts (states mixing alpha, Eq. (14); density error stop tol, Eq. (15))."""
     return AceScfOpts(eig if eig is not None else eig_opts(max_steps=3),
-                      float(alpha), float(tol), int(max_iter), None, None, 0)
+                      float(alpha), float(tol), int(max_iter), None, None, 0, 1)
 
 
 class ConvNet:

@@ -218,6 +218,15 @@ __global__ __launch_bounds__(kT) void k_scale_to_f32(const T* __restrict__ src,
 }
 
 template <typename T>
+__global__ __launch_bounds__(kT) void k_scale_inplace(T* __restrict__ x,
+                                                      const double* __restrict__ scale, size_t ng) {
+  const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
+  if (r >= ng) return;
+  const size_t o = (size_t)blockIdx.y * ng + r;
+  x[o] = (T)((double)x[o] * scale[blockIdx.y]);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kT) void k_fill(T value, size_t count, T* __restrict__ dst) {
   for (size_t e = (size_t)blockIdx.x * kT + threadIdx.x; e < count; e += (size_t)gridDim.x * kT)
     dst[e] = value;
@@ -441,6 +450,15 @@ void launch_scale_to_f32(bool fp64, const void* src, const double* scale, int nv
     k_scale_to_f32<double><<<grid, kT, 0, s>>>((const double*)src, scale, ng, dst);
   else
     k_scale_to_f32<float><<<grid, kT, 0, s>>>((const float*)src, scale, ng, dst);
+}
+
+void launch_scale_inplace(bool fp64, void* x, const double* scale, int nv, size_t ng,
+                          hipStream_t s) {
+  dim3 grid(grid_blocks(ng), nv);
+  if (fp64)
+    k_scale_inplace<double><<<grid, kT, 0, s>>>((double*)x, scale, ng);
+  else
+    k_scale_inplace<float><<<grid, kT, 0, s>>>((float*)x, scale, ng);
 }
 
 void launch_fill(bool fp64, double value, size_t count, void* dst, hipStream_t s) {

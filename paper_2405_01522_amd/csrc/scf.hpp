@@ -49,6 +49,9 @@ void launch_project_complement(bool fp64, const void* phi, int k, const double* 
 // dst_v = scale_v * src_v, converted to float (dst is always float); scale: nv doubles
 void launch_scale_to_f32(bool fp64, const void* src, const double* scale, int nv, size_t ng,
                          float* dst, hipStream_t s);
+// x_v *= scale_v in place (nv vectors of ng points)
+void launch_scale_inplace(bool fp64, void* x, const double* scale, int nv, size_t ng,
+                          hipStream_t s);
 // dst[e] = value for e < count
 void launch_fill(bool fp64, double value, size_t count, void* dst, hipStream_t s);
 // dst_v = src_v (float) converted to the grid precision

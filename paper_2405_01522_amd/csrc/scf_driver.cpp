@@ -58,6 +58,8 @@ struct Recorder {
   float* tgt = nullptr;
   int cap = 0;
   int count = 0;
+  int stride = 1;
+  long long tick = 0;  // residual evaluations seen
 };
 
 // Workspace and steps of the block eigensolver for k vectors.
@@ -201,7 +203,7 @@ struct Eig {
     for (;;) {
       rc = residuals(maxres);
       if (rc) return rc;
-      if (rec && rec->in && rec->count < rec->cap) {
+      if (rec && rec->in && rec->count < rec->cap && (rec->tick++ % rec->stride) == 0) {
         const int nr = std::min(k, rec->cap - rec->count);
         launch_scale_to_f32(fp64, R.p, scale.d(), nr, ng, rec->in + (size_t)rec->count * ng, s);
         launch_scale_to_f32(fp64, V.p, scale.d(), nr, ng, rec->tgt + (size_t)rec->count * ng, s);
@@ -389,7 +391,8 @@ int scf_run(ace_ctx* c, const void* v_ext, void* phi, int k, const ace_scf_opts*
   int rc = check_eig_opts(c, &o->eig);
   if (rc) return rc;
   const bool want_rec = o->rec_in || o->rec_tgt;
-  if (want_rec && (!o->rec_in || !o->rec_tgt || o->rec_cap < 1)) return ACE_ERR_INVALID;
+  if (want_rec && (!o->rec_in || !o->rec_tgt || o->rec_cap < 1 || o->rec_stride < 1))
+    return ACE_ERR_INVALID;
   if ((want_rec || o->eig.precond == ACE_PRECOND_NET) && c->dtype != ACE_R32)
     return ACE_ERR_UNSUPPORTED;
   *res = ace_scf_result{};
@@ -420,6 +423,7 @@ int scf_run(ace_ctx* c, const void* v_ext, void* phi, int k, const ace_scf_opts*
   rec.in = o->rec_in;
   rec.tgt = o->rec_tgt;
   rec.cap = o->rec_cap;
+  rec.stride = std::max(1, o->rec_stride);
   bool converged = false;
   int it = 0, eig_total = 0;
   double err = 0.0, maxres = 0.0;
@@ -496,9 +500,11 @@ int precond_targets(ace_ctx* c, const void* phi, int k, float* tgt, int count) {
   const int chunk = 64;
   size_t pts;
   const int nblk = gram_blocks(ng, &pts);
-  Mem part, z;
-  int rc = part.alloc(sizeof(double) * (size_t)nblk * k * chunk);
+  Mem part, z, g, sc;
+  int rc = part.alloc(sizeof(double) * (size_t)nblk * std::max(k, chunk) * chunk);
   if (!rc) rc = z.alloc(sizeof(double) * (size_t)k * chunk);
+  if (!rc) rc = g.alloc(sizeof(double) * (size_t)chunk * chunk);
+  if (!rc) rc = sc.alloc(sizeof(double) * (size_t)chunk);
   if (rc) return rc;
   const double dv = c->h * c->h * c->h;
   for (int v0 = 0; v0 < count; v0 += chunk) {
@@ -506,6 +512,10 @@ int precond_targets(ace_ctx* c, const void* phi, int k, float* tgt, int count) {
     float* t = tgt + (size_t)v0 * ng;
     launch_gram(ACE_R32, phi, k, t, cv, ng, part.p, dv, z.p, c->stream, nullptr);
     launch_project_complement(false, phi, k, z.d(), cv, ng, t, c->stream);
+    // unit RMS: only the direction of a correction matters to the eigensolver
+    launch_gram(ACE_R32, t, cv, t, cv, ng, part.p, 1.0, g.p, c->stream, nullptr);
+    launch_inv_rms(g.d(), cv, cv, (double)ng, sc.d(), c->stream);
+    launch_scale_inplace(false, t, sc.d(), cv, ng, c->stream);
   }
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
     return ACE_ERR_HIP;
