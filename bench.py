@@ -28,6 +28,10 @@ METRIC = "pair Poisson solves/s and ACE K*psi/s, mixed vs FP64 GPU at 1e-6 Ha"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of k_xy<float, 48> (36 pairs) from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00); valid for the
+# kernel as it stands (profiles/k_xy_c2_hbm_traffic.md)
+XY48_F32_TRAFFIC_BYTES = 2.00 * 32891 * 1024 + 1.00 * 62208 * 1024
 
 
 def xy_pass_flops(n):
@@ -374,6 +378,9 @@ def main(argv=None):
     ap.add_argument("--no-tda", action="store_true")
     ap.add_argument("--no-scf", action="store_true")
     ap.add_argument("--no-scf-oracle", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one plain 256 MiB device-to-device copy (hardware-counter "
+                         "calibration under rocprofv3 --pmc)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -429,17 +436,28 @@ def main(argv=None):
         achieved = flops / (avg_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": "k_xy<float,48>", "achieved": achieved,
                            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": XY48_F32_TRAFFIC_BYTES,
+                           "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
+                           "traffic_gbs": XY48_F32_TRAFFIC_BYTES / (avg_ms * 1e-3) / 1e9,
                            "avg_launch_ms": avg_ms,
                            "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * pairs_per_launch / (avg_ms * 1e-3) / 1e9}
         out["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in kt.items()}
         out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
 
     if not a.no_batched:
-        bt = run_batched(synth.config4(), torch.complex64, min(a.steps, 10), 2)
+        c4 = synth.config4()
+        bt = run_batched(c4, torch.complex64, min(a.steps, 10), 2)
         out["batched_uneven"] = {"workload": "64 systems, edges {32..64} step 8, h=0.25, 2-16 complex "
                                              "orbitals (seed 104), one graph-captured call",
                                  "dtype": "f32", **bt}
+        # FP64 storage fits the LDS plane only up to edge 48: the same batch without 56 and 64
+        sub = [m for m in c4 if m.n <= 48]
+        bt32 = run_batched(sub, torch.complex64, min(a.steps, 10), 2)
+        bt64 = run_batched(sub, torch.complex128, min(a.steps, 10), 2)
+        out["batched_uneven_edges_le_48"] = {
+            "workload": "the %d systems of that batch with edge <= 48" % len(sub),
+            "f32": bt32, "f64": bt64,
+            "speedup_f32_vs_f64": bt32["pair_solves_per_s"] / bt64["pair_solves_per_s"]}
 
     if not a.no_tda:
         td = run_tda(synth.config3(), min(a.steps, 10), 2)
@@ -463,6 +481,12 @@ def main(argv=None):
         scale = float(np.max(np.abs(ref)))
         out["kpsi_rel_error"] = {"mixed": float(np.max(np.abs(mixed["kpsi"] - ref)) / scale),
                                  "fp64": float(np.max(np.abs(fp64["kpsi"] - ref)) / scale)}
+    if a.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out))
     return 0
 
