@@ -208,6 +208,113 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   }
 }
 
+// Wide real Gram (both sides wider than one 16-row tile, at most 64 rows each): a workgroup
+// stages its chunk of kGramPoints points of every A and B row in LDS once, in passes of a
+// few dozen points (rows padded by one element against bank conflicts) and its four wavefronts compute all 16 x 16 output tiles
+// from there, so each input element is read from HBM once instead of once per tile.  Same
+// FP64 MFMA contraction and the same partial layout part[o][block] as k_gram.
+constexpr int kWideRows = 64;
+
+// NT tiles of one wavefront over one staged pass (unconditional, fully unrolled chains)
+template <typename E, int NT, int SC>
+__device__ __forceinline__ void wide_tiles(const E* la, const E* lb, int wave, int tb, int li,
+                                           int g, gf64x4* acc) {
+  constexpr int LD = SC + 1;
+  const E* pa[NT];
+  const E* pb[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int tile = wave + 4 * u;
+    pa[u] = la + ((tile / tb) * 16 + li) * LD + g;
+    pb[u] = lb + ((tile % tb) * 16 + li) * LD + g;
+  }
+  gf64x4 t[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) t[u] = acc[u];
+#pragma unroll 4
+  for (int q = 0; q < SC / 4; ++q)
+#pragma unroll
+    for (int u = 0; u < NT; ++u) t[u] = mma64((double)pa[u][4 * q], (double)pb[u][4 * q], t[u]);
+#pragma unroll
+  for (int u = 0; u < NT; ++u) acc[u] = t[u];
+}
+
+template <typename E, int NT>
+__device__ __forceinline__ void k_gram_wide_body(const E* __restrict__ A, int na,
+                                                 const E* __restrict__ B, int nb, size_t ng,
+                                                 double* __restrict__ part, E* la, E* lb) {
+  // points per pass: small enough (about 33 KiB of LDS) for several workgroups per CU
+  constexpr int SC = sizeof(E) == 4 ? kGramPoints / 4 : kGramPoints / 8;
+  constexpr int LD = SC + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int ta = (na + 15) / 16, tb = (nb + 15) / 16;
+  const int ra = ta * 16, rb = tb * 16;
+  gf64x4 acc[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) acc[u] = gf64x4{0.0, 0.0, 0.0, 0.0};
+  for (int pass = 0; pass < kGramPoints / SC; ++pass) {
+    const size_t p0 = (size_t)blockIdx.x * kGramPoints + (size_t)pass * SC;
+    // staging: eight unconditional (clamped) loads in flight per thread, then the stores
+    constexpr int U = 8;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const E* X = side ? B : A;
+      E* lx = side ? lb : la;
+      const int nx = side ? nb : na, rx = side ? rb : ra;
+      for (int base = 0; base < rx * SC; base += U * kThreads) {
+        E v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * kThreads + threadIdx.x;
+          const int row = e / SC, c = e % SC;
+          const bool ok = row < nx && p0 + c < ng && e < rx * SC;
+          v[u] = X[ok ? (size_t)row * ng + p0 + c : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = base + u * kThreads + threadIdx.x;
+          const int row = e / SC, c = e % SC;
+          const bool ok = row < nx && p0 + c < ng;
+          if (e < rx * SC) lx[row * LD + c] = ok ? v[u] : E(0);
+        }
+      }
+    }
+    __syncthreads();
+    wide_tiles<E, NT, SC>(la, lb, wave, tb, li, g, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int tile = wave + 4 * u;
+    const int k0 = (tile / tb) * 16, l0 = (tile % tb) * 16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + g + 4 * e, l = l0 + li;
+      if (k < na && l < nb) part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = acc[u][e];
+    }
+  }
+}
+
+template <typename E>
+__global__ __launch_bounds__(kThreads) void k_gram_wide(const E* __restrict__ A, int na,
+                                                        const E* __restrict__ B, int nb,
+                                                        size_t ng, double* __restrict__ part) {
+  constexpr int SC = sizeof(E) == 4 ? kGramPoints / 4 : kGramPoints / 8;
+  __shared__ E la[kWideRows * (SC + 1)];
+  __shared__ E lb[kWideRows * (SC + 1)];
+  const int wave = threadIdx.x >> 6;
+  const int ntile = ((na + 15) / 16) * ((nb + 15) / 16);
+  const int nt = (ntile - wave + 3) / 4;  // tiles of this wavefront (uniform), 1..4
+  // every wavefront takes part in the staging barriers whatever its tile count
+  switch (nt) {
+    case 4: k_gram_wide_body<E, 4>(A, na, B, nb, ng, part, la, lb); break;
+    case 3: k_gram_wide_body<E, 3>(A, na, B, nb, ng, part, la, lb); break;
+    case 2: k_gram_wide_body<E, 2>(A, na, B, nb, ng, part, la, lb); break;
+    default: k_gram_wide_body<E, 1>(A, na, B, nb, ng, part, la, lb); break;
+  }
+}
+
 // out[o] = scale * sum_b part[o][b]: one block per output, fixed-order tree.
 template <typename W, typename S>
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale) {
@@ -509,6 +616,21 @@ void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void*
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
                  double scale, void* out, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_GRAM);
+  if ((et == ET_R32 || et == ET_R64) && na > 16 && nb > 16 && na <= kWideRows &&
+      nb <= kWideRows) {
+    size_t chunk;
+    const int nch = gram_blocks(ng, &chunk);
+    if (et == ET_R32)
+      k_gram_wide<float><<<nch, kThreads, 0, s>>>((const float*)A, na, (const float*)B, nb, ng,
+                                                  (double*)part);
+    else
+      k_gram_wide<double><<<nch, kThreads, 0, s>>>((const double*)A, na, (const double*)B, nb,
+                                                   ng, (double*)part);
+    OneRed sr{RedArgs{part, na * nb, out}};
+    dim3 rg(na * nb, 1);
+    k_gram_reduce<double, OneRed><<<rg, kThreads, 0, s>>>(sr, nch, scale);
+    return;
+  }
   OneGram sg{GramArgs{A, na, B, nb, part}};
   OneRed sr{RedArgs{part, na * nb, out}};
   by_elem<GramRun>(et, sg, sr, ((na + 15) / 16) * ((nb + 15) / 16), na * nb, 1, ng, scale, s);

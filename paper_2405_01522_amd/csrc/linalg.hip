@@ -61,22 +61,41 @@ __global__ __launch_bounds__(256) void k_dgemm(int ta, int tb, int M, int N, int
 }
 
 // Symmetric eigendecomposition by the cyclic Jacobi method in round-robin (tournament)
-// order: each round rotates n/2 disjoint index pairs at once (row rotations, barrier, column
-// rotations).  One workgroup; matrix and eigenvectors in LDS.  Output: w ascending,
-// V[i][k] = component i of eigenvector k (row-major, leading dimension ldv).
+// order: each round rotates n/2 disjoint index pairs at once.  The rotations of a round are
+// computed once (one thread per pair); the two-sided update is then one pass over 2x2 blocks:
+// the block (rows of pair k, columns of pair l) becomes R_k B R_l^T with R = [[c, -s], [s, c]],
+// and the eigenvector columns of each pair rotate.  One workgroup; matrix and eigenvectors in
+// LDS.  Output: w ascending, V[i][k] = component i of eigenvector k (row-major, leading
+// dimension ldv).
 constexpr int JMAX = 64;
+constexpr int JT = 512;
 
-__global__ __launch_bounds__(256) void k_jacobi(int n, const double* __restrict__ Ain, int lda,
-                                                double* __restrict__ w, double* __restrict__ V,
-                                                int ldv, int max_sweeps, double tol) {
+// 1 / x and 1 / sqrt(x) in FP64 from the hardware estimates plus two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return r;
+}
+
+__global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__ Ain, int lda,
+                                               double* __restrict__ w, double* __restrict__ V,
+                                               int ldv, int max_sweeps, double tol) {
   __shared__ double a[JMAX][JMAX + 1];
   __shared__ double v[JMAX][JMAX + 1];
   __shared__ double cs[JMAX / 2], sn[JMAX / 2];
   __shared__ int pp[JMAX / 2], qq[JMAX / 2];
-  __shared__ double red[256];
+  __shared__ double red[2][JT];
   __shared__ int rank_s[JMAX];
   const int m = n + (n & 1);  // even order; a padding index acts as an isolated zero row
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+  const int h = m / 2;
+  for (int e = threadIdx.x; e < m * m; e += JT) {
     const int i = e / m, j = e % m;
     double x = 0.0;
     if (i < n && j < n) x = 0.5 * (Ain[(size_t)i * lda + j] + Ain[(size_t)j * lda + i]);
@@ -85,34 +104,29 @@ __global__ __launch_bounds__(256) void k_jacobi(int n, const double* __restrict_
   }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // off-diagonal and total norms
     double off = 0.0, tot = 0.0;
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    for (int e = threadIdx.x; e < m * m; e += JT) {
       const int i = e / m, j = e % m;
       const double x = a[i][j] * a[i][j];
       tot += x;
       if (i != j) off += x;
     }
-    red[threadIdx.x] = off;
+    red[0][threadIdx.x] = off;
+    red[1][threadIdx.x] = tot;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = JT / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + st];
+        red[1][threadIdx.x] += red[1][threadIdx.x + st];
+      }
       __syncthreads();
     }
-    const double offn = red[0];
-    __syncthreads();
-    red[threadIdx.x] = tot;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    const double totn = red[0];
+    const double offn = red[0][0], totn = red[1][0];
     __syncthreads();
     if (offn <= tol * tol * totn || offn == 0.0) break;
     for (int round = 0; round < m - 1; ++round) {
       // tournament pairing: position 0 fixed, the others rotate
-      if ((int)threadIdx.x < m / 2) {
+      if ((int)threadIdx.x < h) {
         const int k = threadIdx.x;
         auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
         int p = at(k), q = at(m - 1 - k);
@@ -120,55 +134,66 @@ __global__ __launch_bounds__(256) void k_jacobi(int n, const double* __restrict_
         pp[k] = p;
         qq[k] = q;
         const double apq = a[p][q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
+        double c = 1.0, sv = 0.0;
+        if (fabs(apq) > 1e-290) {  // below that the rotation is the identity to rounding
+          // t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), c = 1 / sqrt(t^2 + 1), s = t c;
+          // hardware reciprocal / reciprocal square root refined by two Newton steps each
+          // (full FP64 accuracy, much shorter dependency chains than IEEE division)
+          const double theta = (a[q][q] - a[p][p]) * rcp_nr(2.0 * apq);
+          const double at = fabs(theta);
+          double t;
+          if (at > 1e150) {
+            t = 0.5 / theta;
+          } else {
+            const double r2 = theta * theta + 1.0;
+            t = (theta >= 0.0 ? 1.0 : -1.0) * rcp_nr(at + r2 * rsq_nr(r2));
+          }
+          c = rsq_nr(t * t + 1.0);
+          sv = t * c;
         }
         cs[k] = c;
-        sn[k] = s;
+        sn[k] = sv;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {
-        const int k = e / m, j = e % m;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double x = a[p][j], y = a[q][j];
-        a[p][j] = c * x - s * y;
-        a[q][j] = s * x + c * y;
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < (m / 2) * m; e += blockDim.x) {
-        const int k = e / m, i = e % m;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double x = a[i][p], y = a[i][q];
-        a[i][p] = c * x - s * y;
-        a[i][q] = s * x + c * y;
-        const double vx = v[i][p], vy = v[i][q];
-        v[i][p] = c * vx - s * vy;
-        v[i][q] = s * vx + c * vy;
+      // A <- J^T A J by 2x2 blocks; V <- V J by column pairs
+      for (int e = threadIdx.x; e < h * h + m * h; e += JT) {
+        if (e < h * h) {
+          const int k = e / h, l = e % h;
+          const int p = pp[k], q = qq[k], r = pp[l], t = qq[l];
+          const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+          const double b00 = a[p][r], b01 = a[p][t], b10 = a[q][r], b11 = a[q][t];
+          const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+          const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+          a[p][r] = cl * r00 - sl * r01;
+          a[p][t] = sl * r00 + cl * r01;
+          a[q][r] = cl * r10 - sl * r11;
+          a[q][t] = sl * r10 + cl * r11;
+        } else {
+          const int f = e - h * h;
+          const int l = f / m, i = f % m;
+          const int p = pp[l], q = qq[l];
+          const double c = cs[l], sv = sn[l];
+          const double vx = v[i][p], vy = v[i][q];
+          v[i][p] = c * vx - sv * vy;
+          v[i][q] = sv * vx + c * vy;
+        }
       }
       __syncthreads();
     }
   }
   // ascending order: rank of each eigenvalue (ties broken by index)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += JT) {
     int r = 0;
     for (int j = 0; j < n; ++j)
       if (a[j][j] < a[i][i] || (a[j][j] == a[i][i] && j < i)) ++r;
     rank_s[i] = r;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+  for (int e = threadIdx.x; e < n * n; e += JT) {
     const int i = e / n, k = e % n;  // component i of eigenvector k (unsorted)
     V[(size_t)i * ldv + rank_s[k]] = v[i][k];
   }
-  for (int k = threadIdx.x; k < n; k += blockDim.x) w[rank_s[k]] = a[k][k];
+  for (int k = threadIdx.x; k < n; k += JT) w[rank_s[k]] = a[k][k];
 }
 
 // A = C + diag(d) (copy); n x n row-major
@@ -250,7 +275,7 @@ void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const doubl
 
 void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
                    int max_sweeps, double tol, hipStream_t s) {
-  k_jacobi<<<1, 256, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol);
+  k_jacobi<<<1, JT, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol);
 }
 
 }  // namespace ace

@@ -137,13 +137,15 @@ struct Eig {
   // k lowest Ritz vectors in Cm (m x k, row-major).
   void rr(int m) {
     const double rel = fp64 ? 1e-12 : 1e-6;
+    // Jacobi off-diagonal tolerance: far below the rounding of the grid vectors
+    const double jtol = fp64 ? 1e-14 : 1e-11;
     launch_sym_scale(S.d(), G.d(), m, Ss.d(), Gs.d(), D.d(), s);
-    launch_jacobi(m, Ss.d(), m, ws.d(), U.d(), m, 60, 1e-15, s);
+    launch_jacobi(m, Ss.d(), m, ws.d(), U.d(), m, 60, jtol, s);
     launch_canon(ws.d(), U.d(), m, rel, T.d(), s);
     launch_dgemm(1, 0, m, m, m, 1.0, T.d(), m, Gs.d(), m, 0.0, TG.d(), m, s);
     launch_dgemm(0, 0, m, m, m, 1.0, TG.d(), m, T.d(), m, 0.0, A.d(), m, s);
     launch_drop_diag(A.d(), m, ws.d(), rel, s);
-    launch_jacobi(m, A.d(), m, th.d(), Y.d(), m, 60, 1e-15, s);
+    launch_jacobi(m, A.d(), m, th.d(), Y.d(), m, 60, jtol, s);
     launch_dgemm(0, 0, m, k, m, 1.0, T.d(), m, Y.d(), m, 0.0, Cm.d(), k, s);
     launch_scale_coeff_rows(Cm.d(), k, D.d(), m, k, s);
   }
