@@ -53,8 +53,9 @@ enum {
   ACE_ERR_NONFINITE = -6    /* M not finite (device status) */
 };
 
-/* Largest orbital count accepted by ace_build / ace_apply. */
-#define ACE_MAX_ORBITALS 32
+/* Largest orbital count accepted by ace_build / ace_apply: real orbitals, complex orbitals. */
+#define ACE_MAX_ORBITALS 64
+#define ACE_MAX_ORBITALS_COMPLEX 32
 
 /*
  * Create a context for an N^3 box of spacing h holding orbitals of storage type `dtype`.
@@ -93,13 +94,27 @@ int pair_poisson_batched(ace_ctx* ctx, const void* phi_a, int na, const void* ph
  *   xi   = W L^{-H}                                                    (Eq. (12))
  *   E_x  = 1/2 sum_i M_ii   (occupation 1 per orbital; multiply by 2 for a closed-shell RHF
  *                            determinant built from spatial orbitals)
- * phi: [n][N^3], 1 <= n <= ACE_MAX_ORBITALS; xi_out: [n][N^3] (context dtype);
+ * phi: [n][N^3], 1 <= n <= ACE_MAX_ORBITALS (ACE_MAX_ORBITALS_COMPLEX for complex dtypes);
+ * xi_out: [n][N^3] (context dtype);
  * M_out: n*n FP64, complex interleaved for complex dtypes, row-major M[k][l], or NULL;
  * ex_out: one double, or NULL.  n(n+1)/2 pair solves are made.  If -M is not positive
  * definite the status word records ACE_ERR_NOT_POSDEF with the pivot and xi is zero.
  */
 int ace_build(ace_ctx* ctx, const void* phi, int n, void* xi_out, double* M_out,
               double* ex_out);
+
+/*
+ * ACE with extra orbitals (Sec. 3.1: the non-self-consistent run for unoccupied orbitals
+ * includes them in Eqs. (11)-(13)): the exchange operator K of the no occupied orbitals
+ * phi_occ (Eq. (2)) compressed on the span of nt target orbitals psi (typically the occupied
+ * followed by the current unoccupied ones):
+ *   W_t = K psi_t (no * nt pair solves), M = Psi^H W dV, -M = L L^H, xi = W L^{-H};
+ * K_ACE = -xi xi^H dV then equals K on span(psi).  nt <= ACE_MAX_ORBITALS (complex:
+ * ACE_MAX_ORBITALS_COMPLEX).  M_out (device, nt*nt, may be NULL).  Failures of the
+ * factorisation go to the device status word (ace_ctx_status).
+ */
+int ace_build_targets(ace_ctx* ctx, const void* phi_occ, int no, const void* psi, int nt,
+                      void* xi_out, double* M_out);
 
 /*
  * Apply the ACE operator (Eq. (13)): kpsi_out[v] = -sum_k xi_k dV <xi_k | psi_v>.
@@ -138,7 +153,7 @@ typedef struct ace_batch ace_batch;
 typedef struct {
   int n;              /* box edge of this system */
   double h;           /* spacing (bohr) */
-  int norb;           /* orbitals, 1..ACE_MAX_ORBITALS */
+  int norb;           /* orbitals, 1..ACE_MAX_ORBITALS (complex: ACE_MAX_ORBITALS_COMPLEX) */
   const void* phi;    /* [norb][n^3] orbitals (batch dtype), device */
   void* xi;           /* [norb][n^3] ACE projectors, device, output */
   double* M;          /* [norb*norb] M (complex interleaved for complex dtypes), device, or NULL */
@@ -325,6 +340,21 @@ typedef struct ace_eig_opts {
 int fock_lowest_states(ace_ctx* ctx, const void* v_local, const void* xi, int nxi, void* phi,
                        int k, const ace_eig_opts* opts, double* eigval, double* resnorm,
                        int* steps);
+
+/*
+ * Unoccupied orbitals by the non-self-consistent run of Sec. 3.1: the Hamiltonian
+ * F = T + v_local + K[phi_occ] is fixed; each outer iteration rebuilds ACE over the occupied
+ * and the current unoccupied orbitals (ace_build_targets) and takes up to opts->max_steps
+ * LOBPCG steps for the nv lowest states orthogonal to the occupied ones (phi_occ must be
+ * converged, dV-orthonormal eigenvectors of F).  Stops when the residuals measured right after
+ * a rebuild -- where K_ACE equals K on the current vectors -- are all below opts->tol, or
+ * after max_outer rebuilds.  psi: nv start vectors (device), overwritten by the unoccupied
+ * orbitals; eigval, resnorm (host, nv), *outer, *steps (host) may be NULL.  no + nv <=
+ * ACE_MAX_ORBITALS.  Synchronises.
+ */
+int unocc_states(ace_ctx* ctx, const void* v_local, const void* phi_occ, int no, void* psi,
+                 int nv, const ace_eig_opts* opts, int max_outer, double* eigval,
+                 double* resnorm, int* outer, int* steps);
 
 /* Energy terms of k doubly occupied orbitals: energy[5] (host) = total, kinetic, external,
  * Hartree, exchange (see above).  Synchronises. */

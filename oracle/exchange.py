@@ -78,6 +78,32 @@ def ace_build(phi, h, khat=None):
     return xim.reshape(phi.shape), m, lower, ex
 
 
+def ace_build_targets(phi, psi, h, khat=None):
+    """ACE of the exchange operator of the occupied orbitals phi compressed on the span of
+    the target orbitals psi (Sec. 3.1: the unoccupied-orbital run includes the unoccupied
+    orbitals in Eqs. (11)-(13)):
+
+    1. W_t = K[phi] psi_t (Eq. (2));
+    2. M_kl = dV sum_r conj(psi_k) W_l;
+    3. -M = L L^H;
+    4. xi_k = sum_t W_t (L^{-H})_{tk}.
+    Returns (xi, M).
+    """
+    nt = psi.shape[0]
+    dv = h ** 3
+    if khat is None:
+        khat = poisson.kernel_hat(phi.shape[1], h)
+    w = np.stack([apply_direct(phi, psi[t], h, khat) for t in range(nt)])
+    pm = psi.reshape(nt, -1)
+    wm = w.reshape(nt, -1)
+    m = dv * (np.conj(pm) @ wm.T)
+    m = 0.5 * (m + np.conj(m.T))
+    lower = scipy.linalg.cholesky(-m, lower=True)
+    linv = scipy.linalg.solve_triangular(lower, np.eye(nt), lower=True)
+    xim = np.conj(linv.T).T @ wm
+    return xim.reshape(psi.shape), m
+
+
 def ace_apply(xi, psi, h):
     """K_ACE psi = -sum_k xi_k (dV sum_r conj(xi_k) psi): Eq. (13) applied to psi.
 

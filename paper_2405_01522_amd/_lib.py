@@ -56,6 +56,9 @@ SIGNATURES = {
     "kinetic_precondition": (_I, [_P, _P, _I, _D, _I, _D, _P]),
     "fock_lowest_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(_I)]),
     "scf_energies": (_I, [_P, _P, _P, _I, _P]),
+    "ace_build_targets": (_I, [_P, _P, _I, _P, _I, _P, _P]),
+    "unocc_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _I, _P, _P, ctypes.POINTER(_I),
+                          ctypes.POINTER(_I)]),
     "scf_run": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "precond_targets": (_I, [_P, _P, _I, _P, _I]),
     "convnet_create": (_I, [_P, ctypes.POINTER(_P)]),

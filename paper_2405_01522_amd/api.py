@@ -19,7 +19,8 @@ ACE_C128, ACE_C64, ACE_R64, ACE_R32 = 0, 1, 2, 3
 _DTYPES = {torch.complex128: ACE_C128, torch.complex64: ACE_C64,
            torch.float64: ACE_R64, torch.float32: ACE_R32}
 _TORCH = {v: k for k, v in _DTYPES.items()}
-MAX_ORBITALS = 32
+MAX_ORBITALS = 64           # real orbitals
+MAX_ORBITALS_COMPLEX = 32   # complex orbitals
 
 
 def dtype_code(dtype):
@@ -249,6 +250,37 @@ class AceContext:
                                        rn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)),
               "fock_lowest_states")
         return ev, rn, st.value
+
+    def ace_build_targets(self, phi_occ, psi, xi_out=None, m_out=None):
+        """ACE of K[phi_occ] compressed on span(psi) (the unoccupied-run construction)."""
+        nt = psi.shape[0]
+        if xi_out is None:
+            xi_out = self._empty(nt)
+        if m_out is None:
+            m_out = torch.empty((nt, nt), dtype=torch.complex128 if self.dtype.is_complex
+                                else torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().ace_build_targets(self._h, self._vol(phi_occ, "phi_occ"), phi_occ.shape[0],
+                                      self._vol(psi, "psi"), nt, self._vol(xi_out, "xi_out", nt),
+                                      ctypes.c_void_p(m_out.data_ptr())), "ace_build_targets")
+        return xi_out, m_out
+
+    def unocc_states(self, v_local, phi_occ, psi, opts=None, max_outer=50):
+        """Unoccupied orbitals of the fixed Hamiltonian (psi overwritten).  Returns
+        (eigenvalues, residual norms, outer rebuilds, eigensolver steps)."""
+        import numpy as np
+        nv = psi.shape[0]
+        o = opts if opts is not None else eig_opts(max_steps=10)
+        ev, rn = np.zeros(nv), np.zeros(nv)
+        outer, steps = ctypes.c_int(), ctypes.c_int()
+        self._sync_stream()
+        check(lib().unocc_states(self._h, self._vol(v_local, "v_local", 1),
+                                 self._vol(phi_occ, "phi_occ"), phi_occ.shape[0],
+                                 self._vol(psi, "psi"), nv, ctypes.byref(o), int(max_outer),
+                                 ev.ctypes.data_as(ctypes.c_void_p),
+                                 rn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(outer),
+                                 ctypes.byref(steps)), "unocc_states")
+        return ev, rn, outer.value, steps.value
 
     def scf_energies(self, v_ext, phi):
         """dict(total, kinetic, external, hartree, exchange) of doubly occupied orbitals."""

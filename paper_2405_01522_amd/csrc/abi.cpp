@@ -158,7 +158,7 @@ int pair_poisson_batched(ace_ctx* c, const void* phi_a, int na, const void* phi_
 }
 
 int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, double* ex_out) {
-  if (!c || !phi || !xi_out || n < 1 || n > ACE_MAX_ORBITALS) return ACE_ERR_INVALID;
+  if (!c || !phi || !xi_out || n < 1 || n > max_orbitals(c->dtype)) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   const int np = n * (n + 1) / 2;
   std::vector<int> pl(2 * (size_t)np);
@@ -189,8 +189,33 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   return hip_check(hipGetLastError());
 }
 
+int ace_build_targets(ace_ctx* c, const void* phi_occ, int no, const void* psi, int nt,
+                      void* xi_out, double* M_out) {
+  if (!c || !phi_occ || !psi || !xi_out || no < 1 || nt < 1 || no > max_orbitals(c->dtype) ||
+      nt > max_orbitals(c->dtype))
+    return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+  size_t chunk;
+  const int nblk = gram_blocks(ng, &chunk);
+  int rc = ensure(c, c->wbuf, eb * ng * (size_t)nt);
+  if (!rc) rc = ensure(c, c->part, wide * (size_t)nblk * nt * nt);
+  if (!rc) rc = ensure(c, c->small, wide * 2 * (size_t)nt * nt);
+  if (rc) return rc;
+  // W_t = K[phi_occ] psi_t: one pair solve per (occupied, target) pair (Eq. (2))
+  rc = exchange_apply_direct(c, phi_occ, no, psi, nt, c->wbuf.p);
+  if (rc) return rc;
+  char* mred = (char*)c->small.p;
+  char* linvh = mred + wide * (size_t)nt * nt;
+  launch_gram(c->dtype, psi, nt, c->wbuf.p, nt, ng, c->part.p, c->h * c->h * c->h, mred, c->stream,
+              c->tr());
+  launch_chol(c->dtype, mred, nt, M_out, nullptr, linvh, c->status, c->stream, c->tr());
+  launch_trsm(c->dtype, c->wbuf.p, nt, ng, linvh, xi_out, c->stream, c->tr());
+  return hip_check(hipGetLastError());
+}
+
 int ace_apply(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* out) {
-  if (!c || !xi || !psi || !out || n < 1 || n > ACE_MAX_ORBITALS || nv < 1) return ACE_ERR_INVALID;
+  if (!c || !xi || !psi || !out || n < 1 || n > max_orbitals(c->dtype) || nv < 1) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   const size_t wide = is_cplx(c->dtype) ? 16 : 8;
   // vectors per Gram / update pass (bounds the partial-sum workspace)
@@ -212,7 +237,7 @@ int ace_apply(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* 
 }
 
 int exchange_apply_direct(ace_ctx* c, const void* phi, int n, const void* psi, int nv, void* out) {
-  if (!c || !phi || !psi || !out || n < 1 || n > ACE_MAX_ORBITALS || nv < 1) return ACE_ERR_INVALID;
+  if (!c || !phi || !psi || !out || n < 1 || n > max_orbitals(c->dtype) || nv < 1) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   // vectors in groups so that the pair volumes stay within about 1 GiB
   const size_t per_vec = eb * ng * (size_t)n;
@@ -441,7 +466,7 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
   const int dt = b->dtype;
   for (int m = 0; m < nmol; ++m) {
     const ace_mol& x = mols[m];
-    if (!x.phi || !x.xi || x.norb < 1 || x.norb > ACE_MAX_ORBITALS || !(x.h > 0.0) ||
+    if (!x.phi || !x.xi || x.norb < 1 || x.norb > max_orbitals(dt) || !(x.h > 0.0) ||
         !std::isfinite(x.h))
       return ACE_ERR_INVALID;
     if (!ace_size_supported(x.n, dt)) return ACE_ERR_UNSUPPORTED;

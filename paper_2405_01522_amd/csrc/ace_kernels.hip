@@ -525,8 +525,10 @@ struct WaccRun {
       k_wacc<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
     else if (nmax <= 16)
       k_wacc<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
-    else
+    else if (nmax <= 32 || Elem<E>::cplx)
       k_wacc<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else if constexpr (!Elem<E>::cplx)
+      k_wacc<E, 64, S><<<grid, kThreads, 0, s>>>(src, ng);
   }
 };
 
@@ -539,8 +541,10 @@ struct TrsmRun {
       k_trsm<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
     else if (nmax <= 16)
       k_trsm<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
-    else
+    else if (nmax <= 32 || Elem<E>::cplx)
       k_trsm<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else if constexpr (!Elem<E>::cplx)
+      k_trsm<E, 64, S><<<grid, kThreads, 0, s>>>(src, ng);
   }
 };
 
@@ -567,8 +571,10 @@ struct CholRun {
       k_chol<W, 8, S><<<nsys, 64, 0, s>>>(src);
     else if (nmax <= 16)
       k_chol<W, 16, S><<<nsys, 64, 0, s>>>(src);
-    else
+    else if (nmax <= 32 || CPLX)
       k_chol<W, 32, S><<<nsys, 64, 0, s>>>(src);
+    else if constexpr (!CPLX)
+      k_chol<W, 64, S><<<nsys, 64, 0, s>>>(src);
   }
 };
 
@@ -680,8 +686,10 @@ static void apply_impl(const void* xi, int n, size_t ng, const void* z, int nv, 
     k_apply_out<E, 8><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
   else if (n <= 16)
     k_apply_out<E, 16><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
-  else
+  else if (n <= 32 || Elem<E>::cplx)
     k_apply_out<E, 32><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+  else if constexpr (!Elem<E>::cplx)
+    k_apply_out<E, 64><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
 }
 
 void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, int nv, void* out,

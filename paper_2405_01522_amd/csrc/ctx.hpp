@@ -30,6 +30,7 @@ inline size_t elem_bytes(int dt) {
 }
 inline bool is_fp64(int dt) { return dt == ACE_C128 || dt == ACE_R64; }
 inline bool is_cplx(int dt) { return dt == ACE_C128 || dt == ACE_C64; }
+inline int max_orbitals(int dt) { return is_cplx(dt) ? ACE_MAX_ORBITALS_COMPLEX : ACE_MAX_ORBITALS; }
 
 struct Blob {
   Buf dev;

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kT) void k_residual_grid(const T* __restrict__ X, c
 
 constexpr int kPVB = 16;  // vectors per block of the complement projection
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, bool OUT>
 __global__ __launch_bounds__(kT) void k_project_complement(const T* __restrict__ phi, int k,
                                                            const double* __restrict__ z, int nv,
                                                            size_t ng, T* __restrict__ io) {
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kT) void k_project_complement(const T* __restrict__
     for (int i = 0; i < KMAX; ++i)
       if (i < k) s += p[i] * zs[i * kPVB + vb];
     const size_t o = (size_t)(v0 + vb) * ng + r;
-    io[o] = s - io[o];
+    io[o] = OUT ? io[o] - s : s - io[o];
   }
 }
 
@@ -423,24 +423,32 @@ void launch_residual_grid(bool fp64, const void* X, const void* HX, const double
                                                (float*)R);
 }
 
+template <typename T, bool OUT>
+static void project_impl(const void* phi, int k, const double* z, int nv, size_t ng, void* io,
+                         hipStream_t s) {
+  dim3 grid(grid_blocks(ng), (nv + kPVB - 1) / kPVB);
+  if (k <= 16)
+    k_project_complement<T, 16, OUT><<<grid, kT, 0, s>>>((const T*)phi, k, z, nv, ng, (T*)io);
+  else if (k <= 32)
+    k_project_complement<T, 32, OUT><<<grid, kT, 0, s>>>((const T*)phi, k, z, nv, ng, (T*)io);
+  else
+    k_project_complement<T, 64, OUT><<<grid, kT, 0, s>>>((const T*)phi, k, z, nv, ng, (T*)io);
+}
+
 void launch_project_complement(bool fp64, const void* phi, int k, const double* z, int nv,
                                size_t ng, void* inout, hipStream_t s) {
-  dim3 grid(grid_blocks(ng), (nv + kPVB - 1) / kPVB);
-  if (fp64) {
-    if (k <= 16)
-      k_project_complement<double, 16><<<grid, kT, 0, s>>>((const double*)phi, k, z, nv, ng,
-                                                           (double*)inout);
-    else
-      k_project_complement<double, 32><<<grid, kT, 0, s>>>((const double*)phi, k, z, nv, ng,
-                                                           (double*)inout);
-  } else {
-    if (k <= 16)
-      k_project_complement<float, 16><<<grid, kT, 0, s>>>((const float*)phi, k, z, nv, ng,
-                                                          (float*)inout);
-    else
-      k_project_complement<float, 32><<<grid, kT, 0, s>>>((const float*)phi, k, z, nv, ng,
-                                                          (float*)inout);
-  }
+  if (fp64)
+    project_impl<double, false>(phi, k, z, nv, ng, inout, s);
+  else
+    project_impl<float, false>(phi, k, z, nv, ng, inout, s);
+}
+
+void launch_project_out(bool fp64, const void* phi, int k, const double* z, int nv, size_t ng,
+                        void* inout, hipStream_t s) {
+  if (fp64)
+    project_impl<double, true>(phi, k, z, nv, ng, inout, s);
+  else
+    project_impl<float, true>(phi, k, z, nv, ng, inout, s);
 }
 
 void launch_scale_to_f32(bool fp64, const void* src, const double* scale, int nv, size_t ng,

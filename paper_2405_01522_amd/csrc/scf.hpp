@@ -42,9 +42,13 @@ void launch_combine(bool fp64, const void* V, int mb, size_t ng, const double* C
 void launch_residual_grid(bool fp64, const void* X, const void* HX, const double* lam, int k,
                           size_t ng, void* R, hipStream_t s);
 
-// inout_v = sum_k Phi_k z[k * nv + v] - inout_v  (complement projection; z FP64, scaled)
+// inout_v = sum_k Phi_k z[k * nv + v] - inout_v  (complement projection; z FP64, scaled),
+// k <= 64
 void launch_project_complement(bool fp64, const void* phi, int k, const double* z, int nv,
                                size_t ng, void* inout, hipStream_t s);
+// inout_v -= sum_k Phi_k z[k * nv + v]  (removal of the span of Phi), k <= 64
+void launch_project_out(bool fp64, const void* phi, int k, const double* z, int nv, size_t ng,
+                        void* inout, hipStream_t s);
 
 // dst_v = scale_v * src_v, converted to float (dst is always float); scale: nv doubles
 void launch_scale_to_f32(bool fp64, const void* src, const double* scale, int nv, size_t ng,

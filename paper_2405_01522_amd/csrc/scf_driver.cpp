@@ -71,10 +71,12 @@ struct Eig {
   double h = 0, dv = 0;
   hipStream_t s = nullptr;
   Mem V, HV, V2, HV2, R, tmp, nin, nout;
-  Mem S, G, Ss, Gs, D, ws, U, T, TG, A, th, Y, Cm, Gr, rd, scale, part;
+  Mem S, G, Ss, Gs, D, ws, U, T, TG, A, th, Y, Cm, Gr, rd, scale, part, zl;
+  const void* lock = nullptr;  // converged vectors the search space is kept orthogonal to
+  int nlock = 0;
   std::vector<double> h_rd;
 
-  int init(ace_ctx* c_, int k_, bool want_net) {
+  int init(ace_ctx* c_, int k_, bool want_net, int nlock_ = 0) {
     c = c_;
     k = k_;
     fp64 = c->dtype == ACE_R64;
@@ -109,12 +111,22 @@ struct Eig {
     if (!rc) rc = Gr.alloc(sizeof(double) * k * k);
     size_t chunk;
     const int nblk = gram_blocks(ng, &chunk);
-    if (!rc) rc = part.alloc(sizeof(double) * (size_t)nblk * mmax * mmax);
+    nlock = nlock_;
+    const size_t pw = std::max((size_t)mmax * mmax, (size_t)nlock * nw * k);
+    if (!rc) rc = part.alloc(sizeof(double) * (size_t)nblk * pw);
+    if (!rc && nlock) rc = zl.alloc(sizeof(double) * (size_t)nlock * nw * k);
     h_rd.assign(k, 0.0);
     return rc;
   }
 
   char* vec(const Mem& m, int j) const { return (char*)m.p + eb * ng * (size_t)j; }
+
+  // Y <- Y - L (L^T Y dV) for the locked vectors L (dV-orthonormal eigenvectors of F)
+  void deflate(void* Y, int nv) {
+    if (!nlock) return;
+    launch_gram(c->dtype, lock, nlock, Y, nv, ng, part.p, dv, zl.p, s, nullptr);
+    launch_project_out(fp64, lock, nlock, zl.d(), nv, ng, Y, s);
+  }
 
   void gram(const void* A_, int na, const void* B_, int nb, double scale_, double* out) {
     launch_gram(c->dtype, A_, na, B_, nb, ng, part.p, scale_, out, s, nullptr);
@@ -190,6 +202,7 @@ struct Eig {
           Recorder* rec, int* steps_out, double* maxres) {
     const size_t vb = eb * ng;
     int rc = hip_check(hipMemcpyAsync(V.p, X, vb * k, hipMemcpyDeviceToDevice, s));
+    deflate(V.p, k);
     if (!rc) rc = fock(vloc, xi, nxi, V.p, k, HV.p);
     if (rc) return rc;
     // Rayleigh-Ritz on the starting block alone (orthonormalises it)
@@ -213,6 +226,7 @@ struct Eig {
       }
       if (*maxres < o->tol || steps >= o->max_steps) break;
       rc = precondition(o, vec(V, k));
+      deflate(vec(V, k), nw * k);
       if (!rc) rc = fock(vloc, xi, nxi, vec(V, k), nw * k, vec(HV, k));
       if (rc) return rc;
       const int pb = (1 + nw) * k;  // first vector of the P block
@@ -365,6 +379,65 @@ int fock_lowest_states(ace_ctx* c, const void* v_local, const void* xi, int nxi,
   if (eigval) std::copy(th.begin(), th.end(), eigval);
   if (resnorm) std::copy(e.h_rd.begin(), e.h_rd.end(), resnorm);
   if (steps) *steps = st;
+  return ACE_OK;
+}
+
+int unocc_states(ace_ctx* c, const void* v_local, const void* phi_occ, int no, void* psi, int nv,
+                 const ace_eig_opts* o, int max_outer, double* eigval, double* resnorm,
+                 int* outer, int* steps) {
+  if (!c || !v_local || !phi_occ || !psi || no < 1 || nv < 1 || max_outer < 1 ||
+      no + nv > ACE_MAX_ORBITALS)
+    return ACE_ERR_INVALID;
+  if (!real_ctx(c)) return ACE_ERR_UNSUPPORTED;
+  int rc = check_eig_opts(c, o);
+  if (rc) return rc;
+  Eig e;
+  rc = e.init(c, nv, o->precond == ACE_PRECOND_NET, no);
+  if (rc) return rc;
+  e.lock = phi_occ;
+  const int nt = no + nv;
+  const size_t vb = elem_bytes(c->dtype) * c->ng;
+  hipStream_t s = c->stream;
+  Mem targets, xi;
+  if (!rc) rc = targets.alloc(vb * nt);
+  if (!rc) rc = xi.alloc(vb * nt);
+  if (rc) return rc;
+  if (hipMemcpyAsync(targets.p, phi_occ, vb * no, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  // the unoccupied start vectors: orthogonal to the occupied ones
+  e.deflate(psi, nv);
+  int it = 0, total = 0;
+  double maxres = 0.0;
+  for (it = 0; it < max_outer; ++it) {
+    // ACE over occupied + current unoccupied orbitals, then eigensolver steps with it
+    if (hipMemcpyAsync((char*)targets.p + vb * no, psi, vb * nv, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return ACE_ERR_HIP;
+    rc = ace_build_targets(c, phi_occ, no, targets.p, nt, xi.p, nullptr);
+    if (rc) return rc;
+    int st = 0;
+    rc = e.run(v_local, xi.p, nt, psi, o, nullptr, &st, &maxres);
+    if (rc) return rc;
+    total += st;
+    int stc = 0;
+    rc = ace_ctx_status(c, &stc, nullptr);
+    if (rc) return rc;
+    if (stc) return stc;
+    // the first residual of a run is taken right after the rebuild, where K_ACE equals K on
+    // the current vectors: no step taken means every residual of the true operator is small
+    if (st == 0) {
+      ++it;
+      break;
+    }
+  }
+  std::vector<double> th(nv);
+  if (hipMemcpyAsync(th.data(), e.th.p, sizeof(double) * nv, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ACE_ERR_HIP;
+  if (eigval) std::copy(th.begin(), th.end(), eigval);
+  if (resnorm) std::copy(e.h_rd.begin(), e.h_rd.end(), resnorm);
+  if (outer) *outer = it;
+  if (steps) *steps = total;
   return ACE_OK;
 }
 

@@ -327,3 +327,79 @@ def test_scf_with_learned_preconditioner_small():
     learned = ctx.scf_run(v, phi2, ace.scf_opts(alpha=0.3, tol=1e-6, max_iter=200, eig=eig2))
     assert learned["converged"]
     assert abs(learned["total"] - plain["total"]) < 2e-5
+
+
+# ---- ACE over occupied + unoccupied orbitals, the non-self-consistent unoccupied run ----------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ace_build_targets_matches_oracle(prec):
+    ace = _ace()
+    from oracle import exchange
+    mol = synth.small_real(31, 12, 0.45, 2, 3)
+    h = 0.45
+    psi = np.concatenate([mol.phi, mol.phi_virt])
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = ace.AceContext(12, h, dt)
+    xi, m = ctx.ace_build_targets(_t(mol.phi, dt), _t(psi, dt))
+    assert ctx.status()[0] == 0
+    xr, mr = exchange.ace_build_targets(mol.phi, psi, h)
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    assert np.max(np.abs(m.cpu().numpy() - mr)) < tol * np.max(np.abs(mr))
+    # the compressed operator on random vectors (xi itself is unique: L has a positive diagonal)
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(3, 12, 12, 12))
+    got = ctx.ace_apply(xi, _t(v, dt)).cpu().numpy()
+    ref = exchange.ace_apply(xr, v, h)
+    assert np.max(np.abs(got - ref)) < tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ace_build_forty_real_orbitals(prec):
+    """More than 32 real orbitals (the occupied + unoccupied sizes of the unoccupied run)."""
+    ace = _ace()
+    from oracle import exchange
+    n, h, k = 12, 0.5, 40
+    phi = _orthonormal(np.random.default_rng(40), k, n, h)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = ace.AceContext(n, h, dt)
+    xi, m, ex = ctx.ace_build(_t(phi, dt))
+    assert ctx.status()[0] == 0
+    xr, mr, _, exr = exchange.ace_build(phi, h)
+    tol = 1e-10 if prec == "fp64" else 3e-6
+    assert np.max(np.abs(m.cpu().numpy() - mr)) < tol * np.max(np.abs(mr))
+    assert abs(ex.item() - exr) < tol * abs(exr)
+    v = np.random.default_rng(41).normal(size=(2, n, n, n))
+    got = ctx.ace_apply(xi, _t(v, dt)).cpu().numpy()
+    ref = exchange.ace_apply(xr, v, h)
+    assert np.max(np.abs(got - ref)) < tol * 10 * np.max(np.abs(ref))
+
+
+def test_unoccupied_states_match_direct_operator():
+    """Converged occupied orbitals (FP64 SCF), then the unoccupied run with ACE over occupied +
+    unoccupied orbitals: its eigenvalues are those of the direct-exchange Fock operator above
+    the occupied ones (oracle Lanczos on the same operator)."""
+    ace = _ace()
+    s = synth.scf_small()
+    dt = torch.float64
+    ctx = ace.AceContext(s.n, s.h, dt)
+    phi = _core_guess(ace, ctx, s, dt, 2)
+    v = _t(s.v_ext[None], dt)
+    res = ctx.scf_run(v, phi, ace.scf_opts(alpha=0.3, tol=1e-11, max_iter=300,
+                                           eig=ace.eig_opts(max_steps=4, tol=1e-8)))
+    assert res["converged"]
+    nv, nchk = 6, 4  # two buffer states above the four that are checked
+    vloc = v + ctx.hartree_potential(ctx.scf_density(phi))
+    psi = _t(_orthonormal(np.random.default_rng(8), nv, s.n, s.h), dt)
+    ev, rn, outer, steps = ctx.unocc_states(vloc, phi, psi,
+                                            opts=ace.eig_opts(max_steps=20, tol=1e-6), max_outer=60)
+    assert np.all(rn[:nchk] < 1e-6), (rn, outer, steps)
+    p = phi.cpu().numpy()
+    khat = poisson.kernel_hat(s.n, s.h)
+    vl = vloc.cpu().numpy()[0]
+    ref, _ = scf.lowest_states(lambda f: scf.fock_apply(f, p, vl, s.h, khat), s.n, 2 + nchk, s.h,
+                               v0=np.random.default_rng(1).normal(size=s.n ** 3))
+    assert np.allclose(ev[:nchk], ref[2:], atol=1e-8), (ev, ref)
+    # orthogonal to the occupied orbitals, orthonormal among themselves
+    q = psi.cpu().numpy()
+    ov = np.einsum("ixyz,jxyz->ij", q, np.concatenate([p, q])) * s.h ** 3
+    assert np.allclose(ov, np.concatenate([np.zeros((nv, 2)), np.eye(nv)], axis=1), atol=1e-8)

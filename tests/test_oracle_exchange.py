@@ -139,3 +139,26 @@ def test_ace_rank_and_hermitian():
     s = np.linalg.svd(cols, compute_uv=False)
     assert np.sum(s > 1e-10 * s[0]) == 3
     assert np.max(np.abs(cols - cols.conj().T)) < 1e-13 * np.max(np.abs(cols))
+
+
+def test_ace_with_targets_exact_on_target_span():
+    """ACE built over occupied + extra orbitals reproduces the exchange operator of the
+    occupied orbitals on every target and on their combinations, and reduces to the plain
+    construction when the targets are the occupied orbitals."""
+    import synth
+    mol = synth.small_real(31, 12, 0.45, 2, 3)
+    phi, virt = mol.phi, mol.phi_virt
+    h = 0.45
+    khat = poisson.kernel_hat(12, h)
+    psi = np.concatenate([phi, virt])
+    xi, m = exchange.ace_build_targets(phi, psi, h, khat)
+    for t in range(psi.shape[0]):
+        ref = exchange.apply_direct(phi, psi[t], h, khat)
+        got = exchange.ace_apply(xi, psi[t], h)
+        assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    comb = 0.3 * psi[0] - 1.1 * psi[3] + 0.7 * psi[4]
+    assert np.allclose(exchange.ace_apply(xi, comb, h), exchange.apply_direct(phi, comb, h, khat),
+                       atol=1e-12)
+    xi2, m2 = exchange.ace_build_targets(phi, phi, h, khat)
+    xi1, m1, _, _ = exchange.ace_build(phi, h, khat)
+    assert np.allclose(m1, m2, atol=1e-13) and np.allclose(xi1, xi2, atol=1e-12)
