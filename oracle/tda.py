@@ -17,10 +17,20 @@ Readings:
 * Strength function: each delta of Eq. (10) broadened by a normalised Lorentzian of
   half-width gamma.
 
+Full TDHF (Eq. (3)): the RHF B block (spin-adapted from Eq. (5): singlet
+B = 2 (ia|bj) - (ib|aj), triplet B = -(ib|aj), i.e. B_{ia,jb} = delta_M (ia|bj) - (ib|aj)),
+the UHF blocks of Eqs. (4)-(5) with (pq||rs) = (pq|rs) - (pr|qs) over spin orbitals, and the
+positive eigenvalues of the non-Hermitian problem of Eq. (3).
+
 Pinned by (tests/test_oracle_tda.py): brute-force double sums for single integrals on tiny
 grids, the 8-fold symmetry of real integrals, Hermiticity of C, singlet - triplet =
-2 (ai|jb), and diagonal integrals against the Gaussian closed form.
+2 (ai|jb), diagonal integrals against the Gaussian closed form; the one-transition closed
+form omega = sqrt(A^2 - B^2), B = 0 giving the Tamm-Dancoff eigenvalues, agreement with the
+Hermitian half-size form (A-B)^{1/2} (A+B) (A-B)^{1/2} for real orbitals, and the closed-shell
+UHF spectrum being the union of the RHF singlet and triplet spectra (TDA and full TDHF).
 """
+
+import scipy.linalg
 
 import numpy as np
 
@@ -63,6 +73,86 @@ def coupling_block(phi_occ, phi_virt, h, delta_m, khat=None):
     if not (np.iscomplexobj(phi_occ) or np.iscomplexobj(phi_virt)):
         c = c.real
     return c
+
+
+def _pair_potentials(left, right, h, khat):
+    """v[p][q] = G (*) conj(left_p) right_q for every pair, flattened volumes."""
+    return np.stack([np.stack([poisson.fft(np.conj(lp) * rq, h, khat).reshape(-1)
+                               for rq in right]) for lp in left])
+
+
+def b_block(phi_occ, phi_virt, h, delta_m, khat=None):
+    """RHF B_{ia,jb} = delta_M (ia|bj) - (ib|aj) (Eq. (3), spin-adapted Eq. (5))."""
+    no, nv = phi_occ.shape[0], phi_virt.shape[0]
+    if khat is None:
+        khat = poisson.kernel_hat(phi_occ.shape[1], h)
+    dv = h ** 3
+    po = phi_occ.reshape(no, -1)
+    pv = phi_virt.reshape(nv, -1)
+    v_ia = _pair_potentials(phi_occ, phi_virt, h, khat)          # G (*) conj(phi_i) phi_a
+    # (ia|bj) = dV sum_r conj(phi_b) phi_j v_ia ; (ib|aj) = dV sum_r conj(phi_a) phi_j v_ib
+    t1 = dv * np.einsum("iar,br,jr->iajb", v_ia, np.conj(pv), po)
+    t2 = dv * np.einsum("ibr,ar,jr->iajb", v_ia, np.conj(pv), po)
+    b = (delta_m * t1 - t2).reshape(no * nv, no * nv)
+    if not (np.iscomplexobj(phi_occ) or np.iscomplexobj(phi_virt)):
+        b = b.real
+    return b
+
+
+def uhf_blocks(occ_a, virt_a, occ_b, virt_b, h, khat=None):
+    """UHF A - diag(eps_a - eps_i) and B over spin orbitals (Eqs. (4), (5)):
+    (ia||jb) = (ia|jb) - (ij|ab), (ia||bj) = (ia|bj) - (ib|aj), the second terms only between
+    transitions of the same spin.  Index: alpha transitions i*nv_a + a first, then beta."""
+    if khat is None:
+        khat = poisson.kernel_hat(occ_a.shape[1], h)
+    dv = h ** 3
+    spins = [(occ_a, virt_a), (occ_b, virt_b)]
+    sizes = [o.shape[0] * v.shape[0] for o, v in spins]
+    off = [0, sizes[0]]
+    n = sum(sizes)
+    cplx = any(np.iscomplexobj(x) for x in (occ_a, virt_a, occ_b, virt_b))
+    a_m = np.zeros((n, n), dtype=np.complex128)
+    b_m = np.zeros((n, n), dtype=np.complex128)
+    for s, (os_, vs) in enumerate(spins):
+        v_ia = _pair_potentials(os_, vs, h, khat)                     # [i][a] G (*) conj(i) a
+        v_ij = _pair_potentials(os_, os_, h, khat)                    # [i][j] G (*) conj(i) j
+        for t, (ot, vt) in enumerate(spins):
+            po_t = ot.reshape(ot.shape[0], -1)
+            pv_t = vt.reshape(vt.shape[0], -1)
+            coul = dv * np.einsum("iar,jr,br->iajb", v_ia, np.conj(po_t), pv_t)  # (ia|jb)
+            bcou = dv * np.einsum("iar,br,jr->iajb", v_ia, np.conj(pv_t), po_t)  # (ia|bj)
+            blk_a, blk_b = coul, bcou
+            if s == t:
+                pv_s = vs.reshape(vs.shape[0], -1)
+                po_s = os_.reshape(os_.shape[0], -1)
+                exa = dv * np.einsum("ijr,ar,br->iajb", v_ij, np.conj(pv_s), pv_s)  # (ij|ab)
+                v_ib = v_ia
+                exb = dv * np.einsum("ibr,ar,jr->iajb", v_ib, np.conj(pv_s), po_s)  # (ib|aj)
+                blk_a = coul - exa
+                blk_b = bcou - exb
+            ns, nt = sizes[s], sizes[t]
+            a_m[off[s]:off[s] + ns, off[t]:off[t] + nt] = blk_a.reshape(ns, nt)
+            b_m[off[s]:off[s] + ns, off[t]:off[t] + nt] = blk_b.reshape(ns, nt)
+    if not cplx:
+        a_m, b_m = a_m.real, b_m.real
+    return a_m, b_m
+
+
+def rpa_excitations(a_matrix, b_matrix):
+    """Positive eigenvalues omega of Eq. (3): [[A, B], [B*, A*]] z = omega diag(1, -1) z,
+    i.e. of [[A, B], [-B*, -A*]]; ascending."""
+    n = a_matrix.shape[0]
+    big = np.block([[a_matrix, b_matrix], [-np.conj(b_matrix), -np.conj(a_matrix)]])
+    w = np.linalg.eigvals(big)
+    w = np.sort(w.real[w.real > 0])
+    return w[:n]
+
+
+def rpa_hermitian(a_matrix, b_matrix):
+    """For real A, B with A - B positive definite: omega^2 are the eigenvalues of
+    (A - B)^{1/2} (A + B) (A - B)^{1/2} (the half-size Hermitian form of Sec. 2)."""
+    s = scipy.linalg.sqrtm(a_matrix - b_matrix).real
+    return np.sqrt(np.linalg.eigvalsh(s @ (a_matrix + b_matrix) @ s))
 
 
 def coupling_element(phi_occ, phi_virt, h, delta_m, i, a, j, b, khat=None):

@@ -115,3 +115,49 @@ def test_oscillator_two_level():
     wg = np.linspace(-200.0, 200.0, 400001)
     sfun = tda.strength_function(wg, np.array([0.5]), f, 0.01)
     assert np.trapezoid(sfun, wg) == pytest.approx(f[0], rel=1e-4)
+
+
+def test_rpa_closed_forms():
+    # one transition: omega = sqrt(A^2 - B^2); B = 0: the Tamm-Dancoff eigenvalues
+    assert tda.rpa_excitations(np.array([[0.7]]), np.array([[0.2]]))[0] == pytest.approx(
+        np.sqrt(0.7 ** 2 - 0.2 ** 2), rel=1e-14)
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(6, 6))
+    a = a @ a.T + 6 * np.eye(6)
+    assert np.allclose(tda.rpa_excitations(a, np.zeros((6, 6))), np.linalg.eigvalsh(a))
+    b = rng.normal(size=(6, 6)) * 0.3
+    b = 0.5 * (b + b.T)
+    assert np.allclose(tda.rpa_excitations(a, b), tda.rpa_hermitian(a, b), rtol=1e-12)
+
+
+def test_b_block_structure(small):
+    occ, virt, h = small.phi, small.phi_virt, small.h
+    b2 = tda.b_block(occ, virt, h, 2)
+    b0 = tda.b_block(occ, virt, h, 0)
+    assert np.allclose(b2, b2.T, atol=1e-12)
+    no, nv = occ.shape[0], virt.shape[0]
+    i, a, j, bb = 1, 2, 0, 1
+    ref = 2 * tda.integral(occ[i], virt[a], virt[bb], occ[j], h) - \
+        tda.integral(occ[i], virt[bb], virt[a], occ[j], h)
+    assert b2[i * nv + a, j * nv + bb] == pytest.approx(ref.real, abs=1e-12)
+    # singlet - triplet = 2 (ia|bj), the same matrix as the A block's (ai|jb) for real orbitals
+    c2 = tda.coupling_block(occ, virt, h, 2)
+    c0 = tda.coupling_block(occ, virt, h, 0)
+    assert np.allclose(b2 - b0, c2 - c0, atol=1e-12)
+
+
+def test_closed_shell_uhf_is_union_of_singlets_and_triplets(small):
+    occ, virt, h = small.phi, small.phi_virt, small.h
+    no, nv = occ.shape[0], virt.shape[0]
+    eo = np.array([-1.3, -1.1, -0.9][:no])
+    ev = np.linspace(0.1, 0.5, nv)
+    de = (ev[None, :] - eo[:, None]).reshape(-1)
+    cu, bu = tda.uhf_blocks(occ, virt, occ, virt, h)
+    du = np.concatenate([de, de])
+    uhf_tda = np.linalg.eigvalsh(np.diag(du) + cu)
+    rhf = [np.linalg.eigvalsh(np.diag(de) + tda.coupling_block(occ, virt, h, dm)) for dm in (2, 0)]
+    assert np.allclose(uhf_tda, np.sort(np.concatenate(rhf)), atol=1e-10)
+    uhf_rpa = tda.rpa_excitations(np.diag(du) + cu, bu)
+    rhf_rpa = [tda.rpa_excitations(np.diag(de) + tda.coupling_block(occ, virt, h, dm),
+                                   tda.b_block(occ, virt, h, dm)) for dm in (2, 0)]
+    assert np.allclose(uhf_rpa, np.sort(np.concatenate(rhf_rpa)), atol=1e-9)
