@@ -142,6 +142,29 @@ int tda_coupling(ace_ctx* ctx, const void* phi_occ, int no, const void* phi_virt
                  int delta_M, double* C_out);
 
 /*
+ * Full TDHF blocks for real RHF orbitals (Eq. (3)): C as tda_coupling (A without its diagonal
+ * eps_a - eps_i) and the B block spin-adapted from Eq. (5),
+ *   B[ia][jb] = delta_M (ia|bj) - (ib|aj)   (delta_M = 2 singlet, 0 triplet),
+ * from the same pair solves and contraction (for real orbitals (ib|aj) is an entry of the
+ * same (ia|jb) matrix).  B_out: (no*nv)^2 FP64 device, or NULL (then this is tda_coupling).
+ */
+int tdhf_coupling(ace_ctx* ctx, const void* phi_occ, int no, const void* phi_virt, int nv,
+                  int delta_M, double* C_out, double* B_out);
+
+/*
+ * UHF blocks (Eqs. (4), (5)) for real orbitals of two spin channels, alpha (occ_a, virt_a) and
+ * beta (occ_b, virt_b), with (pq||rs) = (pq|rs) - (pr|qs) over spin orbitals:
+ *   C[x][y] = (ia|jb) - delta_st (ij|ab),  B[x][y] = (ia|bj) - delta_st (ib|aj),
+ * x = transition (i, a) of spin s, y = (j, b) of spin t; alpha transitions i*nv_a + a come
+ * first, then beta ones.  C_out, B_out: n x n FP64 device, n = no_a nv_a + no_b nv_b (B_out
+ * may be NULL).  A = diag(eps_a - eps_i) + C.  For a closed shell (the same orbitals in both
+ * channels) the spectrum is the union of the RHF singlet and triplet spectra.
+ */
+int uhf_coupling(ace_ctx* ctx, const void* occ_a, int no_a, const void* virt_a, int nv_a,
+                 const void* occ_b, int no_b, const void* virt_b, int nv_b, double* C_out,
+                 double* B_out);
+
+/*
  * Uneven batches of independent systems (the ACE rebuild of Sec. 3.1, Eqs. (11)-(12), for many
  * molecules at once).  A batch owns one kernel spectrum per distinct (n, h) and groups the
  * systems into size classes that run concurrently on streams of their own between a fork and
@@ -193,6 +216,28 @@ int ace_batch_trace_read(ace_batch* batch, int id, double* total_ms, long long* 
 int tda_excitations(ace_ctx* ctx, const double* C, const double* eps_occ, int no,
                     const double* eps_virt, int nv, int nstates, double tol, int max_iter,
                     double* omega_out, double* X_out, int* iterations);
+
+/*
+ * Lowest eigenpairs of A = C + diag(d) for any dense symmetric C (n x n FP64 device) and
+ * diagonal d (host, n): the general form of tda_excitations (e.g. the UHF transitions of
+ * uhf_coupling with d = eps_a - eps_i per spin).  Same outputs and limits as tda_excitations.
+ */
+int tda_excitations_diag(ace_ctx* ctx, const double* C, const double* d, int n, int nstates,
+                         double tol, int max_iter, double* omega_out, double* X_out,
+                         int* iterations);
+
+/*
+ * Full TDHF (Eq. (3)) for real orbitals, A = C + diag(d), B from tdhf_coupling or
+ * uhf_coupling: with A - B = L L^T (blocked Cholesky on the device), the Hermitian half-size
+ * problem L^T (A + B) L z = omega^2 z (Sec. 2) is solved by the same Davidson iteration.
+ * omega_out (device, nstates) ascending excitation energies; XpY_out (device, nstates x n, may
+ * be NULL) the vectors X + Y = L z / sqrt(omega), normalised by (X+Y)^T (X-Y) = 1, for
+ * transition dipoles as in Eq. (8).  Returns ACE_ERR_NOT_POSDEF if A - B is not positive
+ * definite (an unstable reference).  1 <= nstates <= 16.  Synchronises.
+ */
+int tdhf_excitations(ace_ctx* ctx, const double* C, const double* B, const double* d, int n,
+                     int nstates, double tol, int max_iter, double* omega_out, double* XpY_out,
+                     int* iterations);
 
 /*
  * Transition dipoles and oscillator strengths of TDA states (Eqs. (8)-(9), atomic units):

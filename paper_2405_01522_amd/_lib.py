@@ -57,6 +57,10 @@ SIGNATURES = {
     "fock_lowest_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(_I)]),
     "scf_energies": (_I, [_P, _P, _P, _I, _P]),
     "ace_build_targets": (_I, [_P, _P, _I, _P, _I, _P, _P]),
+    "tdhf_coupling": (_I, [_P, _P, _I, _P, _I, _I, _P, _P]),
+    "uhf_coupling": (_I, [_P, _P, _I, _P, _I, _P, _I, _P, _I, _P, _P]),
+    "tda_excitations_diag": (_I, [_P, _P, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),
+    "tdhf_excitations": (_I, [_P, _P, _P, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),
     "unocc_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _I, _P, _P, ctypes.POINTER(_I),
                           ctypes.POINTER(_I)]),
     "scf_run": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),

@@ -176,6 +176,69 @@ class AceContext:
               "tda_excitations")
         return omega, x, it.value
 
+    def tdhf_coupling(self, phi_occ, phi_virt, delta_m, c_out=None, b_out=None):
+        """(C, B) of full TDHF for real RHF orbitals (Eq. (3)); FP64 GPU matrices."""
+        no, nv = phi_occ.shape[0], phi_virt.shape[0]
+        n = no * nv
+        if c_out is None:
+            c_out = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        if b_out is None:
+            b_out = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().tdhf_coupling(self._h, self._vol(phi_occ, "phi_occ"), no,
+                                  self._vol(phi_virt, "phi_virt"), nv, int(delta_m),
+                                  ctypes.c_void_p(c_out.data_ptr()),
+                                  ctypes.c_void_p(b_out.data_ptr())), "tdhf_coupling")
+        return c_out, b_out
+
+    def uhf_coupling(self, occ_a, virt_a, occ_b, virt_b, with_b=True):
+        """(C, B) UHF blocks (Eqs. (4), (5)); alpha transitions first.  B is None unless with_b."""
+        n = occ_a.shape[0] * virt_a.shape[0] + occ_b.shape[0] * virt_b.shape[0]
+        c_out = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        b_out = torch.empty((n, n), dtype=torch.float64, device=self.device) if with_b else None
+        self._sync_stream()
+        check(lib().uhf_coupling(self._h, self._vol(occ_a, "occ_a"), occ_a.shape[0],
+                                 self._vol(virt_a, "virt_a"), virt_a.shape[0],
+                                 self._vol(occ_b, "occ_b"), occ_b.shape[0],
+                                 self._vol(virt_b, "virt_b"), virt_b.shape[0],
+                                 ctypes.c_void_p(c_out.data_ptr()),
+                                 ctypes.c_void_p(b_out.data_ptr()) if with_b else None),
+              "uhf_coupling")
+        return c_out, b_out
+
+    def tda_excitations_diag(self, c, d, nstates, tol=1e-8, max_iter=200):
+        """Lowest eigenpairs of C + diag(d) (d host array); (omega, X, iterations)."""
+        import numpy as np
+        dd = np.ascontiguousarray(d, dtype=np.float64)
+        n = dd.size
+        omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
+        x = torch.empty((nstates, n), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int()
+        self._sync_stream()
+        check(lib().tda_excitations_diag(self._h, ctypes.c_void_p(c.data_ptr()),
+                                         dd.ctypes.data_as(ctypes.c_void_p), n, int(nstates),
+                                         float(tol), int(max_iter), ctypes.c_void_p(omega.data_ptr()),
+                                         ctypes.c_void_p(x.data_ptr()), ctypes.byref(it)),
+              "tda_excitations_diag")
+        return omega, x, it.value
+
+    def tdhf_excitations(self, c, b, d, nstates, tol=1e-8, max_iter=200):
+        """Full TDHF excitation energies; (omega, X+Y, iterations)."""
+        import numpy as np
+        dd = np.ascontiguousarray(d, dtype=np.float64)
+        n = dd.size
+        omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
+        xpy = torch.empty((nstates, n), dtype=torch.float64, device=self.device)
+        it = ctypes.c_int()
+        self._sync_stream()
+        check(lib().tdhf_excitations(self._h, ctypes.c_void_p(c.data_ptr()),
+                                     ctypes.c_void_p(b.data_ptr()),
+                                     dd.ctypes.data_as(ctypes.c_void_p), n, int(nstates),
+                                     float(tol), int(max_iter), ctypes.c_void_p(omega.data_ptr()),
+                                     ctypes.c_void_p(xpy.data_ptr()), ctypes.byref(it)),
+              "tdhf_excitations")
+        return omega, xpy, it.value
+
     def tda_oscillator_strengths(self, phi_occ, phi_virt, x, omega):
         """(f, d): oscillator strengths (k,) and transition dipoles (k, 3) of TDA states."""
         k = omega.shape[0]

@@ -21,6 +21,28 @@ using namespace ace::host;
 
 namespace {
 constexpr double kC0 = 2.380077363979553;  // 3 ln(2 + sqrt 3) - pi/2
+
+// Real pair solves of an explicit pointer list (two pairs per complex FFT), in batches bounded
+// by the FFT workspace; the list goes to the device through the context's cached blob.
+int solve_pair_list(ace_ctx* c, const std::vector<PairPtrs>& items) {
+  const int np = (int)items.size();
+  int rc = upload_blob(c->stream, c->tda_items, items.data(), sizeof(PairPtrs) * items.size());
+  if (rc) return rc;
+  const bool fp64 = is_fp64(c->dtype);
+  const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
+  const size_t nit = ((size_t)np + 1) / 2;
+  const size_t batch = std::max<size_t>(1, std::min<size_t>(nit, (size_t(1) << 30) / per_item));
+  rc = ensure(c, c->work, per_item * batch);
+  if (rc) return rc;
+  const PairPtrs* dev = (const PairPtrs*)c->tda_items.dev.p;
+  for (size_t i0 = 0; i0 < nit; i0 += batch) {
+    const size_t ni = std::min(batch, nit - i0);
+    const size_t p0 = 2 * i0, npb = std::min(2 * ni, (size_t)np - p0);
+    launch_pair_poisson_ptrs(c->n, fp64, true, dev + p0, (int)npb, c->work.p, c->gpos, c->tw,
+                             c->stream, c->tr());
+  }
+  return hip_check(hipGetLastError());
+}
 }  // namespace
 
 void ace::trace_begin(Trace* t, int id) {
@@ -265,6 +287,11 @@ int exchange_apply_direct(ace_ctx* c, const void* phi, int n, const void* psi, i
 
 int tda_coupling(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, int nv,
                  int delta_M, double* C_out) {
+  return tdhf_coupling(c, phi_occ, no, phi_virt, nv, delta_M, C_out, nullptr);
+}
+
+int tdhf_coupling(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, int nv,
+                  int delta_M, double* C_out, double* B_out) {
   if (!c || !phi_occ || !phi_virt || !C_out || no < 1 || nv < 1) return ACE_ERR_INVALID;
   if (delta_M != 0 && delta_M != 2) return ACE_ERR_INVALID;
   if (is_cplx(c->dtype)) return ACE_ERR_UNSUPPORTED;
@@ -292,28 +319,54 @@ int tda_coupling(ace_ctx* c, const void* phi_occ, int no, const void* phi_virt, 
       t.b = (const char*)phi_occ + eb * ng * b;
       t.v = v_oo + eb * ng * q;
     }
-  rc = upload_blob(c->stream, c->tda_items, items.data(), sizeof(PairPtrs) * items.size());
+  rc = solve_pair_list(c, items);
   if (rc) return rc;
-  {
-    const bool fp64 = is_fp64(c->dtype);
-    const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
-    const size_t nit = ((size_t)np + 1) / 2;  // real: two pairs per complex FFT
-    const size_t batch = std::max<size_t>(1, std::min<size_t>(nit, (size_t(1) << 30) / per_item));
-    rc = ensure(c, c->work, per_item * batch);
-    if (rc) return rc;
-    const PairPtrs* dev = (const PairPtrs*)c->tda_items.dev.p;
-    for (size_t i0 = 0; i0 < nit; i0 += batch) {
-      const size_t ni = std::min(batch, nit - i0);
-      const size_t p0 = 2 * i0, npb = std::min(2 * ni, (size_t)np - p0);
-      launch_pair_poisson_ptrs(c->n, fp64, true, dev + p0, (int)npb, c->work.p, c->gpos, c->tw,
-                               c->stream, c->tr());
-    }
-  }
   TdaWork tw;
   rc = ensure(c, c->tda, tda_workspace_bytes(no, nv, ng, is_fp64(c->dtype), &tw));
   if (rc) return rc;
   launch_tda(is_fp64(c->dtype), phi_occ, no, phi_virt, nv, v_ov, v_oo, ng, c->h * c->h * c->h,
-             delta_M, c->tda.p, tw, C_out, c->stream, c->tr());
+             delta_M, c->tda.p, tw, C_out, B_out, c->stream, c->tr());
+  return hip_check(hipGetLastError());
+}
+
+int uhf_coupling(ace_ctx* c, const void* occ_a, int no_a, const void* virt_a, int nv_a,
+                 const void* occ_b, int no_b, const void* virt_b, int nv_b, double* C_out,
+                 double* B_out) {
+  if (!c || !occ_a || !virt_a || !occ_b || !virt_b || !C_out || no_a < 1 || nv_a < 1 ||
+      no_b < 1 || nv_b < 1)
+    return ACE_ERR_INVALID;
+  if (is_cplx(c->dtype)) return ACE_ERR_UNSUPPORTED;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  UhfSpin sp[2] = {{occ_a, virt_a, no_a, nv_a, nullptr, nullptr},
+                   {occ_b, virt_b, no_b, nv_b, nullptr, nullptr}};
+  size_t nvol = 0;
+  for (const UhfSpin& x : sp) nvol += (size_t)x.no * x.nv + (size_t)x.no * (x.no + 1) / 2;
+  int rc = ensure(c, c->vbuf, eb * ng * nvol);
+  if (rc) return rc;
+  std::vector<PairPtrs> items;
+  items.reserve(nvol);
+  char* vp = (char*)c->vbuf.p;
+  for (UhfSpin& x : sp) {
+    x.v_ov = vp;
+    for (int j = 0; j < x.no; ++j)
+      for (int b = 0; b < x.nv; ++b) {
+        items.push_back({(const char*)x.occ + eb * ng * j, (const char*)x.virt + eb * ng * b, vp});
+        vp += eb * ng;
+      }
+    x.v_oo = vp;
+    for (int b = 0; b < x.no; ++b)
+      for (int a = 0; a <= b; ++a) {
+        items.push_back({(const char*)x.occ + eb * ng * a, (const char*)x.occ + eb * ng * b, vp});
+        vp += eb * ng;
+      }
+  }
+  rc = solve_pair_list(c, items);
+  if (rc) return rc;
+  UhfWork uw;
+  rc = ensure(c, c->tda, uhf_workspace_bytes(sp, ng, is_fp64(c->dtype), &uw));
+  if (rc) return rc;
+  launch_uhf(is_fp64(c->dtype), sp, ng, c->h * c->h * c->h, c->tda.p, uw, C_out, B_out, c->stream,
+             c->tr());
   return hip_check(hipGetLastError());
 }
 
@@ -641,6 +694,7 @@ int ace_batch_trace_read(ace_batch* b, int id, double* total_ms, long long* coun
 // orthonormalisation of each new block.  The host only steers (residual norms, block sizes).
 
 #include "linalg.hpp"
+#include "scf.hpp"
 
 extern "C" {
 
@@ -657,25 +711,26 @@ int dense_gemm(int ta, int tb, int M, int N, int K, double alpha, const double* 
   return hip_check(hipGetLastError());
 }
 
-int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
-                    const double* eps_virt, int nv, int nstates, double tol, int max_iter,
-                    double* omega_out, double* X_out, int* iterations) {
-  if (!c || !C || !eps_occ || !eps_virt || !omega_out || no < 1 || nv < 1) return ACE_ERR_INVALID;
-  const int n = no * nv, k = nstates;
-  if (k < 1 || k > 16 || k > n || !(tol > 0.0) || max_iter < 1) return ACE_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Davidson for the k lowest eigenpairs of the dense symmetric n x n device matrix A:
+// subspace products and Rayleigh-Ritz with the small dense kernels of linalg.hip, diagonal
+// correction (theta - d_i)^{-1} with d (host) the diagonal of A, canonical orthonormalisation of
+// each new block; the start vectors are the unit vectors of the k smallest d_i.
+int davidson_core(ace_ctx* c, const double* Ain, const std::vector<double>& d, int n, int k,
+                  double tol, int max_iter, double* omega_out, double* X_out, int* iterations) {
   hipStream_t s = c->stream;
   const int mmax = std::min(n, std::min(kJacobiMax, std::max(4 * k, 2 * k + 8)));
-  std::vector<double> d(n);
-  for (int i = 0; i < no; ++i)
-    for (int a = 0; a < nv; ++a) d[(size_t)i * nv + a] = eps_virt[a] - eps_occ[i];
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
   std::vector<double> v0((size_t)k * n, 0.0);
   for (int j = 0; j < k; ++j) v0[(size_t)j * n + order[j]] = 1.0;
-  DevBuf A, dd, V, AV, H, th, S, X, AX, R, T, G, nrm, Sm, lam, U, Y, sc;
+  DevBuf dd, V, AV, H, th, S, X, AX, R, T, G, nrm, Sm, lam, U, Y, sc;
   int rc = ACE_OK;
-  for (auto pr : {std::make_pair(&A, (size_t)n * n), std::make_pair(&dd, (size_t)n),
+  for (auto pr : {std::make_pair(&dd, (size_t)n),
                   std::make_pair(&V, (size_t)mmax * n), std::make_pair(&AV, (size_t)mmax * n),
                   std::make_pair(&H, (size_t)mmax * mmax), std::make_pair(&th, (size_t)mmax),
                   std::make_pair(&S, (size_t)mmax * mmax), std::make_pair(&X, (size_t)k * n),
@@ -689,8 +744,8 @@ int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
   if (hipMemcpyAsync(dd.p, d.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(V.p, v0.data(), sizeof(double) * v0.size(), hipMemcpyHostToDevice, s) != hipSuccess)
     return ACE_ERR_HIP;
-  launch_add_diag(C, dd.p, n, A.p, s);
-  launch_dgemm(0, 1, k, n, n, 1.0, V.p, n, A.p, n, 0.0, AV.p, n, s);
+  const double* Ap = Ain;
+  launch_dgemm(0, 1, k, n, n, 1.0, V.p, n, Ap, n, 0.0, AV.p, n, s);
   int m = k, it = 0;
   bool done = false;
   std::vector<double> h_n(k), h_l(k);
@@ -744,7 +799,7 @@ int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
     if (hipMemcpyAsync(V.p + (size_t)m * n, Y.p + (size_t)first * n, sizeof(double) * kk * n,
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
       return ACE_ERR_HIP;
-    launch_dgemm(0, 1, kk, n, n, 1.0, V.p + (size_t)m * n, n, A.p, n, 0.0, AV.p + (size_t)m * n, n, s);
+    launch_dgemm(0, 1, kk, n, n, 1.0, V.p + (size_t)m * n, n, Ap, n, 0.0, AV.p + (size_t)m * n, n, s);
     m += kk;
     if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;  // host vectors reused
   }
@@ -754,6 +809,85 @@ int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
     return ACE_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;
   if (iterations) *iterations = done ? it : -it;
+  return hip_check(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int tda_excitations(ace_ctx* c, const double* C, const double* eps_occ, int no,
+                    const double* eps_virt, int nv, int nstates, double tol, int max_iter,
+                    double* omega_out, double* X_out, int* iterations) {
+  if (!c || !C || !eps_occ || !eps_virt || !omega_out || no < 1 || nv < 1) return ACE_ERR_INVALID;
+  std::vector<double> d((size_t)no * nv);
+  for (int i = 0; i < no; ++i)
+    for (int a = 0; a < nv; ++a) d[(size_t)i * nv + a] = eps_virt[a] - eps_occ[i];
+  return tda_excitations_diag(c, C, d.data(), no * nv, nstates, tol, max_iter, omega_out, X_out,
+                              iterations);
+}
+
+int tda_excitations_diag(ace_ctx* c, const double* C, const double* d, int n, int nstates,
+                         double tol, int max_iter, double* omega_out, double* X_out,
+                         int* iterations) {
+  if (!c || !C || !d || !omega_out || n < 1) return ACE_ERR_INVALID;
+  if (nstates < 1 || nstates > 16 || nstates > n || !(tol > 0.0) || max_iter < 1)
+    return ACE_ERR_INVALID;
+  DevBuf A, dd;
+  int rc = A.alloc((size_t)n * n);
+  if (!rc) rc = dd.alloc((size_t)n);
+  if (rc) return rc;
+  if (hipMemcpyAsync(dd.p, d, sizeof(double) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return ACE_ERR_HIP;
+  launch_add_diag(C, dd.p, n, A.p, c->stream);
+  std::vector<double> dv(d, d + n);
+  return davidson_core(c, A.p, dv, n, nstates, tol, max_iter, omega_out, X_out, iterations);
+}
+
+int tdhf_excitations(ace_ctx* c, const double* C, const double* B, const double* d, int n,
+                     int nstates, double tol, int max_iter, double* omega_out, double* XpY_out,
+                     int* iterations) {
+  if (!c || !C || !B || !d || !omega_out || n < 1) return ACE_ERR_INVALID;
+  if (nstates < 1 || nstates > 16 || nstates > n || !(tol > 0.0) || max_iter < 1)
+    return ACE_ERR_INVALID;
+  hipStream_t s = c->stream;
+  DevBuf P, M, T1, H, dd, Z, sc;
+  int rc = ACE_OK;
+  for (auto pr : {std::make_pair(&P, (size_t)n * n), std::make_pair(&M, (size_t)n * n),
+                  std::make_pair(&T1, (size_t)n * n), std::make_pair(&H, (size_t)n * n),
+                  std::make_pair(&dd, (size_t)n), std::make_pair(&Z, (size_t)nstates * n),
+                  std::make_pair(&sc, (size_t)nstates)})
+    if (!rc) rc = pr.first->alloc(pr.second);
+  if (rc) return rc;
+  int* info = c->status + 2;  // scratch word of the status area
+  if (hipMemsetAsync(info, 0, sizeof(int), s) != hipSuccess ||
+      hipMemcpyAsync(dd.p, d, sizeof(double) * n, hipMemcpyHostToDevice, s) != hipSuccess)
+    return ACE_ERR_HIP;
+  // (A + B)(X + Y) = omega (X - Y), (A - B)(X - Y) = omega (X + Y): with A - B = L L^T,
+  // L^T (A + B) L z = omega^2 z, X + Y = L z / sqrt(omega)  (Hermitian half-size form, Sec. 2)
+  launch_pm(C, B, dd.p, n, P.p, M.p, s);
+  launch_potrf(M.p, n, n, info, s);
+  launch_dgemm(1, 0, n, n, n, 1.0, M.p, n, P.p, n, 0.0, T1.p, n, s);
+  launch_dgemm(0, 0, n, n, n, 1.0, T1.p, n, M.p, n, 0.0, H.p, n, s);
+  std::vector<double> dh(n);
+  int hinfo = 0;
+  DevBuf hd;
+  rc = hd.alloc((size_t)n);
+  if (rc) return rc;
+  launch_diag(H.p, n, n, hd.p, s);
+  if (hipMemcpyAsync(dh.data(), hd.p, sizeof(double) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ACE_ERR_HIP;
+  if (hinfo) return ACE_ERR_NOT_POSDEF;  // A - B not positive definite: unstable reference
+  rc = davidson_core(c, H.p, dh, n, nstates, tol, max_iter, omega_out, Z.p, iterations);
+  if (rc) return rc;
+  launch_sqrt_and_inv(omega_out, sc.p, nstates, s);
+  if (XpY_out) {
+    launch_dgemm(0, 1, nstates, n, n, 1.0, Z.p, n, M.p, n, 0.0, XpY_out, n, s);
+    launch_scale_rows(XpY_out, sc.p, n, nstates, s);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return ACE_ERR_HIP;  // scratch freed on return
   return hip_check(hipGetLastError());
 }
 

@@ -4,6 +4,8 @@
 // eigensolver for symmetric matrices of order <= 64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "linalg.hpp"
 
 namespace ace {
@@ -247,6 +249,103 @@ __global__ void k_scale_rows(double* __restrict__ Y, const double* __restrict__ 
     Y[e] *= s[e / n];
 }
 
+// P = C + B + diag(d), M = C - B + diag(d) (n x n row-major)
+__global__ void k_pm(const double* __restrict__ C, const double* __restrict__ B,
+                     const double* __restrict__ d, int n, double* __restrict__ P,
+                     double* __restrict__ M) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const double dg = i == j ? d[i] : 0.0;
+    P[e] = C[e] + B[e] + dg;
+    M[e] = C[e] - B[e] + dg;
+  }
+}
+
+// Blocked Cholesky A = L L^T (lower, in place), panel width kPanel.
+constexpr int kPanel = 64;
+
+// factor the diagonal block A[j0:j0+nb, j0:j0+nb] in LDS; info[0] = first failing column + 1
+__global__ __launch_bounds__(256) void k_potrf_panel(double* __restrict__ A, int lda, int j0,
+                                                     int nb, int* __restrict__ info) {
+  __shared__ double a[kPanel][kPanel + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    a[i][j] = A[(size_t)(j0 + i) * lda + j0 + j];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (threadIdx.x == 0) {
+      double p = a[j][j];
+      if (!(p > 0.0)) {
+        if (info && info[0] == 0) info[0] = j0 + j + 1;
+        p = 1.0;
+      }
+      a[j][j] = sqrt(p);
+    }
+    __syncthreads();
+    const double inv = 1.0 / a[j][j];
+    for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) a[i][j] *= inv;
+    __syncthreads();
+    const int m = nb - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    if (j <= i) A[(size_t)(j0 + i) * lda + j0 + j] = a[i][j];
+  }
+}
+
+// rows r >= j0 + nb of the panel columns: solve X L11^T = A21 by forward substitution
+__global__ __launch_bounds__(256) void k_trsm_rows(double* __restrict__ A, int lda, int j0, int nb,
+                                                   int n) {
+  __shared__ double l[kPanel][kPanel + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    l[i][j] = j <= i ? A[(size_t)(j0 + i) * lda + j0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int r = j0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double* row = A + (size_t)r * lda + j0;
+  double x[kPanel];
+#pragma unroll
+  for (int k = 0; k < kPanel; ++k) {
+    if (k < nb) {
+      double sv = row[k];
+#pragma unroll
+      for (int q = 0; q < k; ++q) sv -= x[q] * l[k][q];
+      x[k] = sv / l[k][k];
+    } else {
+      x[k] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPanel; ++k)
+    if (k < nb) row[k] = x[k];
+}
+
+__global__ void k_zero_upper(double* __restrict__ A, int n, int lda) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n * n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) A[(size_t)i * lda + j] = 0.0;
+  }
+}
+
+// v[i] = sqrt(max(v[i], 0)); s[i] = 1 / sqrt(v[i]) after the root (0 where v = 0)
+__global__ void k_sqrt_and_inv(double* __restrict__ v, double* __restrict__ s, int k) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const double w = sqrt(fmax(v[i], 0.0));
+    v[i] = w;
+    s[i] = w > 0.0 ? 1.0 / sqrt(w) : 0.0;
+  }
+}
+
 }  // namespace
 
 void launch_add_diag(const double* C, const double* d, int n, double* A, hipStream_t s) {
@@ -276,6 +375,34 @@ void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const doubl
 void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
                    int max_sweeps, double tol, hipStream_t s) {
   k_jacobi<<<1, JT, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol);
+}
+
+}  // namespace ace
+
+namespace ace {
+
+void launch_pm(const double* C, const double* B, const double* d, int n, double* P, double* M,
+               hipStream_t s) {
+  k_pm<<<512, 256, 0, s>>>(C, B, d, n, P, M);
+}
+
+void launch_potrf(double* A, int n, int lda, int* info, hipStream_t s) {
+  for (int j0 = 0; j0 < n; j0 += kPanel) {
+    const int nb = std::min(kPanel, n - j0);
+    k_potrf_panel<<<1, 256, 0, s>>>(A, lda, j0, nb, info);
+    const int m = n - j0 - nb;
+    if (m > 0) {
+      k_trsm_rows<<<(m + 255) / 256, 256, 0, s>>>(A, lda, j0, nb, n);
+      const double* l21 = A + (size_t)(j0 + nb) * lda + j0;
+      launch_dgemm(0, 1, m, m, nb, -1.0, l21, lda, l21, lda, 1.0,
+                   A + (size_t)(j0 + nb) * lda + j0 + nb, lda, s);
+    }
+  }
+  k_zero_upper<<<512, 256, 0, s>>>(A, n, lda);
+}
+
+void launch_sqrt_and_inv(double* v, double* sinv, int k, hipStream_t s) {
+  k_sqrt_and_inv<<<1, 64, 0, s>>>(v, sinv, k);
 }
 
 }  // namespace ace

@@ -23,4 +23,13 @@ void launch_dav_precond(const double* R, const double* d, const double* theta, i
                         double* T, hipStream_t s);
 void launch_scale_rows(double* Y, const double* sc, int n, int k, hipStream_t s);
 
+// full TDHF helpers: P = C + B + diag(d), M = C - B + diag(d)
+void launch_pm(const double* C, const double* B, const double* d, int n, double* P, double* M,
+               hipStream_t s);
+// blocked Cholesky A = L L^T in place (lower; upper set to zero); info[0] (device, zeroed by
+// the caller) = first non-positive pivot + 1
+void launch_potrf(double* A, int n, int lda, int* info, hipStream_t s);
+// v <- sqrt(max(v, 0)), sinv <- 1 / sqrt(v) of the new v (k values)
+void launch_sqrt_and_inv(double* v, double* sinv, int k, hipStream_t s);
+
 }  // namespace ace

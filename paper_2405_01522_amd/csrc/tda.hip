@@ -276,10 +276,34 @@ __global__ void k_tda_assemble(const double* __restrict__ cj, const double* __re
   }
 }
 
+// CJ[row][col] from the (possibly upper-tile-only) storage, symmetrised as in k_tda_assemble
+__device__ __forceinline__ double cj_get(const double* __restrict__ cj, size_t nov, size_t row,
+                                        size_t col, int tile) {
+  const int tr = tile > 0 ? (int)row / tile : 0, tc = tile > 0 ? (int)col / tile : 0;
+  if (tr < tc) return cj[row * nov + col];
+  if (tr > tc) return cj[col * nov + row];
+  return 0.5 * (cj[row * nov + col] + cj[col * nov + row]);
+}
+
+// RHF B block for real orbitals (Eq. (3), spin-adapted Eq. (5)):
+//   B[ia][jb] = delta_M (ia|bj) - (ib|aj) = delta_M CJ[ia][jb] - CJ[ib][ja]
+__global__ void k_tdhf_b_assemble(const double* __restrict__ cj, int no, int nv, int delta_m,
+                                  double* __restrict__ b, int tile) {
+  const size_t nov = (size_t)no * nv;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nov * nov;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t row = idx / nov, col = idx % nov;
+    const int i = (int)(row / nv), a = (int)(row % nv), j = (int)(col / nv), bb = (int)(col % nv);
+    const double direct = cj_get(cj, nov, row, col, tile);
+    const double swapped = cj_get(cj, nov, (size_t)i * nv + bb, (size_t)j * nv + a, tile);
+    b[idx] = delta_m * direct - swapped;
+  }
+}
+
 template <typename T>
 void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_ov,
               const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
-              double* c_out, hipStream_t s, Trace* tr) {
+              double* c_out, double* b_out, hipStream_t s, Trace* tr) {
   const int nov = no * nv, noo = no * (no + 1) / 2, nvv = nv * nv;
   char* base = (char*)ws;
   double* pj = (double*)(base + w.off_pj);
@@ -312,6 +336,7 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
     k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj, nov);
     k_split_reduce_f32<<<rbk, 256, 0, s>>>((const float*)pk, w.nsplit, cntk, dv, ck, 0);
     k_tda_assemble<<<rbj, 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out, MT);
+    if (b_out) k_tdhf_b_assemble<<<rbj, 256, 0, s>>>(cj, no, nv, delta_m, b_out, MT);
     return;
   } else {
     {
@@ -326,6 +351,7 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
     k_split_reduce<<<rbk, 256, 0, s>>>(pk, w.nsplit, cntk, dv, ck);
   }
   k_tda_assemble<<<rbj, 256, 0, s>>>(cj, ck, no, nv, delta_m, c_out, 0);
+  if (b_out) k_tdhf_b_assemble<<<rbj, 256, 0, s>>>(cj, no, nv, delta_m, b_out, 0);
 }
 
 // D[c][i*nv + a] = dV sum_r phi_i(r) x_c(r) phi_a(r), x_c = (k_c - (n-1)/2) h: one block per
@@ -425,11 +451,150 @@ size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
 
 void launch_tda(bool fp64, const void* occ, int no, const void* virt, int nv, const void* v_ov,
                 const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
-                double* c_out, hipStream_t s, Trace* tr) {
+                double* c_out, double* b_out, hipStream_t s, Trace* tr) {
   if (fp64)
-    tda_impl<double>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, s, tr);
+    tda_impl<double>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, b_out, s, tr);
   else
-    tda_impl<float>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, s, tr);
+    tda_impl<float>(occ, no, virt, nv, v_ov, v_oo, ng, dv, delta_m, ws, w, c_out, b_out, s, tr);
+}
+
+// ---- UHF blocks (Eqs. (4), (5)) over two spin channels --------------------------------------
+
+namespace {
+
+// split-K contraction out[m][n] = scale * sum_r A(m, r) B(n, r) over the full M x N grid
+template <typename T>
+void gemm_full(Op<T> A, int M, Op<T> B, int N, size_t ng, const UhfWork& w, void* part,
+               double scale, double* out, hipStream_t s) {
+  const size_t cnt = (size_t)M * N;
+  const unsigned rb = (unsigned)std::min<size_t>(4096, (cnt + 255) / 256);
+  if constexpr (sizeof(T) == 4) {
+    dim3 g((M + MT - 1) / MT, (N + MT - 1) / MT, w.nsplit);
+    if (ng % 4 == 0)
+      k_gemm_nt_mfma<true><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+    else
+      k_gemm_nt_mfma<false><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+    k_split_reduce_f32<<<rb, 256, 0, s>>>((const float*)part, w.nsplit, cnt, scale, out, 0);
+  } else {
+    dim3 g((M + BM - 1) / BM, (N + BN - 1) / BN, w.nsplit);
+    k_gemm_nt<T><<<g, kThreads, 0, s>>>(A, M, B, N, ng, w.kchunk, (double*)part);
+    k_split_reduce<<<rb, 256, 0, s>>>((const double*)part, w.nsplit, cnt, scale, out);
+  }
+}
+
+struct UhfDev {
+  const double* g1[2][2];  // G1[s][t][ia][jb] = dV sum_r (phi_i phi_a)_s v^t_jb
+  const double* g2[2];     // G2[s][pair(i,j)][a nv + b] = dV sum_r v^s_ij (phi_a phi_b)_s
+  int no[2], nv[2], n0;    // n0 = alpha transitions
+};
+
+__device__ __forceinline__ double uhf_g1(const UhfDev& u, int s, int t, int x, int y) {
+  const int nt = u.no[t] * u.nv[t];
+  return 0.5 * (u.g1[s][t][(size_t)x * nt + y] + u.g1[t][s][(size_t)y * (u.no[s] * u.nv[s]) + x]);
+}
+
+// C = (ia||jb) - diag part, B = (ia||bj) (real orbitals: (ia|bj) = (ia|jb), (ib|aj) = (ib|ja))
+__global__ void k_uhf_assemble(UhfDev u, int n, double* __restrict__ c, double* __restrict__ b) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(idx / n), col = (int)(idx % n);
+    const int s = row < u.n0 ? 0 : 1, t = col < u.n0 ? 0 : 1;
+    const int x = row - (s ? u.n0 : 0), y = col - (t ? u.n0 : 0);
+    const double coul = uhf_g1(u, s, t, x, y);
+    double cval = coul, bval = coul;
+    if (s == t) {
+      const int nv = u.nv[s];
+      const int i = x / nv, a = x % nv, j = y / nv, bb = y % nv;
+      const int lo = i < j ? i : j, hi = i < j ? j : i;
+      const double* g2 = u.g2[s] + ((size_t)hi * (hi + 1) / 2 + lo) * (size_t)nv * nv;
+      cval -= 0.5 * (g2[(size_t)a * nv + bb] + g2[(size_t)bb * nv + a]);
+      bval -= uhf_g1(u, s, s, i * nv + bb, j * nv + a);
+    }
+    c[idx] = cval;
+    if (b) b[idx] = bval;
+  }
+}
+
+template <typename T>
+void uhf_impl(const UhfSpin* sp, size_t ng, double dv, void* ws, const UhfWork& w, double* c_out,
+              double* b_out, hipStream_t s, Trace* tr) {
+  char* base = (char*)ws;
+  void* part = base + w.off_part;
+  double* g1[2][2];
+  double* g2[2];
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 2; ++b) g1[a][b] = (double*)(base + w.off_g1[a][b]);
+    g2[a] = (double*)(base + w.off_g2[a]);
+  }
+  {
+    TraceScope ts(tr, TR_TDA_GEMM);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        Op<T> rho{(const T*)sp[a].occ, (const T*)sp[a].virt, sp[a].nv};
+        Op<T> vt{(const T*)sp[b].v_ov, nullptr, 1};
+        gemm_full<T>(rho, sp[a].no * sp[a].nv, vt, sp[b].no * sp[b].nv, ng, w, part, dv, g1[a][b], s);
+      }
+    for (int a = 0; a < 2; ++a) {
+      Op<T> voo{(const T*)sp[a].v_oo, nullptr, 1};
+      Op<T> rvv{(const T*)sp[a].virt, (const T*)sp[a].virt, sp[a].nv};
+      gemm_full<T>(voo, sp[a].no * (sp[a].no + 1) / 2, rvv, sp[a].nv * sp[a].nv, ng, w, part, dv,
+                   g2[a], s);
+    }
+  }
+  UhfDev u;
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 2; ++b) u.g1[a][b] = g1[a][b];
+    u.g2[a] = g2[a];
+    u.no[a] = sp[a].no;
+    u.nv[a] = sp[a].nv;
+  }
+  u.n0 = sp[0].no * sp[0].nv;
+  const int n = u.n0 + sp[1].no * sp[1].nv;
+  const unsigned rb = (unsigned)std::min<size_t>(4096, ((size_t)n * n + 255) / 256);
+  k_uhf_assemble<<<rb, 256, 0, s>>>(u, n, c_out, b_out);
+}
+
+}  // namespace
+
+size_t uhf_workspace_bytes(const UhfSpin* sp, size_t ng, bool fp64, UhfWork* w) {
+  const size_t tile = fp64 ? BM : MT;
+  size_t maxcnt = 0, maxtiles = 0;
+  auto consider = [&](size_t m, size_t n) {
+    maxcnt = std::max(maxcnt, m * n);
+    maxtiles = std::max(maxtiles, ((m + tile - 1) / tile) * ((n + tile - 1) / tile));
+  };
+  for (int a = 0; a < 2; ++a) {
+    for (int b = 0; b < 2; ++b) consider((size_t)sp[a].no * sp[a].nv, (size_t)sp[b].no * sp[b].nv);
+    consider((size_t)sp[a].no * (sp[a].no + 1) / 2, (size_t)sp[a].nv * sp[a].nv);
+  }
+  size_t nsplit = (1024 + maxtiles - 1) / maxtiles;
+  size_t kchunk = (ng + nsplit - 1) / nsplit;
+  kchunk = ((kchunk + kSub - 1) / kSub) * kSub;
+  if (kchunk < kSub) kchunk = kSub;
+  nsplit = (ng + kchunk - 1) / kchunk;
+  w->nsplit = (int)nsplit;
+  w->kchunk = kchunk;
+  size_t off = 0;
+  w->off_part = off;
+  off += nsplit * maxcnt * sizeof(double);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      w->off_g1[a][b] = off;
+      off += (size_t)sp[a].no * sp[a].nv * sp[b].no * sp[b].nv * sizeof(double);
+    }
+  for (int a = 0; a < 2; ++a) {
+    w->off_g2[a] = off;
+    off += (size_t)sp[a].no * (sp[a].no + 1) / 2 * sp[a].nv * sp[a].nv * sizeof(double);
+  }
+  return off;
+}
+
+void launch_uhf(bool fp64, const UhfSpin* sp, size_t ng, double dv, void* ws, const UhfWork& w,
+                double* c_out, double* b_out, hipStream_t s, Trace* tr) {
+  if (fp64)
+    uhf_impl<double>(sp, ng, dv, ws, w, c_out, b_out, s, tr);
+  else
+    uhf_impl<float>(sp, ng, dv, ws, w, c_out, b_out, s, tr);
 }
 
 }  // namespace ace

@@ -97,3 +97,81 @@ def test_tda_states_config3():
     w_ref = np.linalg.eigvalsh(a)[:8]
     assert np.max(np.abs(omega.cpu().numpy() - w_ref)) < 1e-10
     assert w_ref[0] > 0.0
+
+
+# ---- full TDHF (B block), UHF, RHF = UHF ---------------------------------------------------
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("delta_m", [2, 0])
+def test_tdhf_blocks_match_oracle(prec, delta_m):
+    import paper_2405_01522_amd as ace
+    from oracle import tda
+    mol = synth.small_real(51, 12, 0.45, 3, 4)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = ace.AceContext(12, 0.45, dt)
+    c, b = ctx.tdhf_coupling(_dev(mol.phi).to(dt), _dev(mol.phi_virt).to(dt), delta_m)
+    cr = tda.coupling_block(mol.phi, mol.phi_virt, 0.45, delta_m)
+    br = tda.b_block(mol.phi, mol.phi_virt, 0.45, delta_m)
+    tol = 1e-10 if prec == "fp64" else 3e-6
+    sc = max(np.max(np.abs(cr)), np.max(np.abs(br)))
+    assert np.max(np.abs(c.cpu().numpy() - cr)) < tol * sc
+    assert np.max(np.abs(b.cpu().numpy() - br)) < tol * sc
+    assert np.array_equal(b.cpu().numpy(), b.cpu().numpy().T)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_uhf_blocks_match_oracle_open_shell(prec):
+    import paper_2405_01522_amd as ace
+    from oracle import tda
+    a = synth.small_real(61, 12, 0.45, 3, 4)
+    b = synth.small_real(62, 12, 0.45, 2, 3)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ctx = ace.AceContext(12, 0.45, dt)
+    t = lambda x: _dev(x).to(dt)
+    c, bb = ctx.uhf_coupling(t(a.phi), t(a.phi_virt), t(b.phi), t(b.phi_virt))
+    cr, br = tda.uhf_blocks(a.phi, a.phi_virt, b.phi, b.phi_virt, 0.45)
+    tol = 1e-10 if prec == "fp64" else 3e-6
+    sc = max(np.max(np.abs(cr)), np.max(np.abs(br)))
+    assert np.max(np.abs(c.cpu().numpy() - cr)) < tol * sc
+    assert np.max(np.abs(bb.cpu().numpy() - br)) < tol * sc
+
+
+def test_tdhf_excitations_match_oracle_and_rhf_equals_uhf():
+    import paper_2405_01522_amd as ace
+    from oracle import tda
+    mol = synth.small_real(71, 12, 0.45, 3, 5)
+    no, nv = 3, 5
+    ctx = ace.AceContext(12, 0.45, torch.float64)
+    occ, virt = _dev(mol.phi), _dev(mol.phi_virt)
+    de = (mol.eps_virt[None, :] - mol.eps_occ[:, None]).reshape(-1)
+    k = 6
+    res = {}
+    for dm in (2, 0):
+        c, b = ctx.tdhf_coupling(occ, virt, dm)
+        om, xpy, it = ctx.tdhf_excitations(c, b, de, k, tol=1e-9)
+        ref = tda.rpa_excitations(np.diag(de) + c.cpu().numpy(), b.cpu().numpy())
+        assert np.allclose(om.cpu().numpy(), ref[:k], atol=1e-9), (om, ref[:k])
+        # X+Y solves the first Casida equation pair: (A-B)(A+B)(X+Y) = omega^2 (X+Y)
+        am = np.diag(de) + c.cpu().numpy()
+        bm = b.cpu().numpy()
+        v = xpy.cpu().numpy()
+        lhs = (am - bm) @ (am + bm) @ v.T
+        assert np.max(np.abs(lhs - v.T * om.cpu().numpy() ** 2)) < 1e-7 * np.max(np.abs(lhs))
+        # B = 0 in the same solver gives the Tamm-Dancoff eigenvalues
+        tda_om, _, _ = ctx.tda_excitations_diag(c, de, k, tol=1e-9)
+        zom, _, _ = ctx.tdhf_excitations(c, torch.zeros_like(b), de, k, tol=1e-9)
+        assert np.allclose(zom.cpu().numpy(), tda_om.cpu().numpy(), atol=1e-9)
+        res[dm] = np.linalg.eigvalsh(am)[:], ref
+    # closed-shell UHF: union of singlet and triplet spectra (TDA and full TDHF)
+    cu, bu = ctx.uhf_coupling(occ, virt, occ, virt)
+    du = np.concatenate([de, de])
+    om_u, _, _ = ctx.tda_excitations_diag(cu, du, 8, tol=1e-9)
+    union_tda = np.sort(np.concatenate([res[2][0], res[0][0]]))[:8]
+    assert np.allclose(om_u.cpu().numpy(), union_tda, atol=1e-8)
+    om_r, _, _ = ctx.tdhf_excitations(cu, bu, du, 8, tol=1e-9)
+    union_rpa = np.sort(np.concatenate([res[2][1], res[0][1]]))[:8]
+    assert np.allclose(om_r.cpu().numpy(), union_rpa, atol=1e-8)
