@@ -300,7 +300,8 @@ def run_scf(train_seeds=(1051, 1052, 1053, 1054, 1055), eval_seed=105, pairs=100
         out[name] = dict(seconds=time.perf_counter() - t0, iterations=r["iterations"],
                          eig_steps=r["eig_steps"], converged=r["converged"],
                          energy=r["total"], terms={t: r[t] for t in ace.ENERGY_TERMS[1:]},
-                         density_error=r["density_error"])
+                         density_error=r["density_error"],
+                         eigenvalues=[float(x) for x in r["eigenvalues"]])
         finals[name] = phi
     # 4. eigensolver alone on the converged Hamiltonian (non-self-consistent run): steps from
     # the core guess to residuals below 1e-4 with each preconditioner
@@ -316,6 +317,43 @@ def run_scf(train_seeds=(1051, 1052, 1053, 1054, 1055), eval_seed=105, pairs=100
         ev, rn, st = ctx.fock_lowest_states(vloc, phi, xi=xi, opts=eo)
         torch.cuda.synchronize()
         eig_only[name] = dict(steps=st, seconds=time.perf_counter() - t0, max_residual=float(rn.max()))
+    # 5. excited states on top: unoccupied orbitals (ACE over occupied + unoccupied), the
+    # singlet TDA and full TDHF blocks, Davidson, oscillator strengths and the spectrum
+    pipe = {}
+    nvirt, nbuf = 16, 4  # 16 unoccupied orbitals kept, 4 buffer states above them
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi_all = tensor(_scf_start(s, nvirt + nbuf, eval_seed + 7))
+    ev_u, rn_u, outer_u, steps_u = ctx.unocc_states(vloc, phi_c, psi_all,
+                                                    opts=ace.eig_opts(max_steps=10, tol=1e-4),
+                                                    max_outer=80, nconv=nvirt)
+    torch.cuda.synchronize()
+    psi = psi_all[:nvirt].contiguous()
+    ev_u = ev_u[:nvirt]
+    pipe["unoccupied"] = dict(states=nvirt, buffer_states=nbuf, seconds=time.perf_counter() - t0,
+                              outer=outer_u, steps=steps_u, max_residual=float(rn_u[:nvirt].max()),
+                              lowest=float(ev_u[0]), highest=float(ev_u[-1]))
+    eps_occ = np.asarray(out["kinetic"].get("eigenvalues", []), dtype=np.float64)
+    t0 = time.perf_counter()
+    c_s, b_s = ctx.tdhf_coupling(phi_c, psi, 2)
+    torch.cuda.synchronize()
+    pipe["coupling_seconds"] = time.perf_counter() - t0
+    de = (ev_u[None, :] - eps_occ[:, None]).reshape(-1)
+    t0 = time.perf_counter()
+    om_t, x_t, it_t = ctx.tda_excitations_diag(c_s, de, 8, tol=1e-7)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    om_r, xpy_r, it_r = ctx.tdhf_excitations(c_s, b_s, de, 8, tol=1e-7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f_t, _ = ctx.tda_oscillator_strengths(phi_c, psi, x_t, om_t)
+    f_r, _ = ctx.tda_oscillator_strengths(phi_c, psi, xpy_r, om_r)
+    torch.cuda.synchronize()
+    pipe.update(tda=dict(omega_ha=om_t.cpu().tolist(), f=f_t.cpu().tolist(), iterations=it_t,
+                         seconds=t1 - t0),
+                full_tdhf=dict(omega_ha=om_r.cpu().tolist(), f=f_r.cpu().tolist(), iterations=it_r,
+                               seconds=t2 - t1),
+                transitions=int(de.size))
     res = dict(workload="C5: 64^3 box h=0.2 bohr, 16 doubly occupied orbitals, 8 soft nuclei "
                         "(seed %d); ACE rebuilt each SCF iteration; states mixing 0.3; "
                         "stop at density error 1e-6 and residuals 1e-4" % eval_seed,
@@ -323,7 +361,7 @@ def run_scf(train_seeds=(1051, 1052, 1053, 1054, 1055), eval_seed=105, pairs=100
                training=dict(systems=runs, pairs=count, collect_s=t_collect, steps=train_steps,
                              batch=batch, lr=lr, seconds=t_train, loss_first=float(hist[:10].mean()),
                              loss_last=float(hist[-50:].mean()), rel_mse_first64=fit),
-               scf=out, eig_only_converged_hamiltonian=eig_only,
+               scf=out, eig_only_converged_hamiltonian=eig_only, excited_states=pipe,
                energy_diff_learned_vs_kinetic=abs(out["learned"]["energy"] - out["kinetic"]["energy"]))
     if oracle_check:
         from oracle import poisson, scf as oscf

@@ -391,14 +391,14 @@ int fock_lowest_states(ace_ctx* ctx, const void* v_local, const void* xi, int nx
  * F = T + v_local + K[phi_occ] is fixed; each outer iteration rebuilds ACE over the occupied
  * and the current unoccupied orbitals (ace_build_targets) and takes up to opts->max_steps
  * LOBPCG steps for the nv lowest states orthogonal to the occupied ones (phi_occ must be
- * converged, dV-orthonormal eigenvectors of F).  Stops when the residuals measured right after
- * a rebuild -- where K_ACE equals K on the current vectors -- are all below opts->tol, or
- * after max_outer rebuilds.  psi: nv start vectors (device), overwritten by the unoccupied
- * orbitals; eigval, resnorm (host, nv), *outer, *steps (host) may be NULL.  no + nv <=
- * ACE_MAX_ORBITALS.  Synchronises.
+ * converged, dV-orthonormal eigenvectors of F).  Stops when the residuals of the lowest nconv
+ * states (0: all nv; the others are buffer states) measured right after a rebuild -- where
+ * K_ACE equals K on the current vectors -- are below opts->tol, or after max_outer rebuilds.
+ * psi: nv start vectors (device), overwritten by the unoccupied orbitals; eigval, resnorm
+ * (host, nv), *outer, *steps (host) may be NULL.  no + nv <= ACE_MAX_ORBITALS.  Synchronises.
  */
 int unocc_states(ace_ctx* ctx, const void* v_local, const void* phi_occ, int no, void* psi,
-                 int nv, const ace_eig_opts* opts, int max_outer, double* eigval,
+                 int nv, int nconv, const ace_eig_opts* opts, int max_outer, double* eigval,
                  double* resnorm, int* outer, int* steps);
 
 /* Energy terms of k doubly occupied orbitals: energy[5] (host) = total, kinetic, external,

@@ -61,7 +61,7 @@ SIGNATURES = {
     "uhf_coupling": (_I, [_P, _P, _I, _P, _I, _P, _I, _P, _I, _P, _P]),
     "tda_excitations_diag": (_I, [_P, _P, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),
     "tdhf_excitations": (_I, [_P, _P, _P, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),
-    "unocc_states": (_I, [_P, _P, _P, _I, _P, _I, _P, _I, _P, _P, ctypes.POINTER(_I),
+    "unocc_states": (_I, [_P, _P, _P, _I, _P, _I, _I, _P, _I, _P, _P, ctypes.POINTER(_I),
                           ctypes.POINTER(_I)]),
     "scf_run": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "precond_targets": (_I, [_P, _P, _I, _P, _I]),

@@ -328,9 +328,10 @@ class AceContext:
                                       ctypes.c_void_p(m_out.data_ptr())), "ace_build_targets")
         return xi_out, m_out
 
-    def unocc_states(self, v_local, phi_occ, psi, opts=None, max_outer=50):
-        """Unoccupied orbitals of the fixed Hamiltonian (psi overwritten).  Returns
-        (eigenvalues, residual norms, outer rebuilds, eigensolver steps)."""
+    def unocc_states(self, v_local, phi_occ, psi, opts=None, max_outer=50, nconv=0):
+        """Unoccupied orbitals of the fixed Hamiltonian (psi overwritten); the lowest nconv
+        (0: all) must converge, the rest are buffer states.  Returns (eigenvalues, residual
+        norms, outer rebuilds, eigensolver steps)."""
         import numpy as np
         nv = psi.shape[0]
         o = opts if opts is not None else eig_opts(max_steps=10)
@@ -339,7 +340,8 @@ class AceContext:
         self._sync_stream()
         check(lib().unocc_states(self._h, self._vol(v_local, "v_local", 1),
                                  self._vol(phi_occ, "phi_occ"), phi_occ.shape[0],
-                                 self._vol(psi, "psi"), nv, ctypes.byref(o), int(max_outer),
+                                 self._vol(psi, "psi"), nv, int(nconv), ctypes.byref(o),
+                                 int(max_outer),
                                  ev.ctypes.data_as(ctypes.c_void_p),
                                  rn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(outer),
                                  ctypes.byref(steps)), "unocc_states")

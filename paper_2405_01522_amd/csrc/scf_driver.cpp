@@ -68,6 +68,7 @@ struct Eig {
   bool fp64 = false;
   size_t ng = 0, eb = 0;
   int n = 0, k = 0, mmax = 0, nw = 1;
+  int kconv = 0;  // the lowest kconv Ritz pairs decide convergence (0: all k)
   double h = 0, dv = 0;
   hipStream_t s = nullptr;
   Mem V, HV, V2, HV2, R, tmp, nin, nout;
@@ -188,9 +189,10 @@ struct Eig {
         hipStreamSynchronize(s) != hipSuccess)
       return ACE_ERR_HIP;
     double worst = 0.0;
+    const int kc = kconv > 0 ? std::min(kconv, k) : k;
     for (int j = 0; j < k; ++j) {
       h_rd[j] = std::sqrt(std::max(h_rd[j], 0.0) * dv);
-      worst = std::max(worst, h_rd[j]);
+      if (j < kc) worst = std::max(worst, h_rd[j]);
     }
     *maxres = worst;
     return ACE_OK;
@@ -383,10 +385,10 @@ int fock_lowest_states(ace_ctx* c, const void* v_local, const void* xi, int nxi,
 }
 
 int unocc_states(ace_ctx* c, const void* v_local, const void* phi_occ, int no, void* psi, int nv,
-                 const ace_eig_opts* o, int max_outer, double* eigval, double* resnorm,
-                 int* outer, int* steps) {
+                 int nconv, const ace_eig_opts* o, int max_outer, double* eigval,
+                 double* resnorm, int* outer, int* steps) {
   if (!c || !v_local || !phi_occ || !psi || no < 1 || nv < 1 || max_outer < 1 ||
-      no + nv > ACE_MAX_ORBITALS)
+      no + nv > ACE_MAX_ORBITALS || nconv < 0 || nconv > nv)
     return ACE_ERR_INVALID;
   if (!real_ctx(c)) return ACE_ERR_UNSUPPORTED;
   int rc = check_eig_opts(c, o);
@@ -395,6 +397,7 @@ int unocc_states(ace_ctx* c, const void* v_local, const void* phi_occ, int no, v
   rc = e.init(c, nv, o->precond == ACE_PRECOND_NET, no);
   if (rc) return rc;
   e.lock = phi_occ;
+  e.kconv = nconv;
   const int nt = no + nv;
   const size_t vb = elem_bytes(c->dtype) * c->ng;
   hipStream_t s = c->stream;

@@ -391,7 +391,9 @@ def test_unoccupied_states_match_direct_operator():
     vloc = v + ctx.hartree_potential(ctx.scf_density(phi))
     psi = _t(_orthonormal(np.random.default_rng(8), nv, s.n, s.h), dt)
     ev, rn, outer, steps = ctx.unocc_states(vloc, phi, psi,
-                                            opts=ace.eig_opts(max_steps=20, tol=1e-6), max_outer=60)
+                                            opts=ace.eig_opts(max_steps=20, tol=1e-6), max_outer=60,
+                                            nconv=nchk)
+    assert outer < 60
     assert np.all(rn[:nchk] < 1e-6), (rn, outer, steps)
     p = phi.cpu().numpy()
     khat = poisson.kernel_hat(s.n, s.h)
