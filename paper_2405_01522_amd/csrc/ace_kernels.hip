@@ -112,7 +112,10 @@ __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng) {
 // are summed in LDS in a fixed order; one FP64 partial per workgroup: part[o][block].
 // Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A[i][k] in lane i + 16k,
 // B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4.
-constexpr int kGramChunk = 64;                  // points per wavefront
+#ifndef ACE_GRAM_CHUNK
+#define ACE_GRAM_CHUNK 64
+#endif
+constexpr int kGramChunk = ACE_GRAM_CHUNK;      // points per wavefront (multiple of 16)
 constexpr int kGramWaves = kThreads / 64;       // wavefronts per workgroup
 constexpr int kGramPoints = kGramChunk * kGramWaves;
 
@@ -127,7 +130,35 @@ __device__ __forceinline__ void split_ri(double v, double& r, double& i) { r = v
 template <typename T>
 __device__ __forceinline__ void split_ri(C2<T> v, double& r, double& i) { r = v.r; i = v.i; }
 
-template <typename E, typename S>
+// Four consecutive elements r0 .. r0+3 of a row (r0 a multiple of 4).  VEC: the row length
+// is a multiple of 4, so the group is 16-byte aligned and wholly inside or outside the row;
+// it is loaded with vector instructions (a group past the end reads the last group).
+template <typename E, bool VEC>
+__device__ __forceinline__ void load4(const E* __restrict__ row, size_t r0, size_t ng, E* out) {
+  if constexpr (VEC && sizeof(E) <= 8) {
+    const size_t g0 = r0 < ng ? r0 : ng - 4;
+    const float4* p = reinterpret_cast<const float4*>(row + g0);
+    if constexpr (sizeof(E) == 4) {
+      const float4 v = p[0];
+      const float t[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[s] = *reinterpret_cast<const E*>(&t[s]);
+    } else {
+      const float4 v0 = p[0], v1 = p[1];
+      const float t[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) out[s] = *reinterpret_cast<const E*>(&t[2 * s]);
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const size_t r = r0 + s;
+      out[s] = row[r < ng ? r : ng - 1];
+    }
+  }
+}
+
+template <typename E, typename S, int TB, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   typedef typename Elem<E>::wide W;
   const GramArgs ga = src.get(blockIdx.z);
@@ -135,76 +166,86 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   const E* __restrict__ B = (const E*)ga.B;
   const int na = ga.na, nb = ga.nb;
   W* __restrict__ part = (W*)ga.part;
-  if ((int)blockIdx.y >= ((na + 15) / 16) * ((nb + 15) / 16)) return;  // tile beyond this system
+  const int tiles_l = (nb + 15) / 16, groups_l = (tiles_l + TB - 1) / TB;
+  if ((int)blockIdx.y >= ((na + 15) / 16) * groups_l) return;  // tile beyond this system
   constexpr bool CPLX = Elem<E>::cplx;
   constexpr int NQ = kGramChunk / 16;
   __shared__ W red[kGramWaves][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int tiles_l = (nb + 15) / 16;
-  const int k0 = (blockIdx.y / tiles_l) * 16, l0 = (blockIdx.y % tiles_l) * 16;
+  const int k0 = (blockIdx.y / groups_l) * 16, lg0 = (blockIdx.y % groups_l) * 16 * TB;
   const int li = lane & 15, g = lane >> 4;
-  const int ka = k0 + li, lb = l0 + li;
+  const int ka = k0 + li;
   // loads are unconditional (clamped row and point) so they issue back to back; values
   // outside the matrices are zeroed afterwards
   const E* ra = A + (size_t)(ka < na ? ka : na - 1) * ng;
-  const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
   const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * kGramChunk;
-  E av[NQ][4], bv[NQ][4];
+  E av[NQ][4];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const size_t r = start + 16 * q + 4 * g + s;
-      const size_t rc = r < ng ? r : ng - 1;
-      av[q][s] = ra[rc];
-      bv[q][s] = rb[rc];
-    }
+  for (int q = 0; q < NQ; ++q) load4<E, VEC>(ra, start + 16 * q + 4 * g, ng, av[q]);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const size_t r = start + 16 * q + 4 * g + s;
       if (!(ka < na && r < ng)) av[q][s] = e_zero<E>();
-      if (!(lb < nb && r < ng)) bv[q][s] = e_zero<E>();
     }
-  // conj(a) b with c = ar, d = -ai, e = br, f = bi: three real contractions (Gauss)
-  //   t1 = e (c + d), t2 = c (f - e), t3 = d (e + f);  re = t1 - t3, im = t1 + t2
-  gf64x4 t1 = {}, t2 = {}, t3 = {};
+  // the A tile is reused for TB consecutive B tiles (each A element is read once per block)
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int t = 0; t < TB; ++t) {
+    const int l0 = lg0 + 16 * t;
+    if (l0 >= nb) break;  // uniform
+    const int lb = l0 + li;
+    const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
+    E bv[NQ][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      double ar, ai, br, bi;
-      split_ri(av[q][s], ar, ai);
-      split_ri(bv[q][s], br, bi);
-      if constexpr (CPLX) {
-        t1 = mma64(ar - ai, br, t1);
-        t2 = mma64(ar, bi - br, t2);
-        t3 = mma64(-ai, br + bi, t3);
-      } else {
-        t1 = mma64(ar, br, t1);
+    for (int q = 0; q < NQ; ++q) load4<E, VEC>(rb, start + 16 * q + 4 * g, ng, bv[q]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const size_t r = start + 16 * q + 4 * g + s;
+        if (!(lb < nb && r < ng)) bv[q][s] = e_zero<E>();
       }
-    }
+    // conj(a) b with c = ar, d = -ai, e = br, f = bi: three real contractions (Gauss)
+    //   t1 = e (c + d), t2 = c (f - e), t3 = d (e + f);  re = t1 - t3, im = t1 + t2
+    gf64x4 t1 = {}, t2 = {}, t3 = {};
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int t = (g + 4 * e) * 16 + li;  // tile element (row g + 4e, column li)
-    W v;
-    if constexpr (CPLX) {
-      v.r = t1[e] - t3[e];
-      v.i = t1[e] + t2[e];
-    } else {
-      v = t1[e];
-    }
-    red[wave][t] = v;
-  }
-  __syncthreads();
-  const int t = threadIdx.x;  // 256 threads, 256 tile elements
-  const int k = k0 + t / 16, l = l0 + t % 16;
-  if (k < na && l < nb) {
-    W v = red[0][t];
+    for (int q = 0; q < NQ; ++q)
 #pragma unroll
-    for (int w = 1; w < kGramWaves; ++w) v = e_add(v, red[w][t]);
-    part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = v;
+      for (int s = 0; s < 4; ++s) {
+        double ar, ai, br, bi;
+        split_ri(av[q][s], ar, ai);
+        split_ri(bv[q][s], br, bi);
+        if constexpr (CPLX) {
+          t1 = mma64(ar - ai, br, t1);
+          t2 = mma64(ar, bi - br, t2);
+          t3 = mma64(-ai, br + bi, t3);
+        } else {
+          t1 = mma64(ar, br, t1);
+        }
+      }
+    if (t > 0) __syncthreads();  // the previous tile's sums have been read
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int tt = (g + 4 * e) * 16 + li;  // tile element (row g + 4e, column li)
+      W v;
+      if constexpr (CPLX) {
+        v.r = t1[e] - t3[e];
+        v.i = t1[e] + t2[e];
+      } else {
+        v = t1[e];
+      }
+      red[wave][tt] = v;
+    }
+    __syncthreads();
+    const int th = threadIdx.x;  // 256 threads, 256 tile elements
+    const int k = k0 + th / 16, l = l0 + th % 16;
+    if (k < na && l < nb) {
+      W v = red[0][th];
+#pragma unroll
+      for (int w = 1; w < kGramWaves; ++w) v = e_add(v, red[w][th]);
+      part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = v;
+    }
   }
 }
 
@@ -499,10 +540,25 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
   }
 }
 
+// ta row tiles; tb column tiles (upper bounds over the systems of a launch); the B tiles of
+// a row tile are taken two at a time for single-precision storage
 template <typename E, typename S>
-void gram_impl(S src, int ntiles, int nsys, size_t ng, int nchunks, hipStream_t s) {
-  dim3 grid(nchunks, ntiles, nsys);
-  k_gram<E, S><<<grid, kThreads, 0, s>>>(src, ng);
+void gram_impl(S src, int ta, int tb, int nsys, size_t ng, int nchunks, hipStream_t s) {
+  constexpr bool SMALL = sizeof(typename Elem<E>::real) == 4;
+  const bool vec = ng % 4 == 0;
+  if (SMALL && tb >= 2) {
+    dim3 grid(nchunks, ta * ((tb + 1) / 2), nsys);
+    if (vec)
+      k_gram<E, S, 2, true><<<grid, kThreads, 0, s>>>(src, ng);
+    else
+      k_gram<E, S, 2, false><<<grid, kThreads, 0, s>>>(src, ng);
+  } else {
+    dim3 grid(nchunks, ta * tb, nsys);
+    if (vec)
+      k_gram<E, S, 1, true><<<grid, kThreads, 0, s>>>(src, ng);
+    else
+      k_gram<E, S, 1, false><<<grid, kThreads, 0, s>>>(src, ng);
+  }
 }
 
 // dispatch on the storage element type
@@ -551,12 +607,12 @@ struct TrsmRun {
 template <typename E>
 struct GramRun {
   template <typename SG, typename SR>
-  static void run(SG sg, SR sr, int ntiles, int nout, int nsys, size_t ng, double scale,
+  static void run(SG sg, SR sr, int ta, int tb, int nout, int nsys, size_t ng, double scale,
                   hipStream_t s) {
     typedef typename Elem<E>::wide W;
     size_t chunk;
     const int nch = gram_blocks(ng, &chunk);
-    gram_impl<E, SG>(sg, ntiles, nsys, ng, nch, s);
+    gram_impl<E, SG>(sg, ta, tb, nsys, ng, nch, s);
     dim3 rg(nout, nsys);
     k_gram_reduce<W, SR><<<rg, kThreads, 0, s>>>(sr, nch, scale);
   }
@@ -639,7 +695,7 @@ void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng
   }
   OneGram sg{GramArgs{A, na, B, nb, part}};
   OneRed sr{RedArgs{part, na * nb, out}};
-  by_elem<GramRun>(et, sg, sr, ((na + 15) / 16) * ((nb + 15) / 16), na * nb, 1, ng, scale, s);
+  by_elem<GramRun>(et, sg, sr, (na + 15) / 16, (nb + 15) / 16, na * nb, 1, ng, scale, s);
 }
 
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
@@ -667,7 +723,7 @@ void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nma
   {
     TraceScope ts(tr, TR_GRAM);
     const int t = (nmax + 15) / 16;
-    by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t * t, nmax * nmax, nmol, ng, dv, s);
+    by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t, t, nmax * nmax, nmol, ng, dv, s);
   }
   {
     TraceScope ts(tr, TR_CHOL);
