@@ -442,3 +442,67 @@ def test_tda_graph_replays_match_eager():
         ctx.tda_coupling(occ, virt, 0, c)     # eager work in between (triplet block)
         torch.cuda.synchronize()
     del g
+
+
+# ---- edge cases: one orbital, ragged box edges, the largest orbital counts, many vectors -----
+
+@pytest.mark.parametrize("dt", [torch.complex128, torch.complex64, torch.float64, torch.float32])
+def test_ace_single_orbital(dt):
+    cplx = dt.is_complex
+    m = synth.small_complex(11, 12, 0.4, 1, nvec=2) if cplx else synth.small_real(11, 12, 0.4, 1, 1)
+    if not cplx:
+        m.psi = synth.random_vectors(np.random.default_rng(2), 12, 0.4, 2)
+    g = _ace_case(m, dt)
+    xi, mm, _, ex = exchange.ace_build(m.phi, m.h)
+    single = dt in (torch.complex64, torch.float32)
+    assert abs(g["ex"] - ex) < (1e-6 if single else 1e-10 * abs(ex))
+    assert _rel(g["kpsi"], exchange.ace_apply(xi, g["psi"], m.h)) < (1e-5 if single else 1e-10)
+
+
+@pytest.mark.parametrize("n", [9, 15])
+@pytest.mark.parametrize("dt", [torch.complex128, torch.complex64])
+def test_ace_ragged_box_edges(n, dt):
+    m = synth.small_complex(20 + n, n, 0.4, 3, nvec=2)
+    g = _ace_case(m, dt)
+    xi, mm, _, ex = exchange.ace_build(m.phi, m.h)
+    single = dt == torch.complex64
+    assert abs(g["ex"] - ex) < (1e-6 if single else 1e-10 * abs(ex))
+    assert _rel(g["M"], mm) < (2e-6 if single else 1e-10)
+    assert _rel(g["kpsi"], exchange.ace_apply(xi, m.psi, m.h)) < (1e-5 if single else 1e-10)
+
+
+@pytest.mark.parametrize("dt,k", [(torch.complex64, 32), (torch.float32, 64), (torch.float64, 64)])
+def test_ace_largest_orbital_counts(dt, k):
+    """ACE with the largest orbital count each storage type accepts (complex 32, real 64)."""
+    import paper_2405_01522_amd as ace
+    n, h = 8, 0.6
+    rng = np.random.default_rng(k)
+    x = synth.coords(n, h)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    raw = rng.normal(size=(k, n, n, n)) * np.exp(-0.05 * r2)
+    if dt.is_complex:
+        raw = raw + 1j * rng.normal(size=(k, n, n, n)) * np.exp(-0.05 * r2)
+    phi = synth.mgs(raw, h ** 3)
+    ctx = ace.AceContext(n, h, dt)
+    xi, mm, ex = ctx.ace_build(_t(synth.to_precision(phi, dt in (torch.complex64, torch.float32)), dt))
+    st, info = ctx.status()
+    assert st == 0, (st, info)
+    xr, mr, _, exr = exchange.ace_build(phi, h)
+    tol = 1e-10 if dt == torch.float64 else 5e-6
+    assert abs(ex.item() - exr) < tol * abs(exr)
+    assert _rel(mm.cpu().numpy(), mr) < tol
+    # one more orbital than allowed is rejected on the host
+    too_many = k + 1
+    with pytest.raises(RuntimeError):
+        ctx.ace_build(_t(np.zeros((too_many, n, n, n), dtype=np.complex128 if dt.is_complex else np.float64), dt))
+
+
+def test_ace_apply_many_vectors_chunked():
+    """More vectors than one Gram pass holds (64): the apply runs in chunks."""
+    import paper_2405_01522_amd as ace
+    m = synth.small_complex(5, 10, 0.5, 3, nvec=70)
+    ctx = ace.AceContext(10, 0.5, torch.complex128)
+    xi, _, _ = ctx.ace_build(_t(m.phi, torch.complex128))
+    kp = ctx.ace_apply(xi, _t(m.psi, torch.complex128)).cpu().numpy()
+    xr, _, _, _ = exchange.ace_build(m.phi, m.h)
+    assert _rel(kp, exchange.ace_apply(xr, m.psi, m.h)) < 1e-10
