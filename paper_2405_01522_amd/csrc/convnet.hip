@@ -120,25 +120,36 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
 }
 
 // Weight and bias gradient partials of one tile: gw[o][i][t] = sum_p g[o](p) in[i](p + d_t),
-// gb[o] = sum_p g[o](p).  Thread (i, t[, o-group]) runs over the tile's points; the input
-// tile with halo is in LDS, g is read at uniform addresses.
+// gb[o] = sum_p g[o](p).  The input tile (with halo) and the tile of g (zero outside the box,
+// stored [point][o]) are staged in LDS; thread (i, t[, o-group]) runs over the tile's points
+// reading its input value and the (broadcast) g values of the point.
 template <int CI, int CO>
 __global__ __launch_bounds__(kT) void k_wgrad(const float* __restrict__ in, const float* __restrict__ g,
                                               float* __restrict__ part, int n, int tny, int tnz) {
   __shared__ float tile[CI * HVOL];
+  __shared__ __align__(16) float gt[TX * TY * TZ * CO];
   constexpr int OG = (CI == 1) ? CO : 1, OPT = CO / OG, NACT = CI * 27 * OG;
   constexpr int NPL = CO * CI * 27 + CO;
+  constexpr int TP = TX * TY * TZ;
   static_assert(NACT + CO <= kT, "threads");
   const size_t ng = (size_t)n * n * n;
   int x0, y0, z0;
   tile_origin(blockIdx.x, tny, tnz, &x0, &y0, &z0);
   const size_t sb = blockIdx.y;
   stage_halo<CI>(tile, in + sb * CI * ng, n, ng, x0, y0, z0);
+  const float* gb = g + sb * CO * ng;
+  for (int e = threadIdx.x; e < TP * CO; e += kT) {
+    const int o = e / TP, pt = e % TP;  // consecutive threads: consecutive z (coalesced)
+    const int pz = pt % TZ, py = (pt / TZ) % TY, px = pt / (TZ * TY);
+    const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
+    const bool ok = gx < n && gy < n && gz < n;
+    const size_t idx = ok ? (size_t)o * ng + ((size_t)gx * n + gy) * n + gz : 0;
+    const float v = gb[idx];
+    gt[pt * CO + o] = ok ? v : 0.f;
+  }
   __syncthreads();
   const int t = threadIdx.x;
-  const float* gb = g + sb * CO * ng;
   float* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NPL;
-  const int xe = min(TX, n - x0), ye = min(TY, n - y0), ze = min(TZ, n - z0);
   if (t < NACT) {
     const int og = t % OG, id = t / OG;
     const int i = id / 27, tap = id % 27;
@@ -146,27 +157,24 @@ __global__ __launch_bounds__(kT) void k_wgrad(const float* __restrict__ in, cons
     float acc[OPT];
 #pragma unroll
     for (int q = 0; q < OPT; ++q) acc[q] = 0.f;
-    for (int px = 0; px < xe; ++px)
-      for (int py = 0; py < ye; ++py) {
+    for (int px = 0; px < TX; ++px)
+      for (int py = 0; py < TY; ++py) {
         const float* trow = tile + i * HVOL + ((px + dx) * HY + (py + dy)) * HZ + dz;
-        const size_t prow = ((size_t)(x0 + px) * n + (y0 + py)) * n + z0;
-        for (int pz = 0; pz < ze; ++pz) {
+        const float* grow = gt + ((px * TY + py) * TZ) * CO + og * OPT;
+#pragma unroll
+        for (int pz = 0; pz < TZ; ++pz) {
           const float v = trow[pz];
 #pragma unroll
-          for (int q = 0; q < OPT; ++q) acc[q] += gb[(size_t)(og * OPT + q) * ng + prow + pz] * v;
+          for (int q = 0; q < OPT; ++q) acc[q] += grow[pz * CO + q] * v;
         }
       }
 #pragma unroll
     for (int q = 0; q < OPT; ++q) pb[((og * OPT + q) * CI + i) * 27 + tap] = acc[q];
   } else if (t < NACT + CO) {
     const int o = t - NACT;
-    float s = 0.f;
-    for (int px = 0; px < xe; ++px)
-      for (int py = 0; py < ye; ++py) {
-        const size_t prow = ((size_t)(x0 + px) * n + (y0 + py)) * n + z0;
-        for (int pz = 0; pz < ze; ++pz) s += gb[(size_t)o * ng + prow + pz];
-      }
-    pb[CO * CI * 27 + o] = s;
+    float sum = 0.f;
+    for (int pt = 0; pt < TP; ++pt) sum += gt[pt * CO + o];
+    pb[CO * CI * 27 + o] = sum;
   }
 }
 
