@@ -68,11 +68,18 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
                                              const float* __restrict__ mask, float* __restrict__ out,
                                              int n, int tny, int tnz) {
   __shared__ float tile[CI * HVOL];
+  // weights re-laid out [i][t][o] (o fastest) so a tap's CO weights are one broadcast read
+  constexpr int COP = CO < 4 ? 4 : CO;
+  __shared__ __align__(16) float wl[CI * 27 * COP];
   const size_t ng = (size_t)n * n * n;
   int x0, y0, z0;
   tile_origin(blockIdx.x, tny, tnz, &x0, &y0, &z0);
   const size_t sb = blockIdx.y;
   stage_halo<CI>(tile, in + sb * CI * ng, n, ng, x0, y0, z0);
+  for (int e = threadIdx.x; e < CI * 27 * COP; e += kT) {
+    const int o = e % COP, it = e / COP;  // it = i * 27 + t
+    wl[e] = o < CO ? w[(o * CI + it / 27) * 27 + it % 27] : 0.f;
+  }
   __syncthreads();
   const int lz = (threadIdx.x % 4) * ZP, ly = (threadIdx.x / 4) % TY, lx = threadIdx.x / 32;
   float acc[CO][ZP];
@@ -82,8 +89,7 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
     for (int p = 0; p < ZP; ++p) acc[o][p] = BIAS ? b[o] : 0.f;
 #pragma unroll 1
   for (int i = 0; i < CI; ++i) {
-    const float* wi = w + i * 27;
-#pragma unroll
+#pragma unroll 1
     for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
@@ -92,13 +98,22 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
 #pragma unroll
         for (int u = 0; u < ZP + 2; ++u) c[u] = col[u];
 #pragma unroll
-        for (int o = 0; o < CO; ++o)
+        for (int dz = 0; dz < 3; ++dz) {
+          const float* wt = wl + ((i * 27) + dx * 9 + dy * 3 + dz) * COP;
+          float wv[COP];
 #pragma unroll
-          for (int dz = 0; dz < 3; ++dz) {
-            const float wv = wi[o * CI * 27 + dx * 9 + dy * 3 + dz];
-#pragma unroll
-            for (int p = 0; p < ZP; ++p) acc[o][p] += wv * c[p + dz];
+          for (int q = 0; q < COP; q += 4) {
+            const float4 v4 = *reinterpret_cast<const float4*>(wt + q);
+            wv[q] = v4.x;
+            wv[q + 1] = v4.y;
+            wv[q + 2] = v4.z;
+            wv[q + 3] = v4.w;
           }
+#pragma unroll
+          for (int o = 0; o < CO; ++o)
+#pragma unroll
+            for (int p = 0; p < ZP; ++p) acc[o][p] += wv[o] * c[p + dz];
+        }
       }
   }
   const int gx = x0 + lx, gy = y0 + ly;
