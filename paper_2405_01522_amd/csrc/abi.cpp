@@ -201,11 +201,10 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   if (rc) return rc;
   rc = run_pairs(c, phi, phi, (const int*)c->pairs.p, np, c->vbuf.p);
   if (rc) return rc;
-  launch_wacc(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->stream, c->tr());
   char* mred = (char*)c->small.p;
   char* linvh = mred + wide * (size_t)n * n;
-  launch_gram(c->dtype, phi, n, c->wbuf.p, n, ng, c->part.p, c->h * c->h * c->h, mred, c->stream,
-              c->tr());
+  launch_wacc_gram(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p, c->h * c->h * c->h,
+                   mred, c->stream, c->tr());
   launch_chol(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->stream, c->tr());
   launch_trsm(c->dtype, c->wbuf.p, n, ng, linvh, xi_out, c->stream, c->tr());
   return hip_check(hipGetLastError());

@@ -249,6 +249,98 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   }
 }
 
+// W accumulation fused with the block's partial of M = Phi^H W dV (used when the orbitals and
+// W of one workgroup's points fit in LDS): after forming W_i(r) for its 256 points (as k_wacc),
+// the workgroup transposes phi and W through LDS and contracts them on the FP64 matrix cores
+// (each wavefront 64 points, the four summed in a fixed order), writing the same partial
+// layout part[o][block] as k_gram, so M is reduced by k_gram_reduce and W is not read again.
+template <typename E, int NMAX, typename S>
+__global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
+  static_assert(NMAX <= 16, "one 16 x 16 tile");
+  typedef typename Elem<E>::wide W;
+  constexpr bool CPLX = Elem<E>::cplx;
+  constexpr int LD = kThreads + 1;
+  __shared__ E lp[NMAX * LD];
+  __shared__ E lw[NMAX * LD];
+  __shared__ W red[kGramWaves][256];
+  const MolArgs m = src.get(blockIdx.y);
+  const E* __restrict__ phi = (const E*)m.phi;
+  const E* __restrict__ v = (const E*)m.v;
+  E* __restrict__ w = (E*)m.w;
+  W* __restrict__ part = (W*)m.part;
+  const int n = m.n;
+  const size_t r0 = (size_t)blockIdx.x * kThreads;
+  const size_t r = r0 + threadIdx.x;
+  const bool in = r < ng;
+  const size_t rc = in ? r : ng - 1;
+  E ph[NMAX], acc[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    acc[j] = e_zero<E>();
+    ph[j] = phi[(size_t)(j < n ? j : n - 1) * ng + rc];
+  }
+#pragma unroll
+  for (int b = 0; b < NMAX; ++b) {
+    if (b < n) {
+#pragma unroll
+      for (int a = 0; a <= b; ++a) {
+        const E vab = v[pair_index(a, b) * ng + rc];
+        acc[b] = e_add(acc[b], e_mul(ph[a], vab));
+        if (a != b) acc[a] = e_add(acc[a], e_mul(ph[b], e_conj(vab)));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    const bool use = i < n && in;
+    const E wi = e_neg(acc[i]);
+    if (use) w[(size_t)i * ng + r] = wi;
+    lp[i * LD + threadIdx.x] = use ? ph[i] : e_zero<E>();
+    lw[i * LD + threadIdx.x] = use ? wi : e_zero<E>();
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  gf64x4 t1 = {}, t2 = {}, t3 = {};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int pt = wave * 64 + 4 * q + g;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    if (NMAX == 16 || li < NMAX) {
+      split_ri(lp[li * LD + pt], ar, ai);
+      split_ri(lw[li * LD + pt], br, bi);
+    }
+    if constexpr (CPLX) {
+      t1 = mma64(ar - ai, br, t1);
+      t2 = mma64(ar, bi - br, t2);
+      t3 = mma64(-ai, br + bi, t3);
+    } else {
+      t1 = mma64(ar, br, t1);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int tt = (g + 4 * e) * 16 + li;
+    W x;
+    if constexpr (CPLX) {
+      x.r = t1[e] - t3[e];
+      x.i = t1[e] + t2[e];
+    } else {
+      x = t1[e];
+    }
+    red[wave][tt] = x;
+  }
+  __syncthreads();
+  const int th = threadIdx.x;
+  const int k = th / 16, l = th % 16;
+  if (k < n && l < n) {
+    W x = red[0][th];
+#pragma unroll
+    for (int q = 1; q < kGramWaves; ++q) x = e_add(x, red[q][th]);
+    part[((size_t)k * n + l) * gridDim.x + blockIdx.x] = x;
+  }
+}
+
 // Wide real Gram (both sides wider than one 16-row tile, at most 64 rows each): a workgroup
 // stages its chunk of kGramPoints points of every A and B row in LDS once, in passes of a
 // few dozen points (rows padded by one element against bank conflicts) and its four wavefronts compute all 16 x 16 output tiles
@@ -588,6 +680,24 @@ struct WaccRun {
   }
 };
 
+// fused W + M partials when one workgroup's phi and W fit in LDS (nmax <= 16, and <= 8 for
+// complex FP64); returns false if the separate W and Gram kernels must be used
+template <typename E>
+struct WaccGramRun {
+  template <typename S>
+  static void run(S src, int nmax, int nsys, size_t ng, bool* done, hipStream_t s) {
+    *done = false;
+    const int lim = sizeof(E) > 8 ? 8 : 16;
+    if (kGramPoints != kThreads || nmax > lim) return;
+    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+    if (nmax <= 8)
+      k_wacc_gram<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+    else if constexpr (sizeof(E) <= 8)
+      k_wacc_gram<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+    *done = true;
+  }
+};
+
 template <typename E>
 struct TrsmRun {
   template <typename S>
@@ -675,6 +785,31 @@ void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void*
   by_elem<WaccRun>(et, src, n, 1, ng, s);
 }
 
+void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                      void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
+  bool done = false;
+  {
+    TraceScope ts(tr, TR_WACC);
+    MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n);
+    m.part = part;
+    by_elem<WaccGramRun>(et, OneMol{m}, n, 1, ng, &done, s);
+  }
+  if (done) {
+    TraceScope ts(tr, TR_GRAM);
+    size_t chunk;
+    const int nch = gram_blocks(ng, &chunk);
+    if (et == ET_C128 || et == ET_C64)
+      k_gram_reduce<C2<double>, OneRed><<<dim3(n * n, 1), kThreads, 0, s>>>(
+          OneRed{RedArgs{part, n * n, mred}}, nch, scale);
+    else
+      k_gram_reduce<double, OneRed><<<dim3(n * n, 1), kThreads, 0, s>>>(
+          OneRed{RedArgs{part, n * n, mred}}, nch, scale);
+    return;
+  }
+  launch_wacc(et, phi, v, n, ng, w, s, tr);
+  launch_gram(et, phi, n, w, n, ng, part, scale, mred, s, tr);
+}
+
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
                  double scale, void* out, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_GRAM);
@@ -716,14 +851,27 @@ void launch_trsm(int et, const void* w, int n, size_t ng, const void* linvh, voi
 void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nmax, size_t ng,
                               double dv, hipStream_t s, Trace* tr) {
   ManyMol mm{mols_dev};
+  bool fused = false;
   {
     TraceScope ts(tr, TR_WACC);
-    by_elem<WaccRun>(et, mm, nmax, nmol, ng, s);
+    by_elem<WaccGramRun>(et, mm, nmax, nmol, ng, &fused, s);
+    if (!fused) by_elem<WaccRun>(et, mm, nmax, nmol, ng, s);
   }
   {
     TraceScope ts(tr, TR_GRAM);
-    const int t = (nmax + 15) / 16;
-    by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t, t, nmax * nmax, nmol, ng, dv, s);
+    if (fused) {
+      size_t chunk;
+      const int nch = gram_blocks(ng, &chunk);
+      dim3 rg(nmax * nmax, nmol);
+      if (et == ET_C128 || et == ET_C64)
+        k_gram_reduce<C2<double>, ManyRed><<<rg, kThreads, 0, s>>>(ManyRed{mols_dev}, nch, dv);
+      else
+        k_gram_reduce<double, ManyRed><<<rg, kThreads, 0, s>>>(ManyRed{mols_dev}, nch, dv);
+    } else {
+      const int t = (nmax + 15) / 16;
+      by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t, t, nmax * nmax, nmol, ng, dv,
+                       s);
+    }
   }
   {
     TraceScope ts(tr, TR_CHOL);

@@ -32,6 +32,11 @@ enum { ET_C128 = 0, ET_C64 = 1, ET_R64 = 2, ET_R32 = 3 };
 int gram_blocks(size_t ng, size_t* chunk);
 
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr);
+// W accumulation followed by M = scale * Phi^H W into mred (n*n FP64, complex or real): one
+// fused kernel plus the partial reduction when the orbitals fit its LDS tile, else the
+// separate W and Gram kernels.  part: gram_blocks(ng) * n * n partials.
+void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                      void* part, double scale, void* mred, hipStream_t s, Trace* tr);
 // out[k*nb + l] = scale * sum_r conj(A_k(r)) B_l(r), FP64 (complex or real), any na, nb.
 // part: gram_blocks(ng) * na * nb FP64 elements.
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
