@@ -28,10 +28,11 @@ METRIC = "pair Poisson solves/s and ACE K*psi/s, mixed vs FP64 GPU at 1e-6 Ha"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
-# HBM bytes per launch of k_xy<float, 48> (36 pairs) from rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00); valid for the
-# kernel as it stands (profiles/k_xy_c2_hbm_traffic.md)
-XY48_F32_TRAFFIC_BYTES = 2.00 * 32891 * 1024 + 1.00 * 62208 * 1024
+# HBM bytes per launch of k_xy<float, 48> (32 transforms) from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE, each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00);
+# valid for the kernel and launch as they stand (profiles/k_xy_c2_hbm_traffic.md); None until
+# measured for this launch
+XY48_F32_TRAFFIC_BYTES = None
 
 
 def xy_pass_flops(n):
@@ -469,16 +470,21 @@ def main(argv=None):
         xy_ms, xy_cnt = kt.get("poisson_xy", (0.0, 0))
         launches = xy_cnt
         avg_ms = xy_ms / max(1, launches)
-        pairs_per_launch = npairs  # one launch covers every pair of a build
-        flops = xy_pass_flops(mol.n) * pairs_per_launch
+        # one launch covers every transform of a build: the n(n-1)/2 off-diagonal pair
+        # densities, and the n real diagonal densities two per complex transform
+        norb = int(mol.phi.shape[0])
+        per_launch = norb * (norb - 1) // 2 + (norb + 1) // 2
+        flops = xy_pass_flops(mol.n) * per_launch
         achieved = flops / (avg_ms * 1e-3) / 1e12
+        tb = XY48_F32_TRAFFIC_BYTES
         out["roofline"] = {"bound": "alu", "kernel": "k_xy<float,48>", "achieved": achieved,
                            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": XY48_F32_TRAFFIC_BYTES,
+                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": tb,
                            "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
-                           "traffic_gbs": XY48_F32_TRAFFIC_BYTES / (avg_ms * 1e-3) / 1e9,
+                           "traffic_gbs": tb / (avg_ms * 1e-3) / 1e9 if tb else None,
+                           "transforms_per_launch": per_launch,
                            "avg_launch_ms": avg_ms,
-                           "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * pairs_per_launch / (avg_ms * 1e-3) / 1e9}
+                           "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * per_launch / (avg_ms * 1e-3) / 1e9}
         out["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in kt.items()}
         out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
 

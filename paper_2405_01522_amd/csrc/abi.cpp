@@ -183,29 +183,49 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   if (!c || !phi || !xi_out || n < 1 || n > max_orbitals(c->dtype)) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   const int np = n * (n + 1) / 2;
-  std::vector<int> pl(2 * (size_t)np);
-  for (int b = 0; b < n; ++b)
-    for (int a = 0; a <= b; ++a) {
-      const int p = b * (b + 1) / 2 + a;
-      pl[2 * p] = a;
-      pl[2 * p + 1] = b;
+  const bool cplx = is_cplx(c->dtype);
+  // real storage: the pair list in pair_index order (two real pairs per transform); complex
+  // storage: 4-int transform slots (off-diagonal pairs, then the real diagonal densities two
+  // per transform, orbitals 2m and 2m + 1 together)
+  std::vector<int> pl;
+  int nitems = np;
+  if (!cplx) {
+    pl.resize(2 * (size_t)np);
+    for (int b = 0; b < n; ++b)
+      for (int a = 0; a <= b; ++a) {
+        const int p = b * (b + 1) / 2 + a;
+        pl[2 * p] = a;
+        pl[2 * p + 1] = b;
+      }
+  } else {
+    for (int b = 0; b < n; ++b)
+      for (int a = 0; a < b; ++a) pl.insert(pl.end(), {a, b, b * (b + 1) / 2 + a, -1});
+    for (int a = 0; a < n; a += 2) {
+      const int d0 = a * (a + 1) / 2 + a;
+      if (a + 1 < n)
+        pl.insert(pl.end(), {a, a + 1, d0, (a + 1) * (a + 2) / 2 + a + 1});
+      else
+        pl.insert(pl.end(), {a, a, d0, -2});
     }
-  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+    nitems = (int)(pl.size() / 4);
+  }
+  const size_t wide = cplx ? 16 : 8;
   size_t chunk;
   const int nblk = gram_blocks(ng, &chunk);
-  int rc = upload_pairs(c, pl.data(), np);
+  int rc = upload_pairs(c, pl.data(), (int)(pl.size() / 2));
   if (!rc) rc = ensure(c, c->vbuf, eb * ng * (size_t)np);
   if (!rc) rc = ensure(c, c->wbuf, eb * ng * (size_t)n);
   if (!rc) rc = ensure(c, c->part, wide * (size_t)nblk * n * n);
   if (!rc) rc = ensure(c, c->small, wide * 2 * (size_t)n * n);
   if (rc) return rc;
-  rc = run_pairs(c, phi, phi, (const int*)c->pairs.p, np, c->vbuf.p);
+  rc = cplx ? run_slots(c, phi, (const int*)c->pairs.p, nitems, c->vbuf.p)
+            : run_pairs(c, phi, phi, (const int*)c->pairs.p, np, c->vbuf.p);
   if (rc) return rc;
   char* mred = (char*)c->small.p;
   char* linvh = mred + wide * (size_t)n * n;
-  launch_wacc_gram(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p, c->h * c->h * c->h,
-                   mred, c->stream, c->tr());
-  launch_chol(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->stream, c->tr());
+  launch_wacc_gram_chol(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p,
+                        c->h * c->h * c->h, mred, M_out, ex_out, linvh, c->status, c->stream,
+                        c->tr());
   launch_trsm(c->dtype, c->wbuf.p, n, ng, linvh, xi_out, c->stream, c->tr());
   return hip_check(hipGetLastError());
 }
@@ -567,18 +587,20 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
     size_t chunk;
     const int nch = gram_blocks(ng, &chunk);
     // sizes of this class
-    size_t np = 0, norb = 0, nsq = 0;
+    // np: pair volumes; nlist: list entries (complex: off-diagonal pairs + diagonal couples)
+    size_t np = 0, norb = 0, nsq = 0, nlist = 0;
     int nm = 0, nmax = 0;
     for (int m = 0; m < nmol; ++m)
       if (cls[m] == ci) {
         const int k = mols[m].norb;
         np += (size_t)k * (k + 1) / 2;
+        nlist += rp ? (size_t)k * (k + 1) / 2 : (size_t)k * (k - 1) / 2 + (k + 1) / 2;
         norb += k;
         nsq += (size_t)k * k;
         nmax = std::max(nmax, k);
         ++nm;
       }
-    const size_t items = rp ? (np + 1) / 2 : np;
+    const size_t items = rp ? (np + 1) / 2 : nlist;
     const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
     const size_t budget = size_t(2) << 30;
     const size_t batch = std::max<size_t>(1, std::min<size_t>(items, budget / per_item));
@@ -590,10 +612,10 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
     if (!rc) rc = ensure_on(c->stream, c->linvh, wide * nsq);
     if (rc) return rc;
     // descriptors
-    std::vector<unsigned char> blob(sizeof(MolArgs) * nm + sizeof(PairPtrs) * np);
+    std::vector<unsigned char> blob(sizeof(MolArgs) * nm + sizeof(PairPtrs) * nlist);
     MolArgs* ma = (MolArgs*)blob.data();
     PairPtrs* pp = (PairPtrs*)(blob.data() + sizeof(MolArgs) * nm);
-    size_t pv = 0, pw = 0, psq = 0;
+    size_t pv = 0, pw = 0, psq = 0, pl = 0;
     int im = 0;
     for (int m = 0; m < nmol; ++m) {
       if (cls[m] != ci) continue;
@@ -612,14 +634,44 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
       a.status = (int*)b->status.p + 2 * m;
       a.n = k;
       ma[im++] = a;
-      for (int q = 0; q < k; ++q)
-        for (int p = 0; p <= q; ++p) {
+      auto orb = [&](int j) { return (const char*)x.phi + eb * ng * j; };
+      auto vol = [&](int j, int i) { return (char*)a.v + eb * ng * ((size_t)i * (i + 1) / 2 + j); };
+      if (rp) {
+        for (int q = 0; q < k; ++q)
+          for (int p = 0; p <= q; ++p) {
+            PairPtrs t;
+            t.a = orb(p);
+            t.b = orb(q);
+            t.v = vol(p, q);
+            pp[pl + (size_t)q * (q + 1) / 2 + p] = t;
+          }
+        pl += (size_t)k * (k + 1) / 2;
+      } else {
+        // the same transforms as the one-system build: off-diagonal pairs, then the real
+        // diagonal densities of orbitals 2m and 2m + 1 together
+        for (int q = 0; q < k; ++q)
+          for (int p = 0; p < q; ++p) {
+            PairPtrs t;
+            t.a = orb(p);
+            t.b = orb(q);
+            t.v = vol(p, q);
+            pp[pl++] = t;
+          }
+        for (int d = 0; d < k; d += 2) {
           PairPtrs t;
-          t.a = (const char*)x.phi + eb * ng * p;
-          t.b = (const char*)x.phi + eb * ng * q;
-          t.v = (char*)a.v + eb * ng * ((size_t)q * (q + 1) / 2 + p);
-          pp[pv + (size_t)q * (q + 1) / 2 + p] = t;
+          t.a = orb(d);
+          t.v = vol(d, d);
+          if (d + 1 < k) {
+            t.b = orb(d + 1);
+            t.v2 = vol(d + 1, d + 1);
+            t.kind = 1;
+          } else {
+            t.b = orb(d);
+            t.kind = 2;
+          }
+          pp[pl++] = t;
         }
+      }
       pv += (size_t)k * (k + 1) / 2;
       pw += k;
       psq += (size_t)k * k;
@@ -633,7 +685,7 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
     for (size_t i0 = 0; i0 < items; i0 += batch) {
       const size_t ni = std::min(batch, items - i0);
       const size_t p0 = rp ? 2 * i0 : i0;
-      const size_t npb = rp ? std::min(2 * ni, np - p0) : ni;
+      const size_t npb = rp ? std::min(2 * ni, nlist - p0) : ni;
       launch_pair_poisson_ptrs(c->n, fp64, rp, pdev + p0, (int)npb, c->work.p, c->ctx->gpos,
                                c->ctx->tw, c->stream, tr);
     }

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng) {
 // converted to FP64 in registers: products of FP32 inputs are exact in FP64 and the sums
 // carry FP64 rounding only, whatever the storage precision.  Complex products take three
 // real contractions (Gauss's three-multiplication form of conj(a) b).  The four wavefront tiles
-// are summed in LDS in a fixed order; one FP64 partial per workgroup: part[o][block].
+// are summed in LDS in a fixed order; one FP64 partial per workgroup: part[block][o].
 // Lane layout of v_mfma_f64_16x16x4f64 (checked on gfx950): A[i][k] in lane i + 16k,
 // B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4.
 #ifndef ACE_GRAM_CHUNK
@@ -129,6 +129,8 @@ __device__ __forceinline__ void split_ri(float v, double& r, double& i) { r = v;
 __device__ __forceinline__ void split_ri(double v, double& r, double& i) { r = v; i = 0.0; }
 template <typename T>
 __device__ __forceinline__ void split_ri(C2<T> v, double& r, double& i) { r = v.r; i = v.i; }
+__device__ __forceinline__ void set_ri(double& x, double r, double) { x = r; }
+__device__ __forceinline__ void set_ri(C2<double>& x, double r, double i) { x.r = r; x.i = i; }
 
 // Four consecutive elements r0 .. r0+3 of a row (r0 a multiple of 4).  VEC: the row length
 // is a multiple of 4, so the group is 16-byte aligned and wholly inside or outside the row;
@@ -158,9 +160,11 @@ __device__ __forceinline__ void load4(const E* __restrict__ row, size_t r0, size
   }
 }
 
+// skip8: complex systems with at most 8 A rows are left to k_gram_c8 (launched beside it)
 template <typename E, typename S, int TB, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
+__global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng, int skip8) {
   typedef typename Elem<E>::wide W;
+  constexpr bool CPLX = Elem<E>::cplx;
   const GramArgs ga = src.get(blockIdx.z);
   const E* __restrict__ A = (const E*)ga.A;
   const E* __restrict__ B = (const E*)ga.B;
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
   W* __restrict__ part = (W*)ga.part;
   const int tiles_l = (nb + 15) / 16, groups_l = (tiles_l + TB - 1) / TB;
   if ((int)blockIdx.y >= ((na + 15) / 16) * groups_l) return;  // tile beyond this system
-  constexpr bool CPLX = Elem<E>::cplx;
+  if (CPLX && skip8 && na <= 8) return;
   constexpr int NQ = kGramChunk / 16;
   __shared__ W red[kGramWaves][256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -244,8 +248,164 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
       W v = red[0][th];
 #pragma unroll
       for (int w = 1; w < kGramWaves; ++w) v = e_add(v, red[w][th]);
-      part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = v;
+      part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l] = v;
     }
+  }
+}
+
+// Complex Gram with at most 8 A rows: the real and imaginary parts of the A rows are stacked
+// as the 16 rows of one FP64 MFMA operand, and those of 8 B columns as its 16 columns, so one
+// 16x16x4 product per 4 points gives all four real products of the 8 x 8 complex tile
+//   D = [Re A; Im A] [Re B, Im B],  Re(A^H B) = D_rr + D_ii,  Im(A^H B) = D_ri - D_ir
+// with no padded rows and no third (Gauss) product.  TB tiles of 8 B columns share the A rows.
+template <typename E, typename S, int TB, bool VEC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng) {
+  typedef typename Elem<E>::wide W;
+  static_assert(Elem<E>::cplx, "complex elements");
+  const GramArgs ga = src.get(blockIdx.z);
+  const E* __restrict__ A = (const E*)ga.A;
+  const E* __restrict__ B = (const E*)ga.B;
+  const int na = ga.na, nb = ga.nb;
+  W* __restrict__ part = (W*)ga.part;
+  const int tiles_l = (nb + 7) / 8;
+  if ((int)blockIdx.y * TB >= tiles_l || na > 8) return;  // beyond this system, or k_gram's
+  constexpr int CHUNK = kGramPoints / WAVES;  // points per wavefront
+  constexpr int NQ = CHUNK / 16;
+  static_assert(NQ >= 1 && CHUNK % 16 == 0, "whole 16-point steps per wavefront");
+  __shared__ double red[WAVES][TB * 256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int ri = li & 7;
+  const bool imag = li >= 8;
+  const E* ra = A + (size_t)(ri < na ? ri : na - 1) * ng;
+  const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * CHUNK;
+  E av[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load4<E, VEC>(ra, start + 16 * q + 4 * g, ng, av[q]);
+  double ao[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const size_t r = start + 16 * q + 4 * g + s;
+      ao[q][s] = (ri < na && r < ng) ? (imag ? (double)av[q][s].i : (double)av[q][s].r) : 0.0;
+    }
+  // every B tile's loads are issued before the first product
+  E bv[TB][NQ][4];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
+    if (l0 >= nb) break;  // uniform
+    const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) load4<E, VEC>(rb, start + 16 * q + 4 * g, ng, bv[t][q]);
+  }
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
+    if (l0 >= nb) break;  // uniform; these outputs are not written
+    gf64x4 d = {};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const size_t r = start + 16 * q + 4 * g + s;
+        const double bo =
+            (lb < nb && r < ng) ? (imag ? (double)bv[t][q][s].i : (double)bv[t][q][s].r) : 0.0;
+        d = mma64(ao[q][s], bo, d);
+      }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave][t * 256 + (g + 4 * e) * 16 + li] = d[e];
+  }
+  __syncthreads();
+  // TB * 64 complex outputs
+  for (int th = threadIdx.x; th < TB * 64; th += 64 * WAVES) {
+    const int t = th >> 6, k = (th >> 3) & 7, l = th & 7;
+    const int l0 = ((int)blockIdx.y * TB + t) * 8;
+    const double* rt = &red[0][t * 256];
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      re += rt[w * TB * 256 + k * 16 + l] + rt[w * TB * 256 + (k + 8) * 16 + l + 8];
+      im += rt[w * TB * 256 + k * 16 + l + 8] - rt[w * TB * 256 + (k + 8) * 16 + l];
+    }
+    if (k < na && l0 + l < nb) {
+      W v;
+      v.r = re;
+      v.i = im;
+      part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l0 + l] = v;
+    }
+  }
+}
+
+template <typename W>
+__device__ __forceinline__ W shfl_w(W v, int src);
+template <>
+__device__ __forceinline__ double shfl_w<double>(double v, int src) { return __shfl(v, src, 64); }
+template <>
+__device__ __forceinline__ C2<double> shfl_w<C2<double>>(C2<double> v, int src) {
+  return {__shfl(v.r, src, 64), __shfl(v.i, src, 64)};
+}
+__device__ __forceinline__ double w_from_real(double r, double) { return r; }
+__device__ __forceinline__ C2<double> w_from_real(double r, C2<double>) { return {r, 0.0}; }
+
+// Cholesky of -M (Hermitised), L^{-H} and E_x for n <= 8 in one wavefront, FP64, with one lane
+// per matrix entry (lane 8i + k holds entry (i, k)): every
+// elimination step is one pivot broadcast and one rank-1 update across the whole wavefront,
+// and L^{-1} is formed the same way, one column step at a time, so the dependent chain is
+// O(n) broadcasts instead of O(n^2) serial multiply-adds per lane.
+template <typename W>
+__device__ __forceinline__ void chol_lanes_body(const MolArgs& ma, const W* msrc) {
+  const int n = ma.n;
+  W* __restrict__ m_out = (W*)ma.m_out;
+  double* __restrict__ ex_out = ma.ex_out;
+  W* __restrict__ linvh = (W*)ma.linvh;
+  int* __restrict__ status = ma.status;
+  const int lane = threadIdx.x & 63, i = lane >> 3, k = lane & 7;
+  const bool in = i < n && k < n;
+  W a = W{};
+  bool bad = false;
+  double diag = 0.0;
+  if (in) {
+    const W mik = msrc[i * n + k], mki = msrc[k * n + i];
+    bad = !e_finite(mik);
+    const W herm = e_scale(e_add(mik, e_conj(mki)), 0.5);
+    if (m_out) m_out[i * n + k] = herm;
+    if (i == k) diag = e_re(herm);
+    a = e_neg(herm);
+  }
+  // E_x: diagonal i moved to lane i first, so the sum rounds as in k_chol
+  const double dl = __shfl(diag, lane < 8 ? 9 * lane : 0, 64);
+  double e = lane < n ? dl : 0.0;
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if (lane == 0 && ex_out) *ex_out = 0.5 * e;
+  const bool any_bad = __any(bad);
+  int fail = -1;
+  double dinv = 1.0;  // 1 / L_ii of this lane's row
+  for (int j = 0; j < n; ++j) {
+    const double piv = __shfl(e_re(a), 9 * j, 64);
+    if (!(piv > 0.0) && fail < 0) fail = j;
+    const double d = piv > 0.0 ? sqrt(piv) : 1.0;
+    const double invd = 1.0 / d;
+    if (i == j) dinv = invd;
+    if (k == j) a = (i > j) ? e_scale(a, invd) : (i == j ? w_from_real(d, W{}) : W{});
+    const W li = shfl_w(a, 8 * i + j), lk = shfl_w(a, 8 * k + j);
+    if (i > j && k > j) a = e_sub(a, e_mul(li, e_conj(lk)));
+  }
+  const W l = (in && k <= i) ? a : W{};
+  // X = L^{-1}, right-looking: step m finishes row m of X and removes it from the rows below
+  W x = (in && i == k) ? w_from_real(1.0, W{}) : W{};
+  for (int m = 0; m < n; ++m) {
+    if (i == m) x = e_scale(x, dinv);
+    const W xm = shfl_w(x, 8 * m + k), lim = shfl_w(l, 8 * i + m);
+    if (i > m) x = e_sub(x, e_mul(lim, xm));
+  }
+  const bool ok = fail < 0 && !any_bad;
+  // L^{-H}[c][r] = conj(X[r][c]); this lane holds X[i][k]
+  if (in) linvh[k * n + i] = ok ? e_conj(x) : W{};
+  if (lane == 0 && !ok && status && status[0] == 0) {
+    status[0] = any_bad ? -6 : -5;
+    status[1] = any_bad ? -1 : fail;
   }
 }
 
@@ -253,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng) {
 // W of one workgroup's points fit in LDS): after forming W_i(r) for its 256 points (as k_wacc),
 // the workgroup transposes phi and W through LDS and contracts them on the FP64 matrix cores
 // (each wavefront 64 points, the four summed in a fixed order), writing the same partial
-// layout part[o][block] as k_gram, so M is reduced by k_gram_reduce and W is not read again.
+// layout part[block][o] as k_gram, so M is reduced by k_gram_reduce and W is not read again.
 template <typename E, int NMAX, typename S>
 __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
   static_assert(NMAX <= 16, "one 16 x 16 tile");
@@ -301,43 +461,83 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  gf64x4 t1 = {}, t2 = {}, t3 = {};
+  // products in the same order as k_gram / k_gram_c8 over the same 256 points (wavefront w:
+  // points 64w + 16q + 4g + s at step (q, s)), so fused and separate builds agree bit for bit
+  if (CPLX && n <= 8) {
+    // real and imaginary parts stacked into one 16 x 16 product (as k_gram_c8)
+    const int ri = li & 7;
+    const bool imag = li >= 8;
+    gf64x4 d = {};
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int pt = wave * 64 + 4 * q + g;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-    if (NMAX == 16 || li < NMAX) {
-      split_ri(lp[li * LD + pt], ar, ai);
-      split_ri(lw[li * LD + pt], br, bi);
-    }
-    if constexpr (CPLX) {
-      t1 = mma64(ar - ai, br, t1);
-      t2 = mma64(ar, bi - br, t2);
-      t3 = mma64(-ai, br + bi, t3);
-    } else {
-      t1 = mma64(ar, br, t1);
-    }
-  }
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int tt = (g + 4 * e) * 16 + li;
-    W x;
-    if constexpr (CPLX) {
-      x.r = t1[e] - t3[e];
-      x.i = t1[e] + t2[e];
-    } else {
-      x = t1[e];
-    }
-    red[wave][tt] = x;
-  }
-  __syncthreads();
-  const int th = threadIdx.x;
-  const int k = th / 16, l = th % 16;
-  if (k < n && l < n) {
-    W x = red[0][th];
+      for (int s = 0; s < 4; ++s) {
+        const int pt = wave * 64 + 16 * q + 4 * g + s;
+        double ar, ai, br, bi;
+        split_ri(lp[(ri < NMAX ? ri : 0) * LD + pt], ar, ai);
+        split_ri(lw[(ri < NMAX ? ri : 0) * LD + pt], br, bi);
+        d = mma64(imag ? ai : ar, imag ? bi : br, d);
+      }
+    double* rd = reinterpret_cast<double*>(&red[0][0]);
 #pragma unroll
-    for (int q = 1; q < kGramWaves; ++q) x = e_add(x, red[q][th]);
-    part[((size_t)k * n + l) * gridDim.x + blockIdx.x] = x;
+    for (int e = 0; e < 4; ++e) rd[wave * 256 + (g + 4 * e) * 16 + li] = d[e];
+    __syncthreads();
+    const int th = threadIdx.x;
+    if (th < 64) {
+      const int k = th >> 3, l = th & 7;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGramWaves; ++w) {
+        re += rd[w * 256 + k * 16 + l] + rd[w * 256 + (k + 8) * 16 + l + 8];
+        im += rd[w * 256 + k * 16 + l + 8] - rd[w * 256 + (k + 8) * 16 + l];
+      }
+      if (k < n && l < n) {
+        W x = {};
+        set_ri(x, re, im);
+        part[(size_t)blockIdx.x * n * n + (size_t)k * n + l] = x;
+      }
+    }
+  } else {
+    gf64x4 t1 = {}, t2 = {}, t3 = {};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int pt = wave * 64 + 16 * q + 4 * g + s;
+        double ar = 0, ai = 0, br = 0, bi = 0;
+        if (NMAX == 16 || li < NMAX) {
+          split_ri(lp[li * LD + pt], ar, ai);
+          split_ri(lw[li * LD + pt], br, bi);
+        }
+        if constexpr (CPLX) {
+          t1 = mma64(ar - ai, br, t1);
+          t2 = mma64(ar, bi - br, t2);
+          t3 = mma64(-ai, br + bi, t3);
+        } else {
+          t1 = mma64(ar, br, t1);
+        }
+      }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int tt = (g + 4 * e) * 16 + li;
+      W x;
+      if constexpr (CPLX) {
+        x.r = t1[e] - t3[e];
+        x.i = t1[e] + t2[e];
+      } else {
+        x = t1[e];
+      }
+      red[wave][tt] = x;
+    }
+    __syncthreads();
+    const int th = threadIdx.x;
+    const int k = th / 16, l = th % 16;
+    if (k < n && l < n) {
+      W x = red[0][th];
+#pragma unroll
+      for (int q = 1; q < kGramWaves; ++q) x = e_add(x, red[q][th]);
+      part[(size_t)blockIdx.x * n * n + (size_t)k * n + l] = x;
+    }
   }
 }
 
@@ -345,7 +545,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
 // stages its chunk of kGramPoints points of every A and B row in LDS once, in passes of a
 // few dozen points (rows padded by one element against bank conflicts) and its four wavefronts compute all 16 x 16 output tiles
 // from there, so each input element is read from HBM once instead of once per tile.  Same
-// FP64 MFMA contraction and the same partial layout part[o][block] as k_gram.
+// FP64 MFMA contraction and the same partial layout part[block][o] as k_gram.
 constexpr int kWideRows = 64;
 
 // NT tiles of one wavefront over one staged pass (unconditional, fully unrolled chains)
@@ -424,7 +624,7 @@ __device__ __forceinline__ void k_gram_wide_body(const E* __restrict__ A, int na
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = k0 + g + 4 * e, l = l0 + li;
-      if (k < na && l < nb) part[((size_t)k * nb + l) * gridDim.x + blockIdx.x] = acc[u][e];
+      if (k < na && l < nb) part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l] = acc[u][e];
     }
   }
 }
@@ -448,39 +648,55 @@ __global__ __launch_bounds__(kThreads) void k_gram_wide(const E* __restrict__ A,
   }
 }
 
-// out[o] = scale * sum_b part[o][b]: one block per output, fixed-order tree.
+// out[o] = scale * sum_b part[b][o], one workgroup per output o: thread t adds blocks t,
+// t + kThreads, ... in order, each wavefront adds its 64 sums by a butterfly, and the
+// wavefront sums are added in order (a fixed summation for every launch).
+template <typename W>
+__device__ __forceinline__ W shfl_xor_w(W v, int m);
+template <>
+__device__ __forceinline__ double shfl_xor_w<double>(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+template <>
+__device__ __forceinline__ C2<double> shfl_xor_w<C2<double>>(C2<double> v, int m) {
+  return {__shfl_xor(v.r, m, 64), __shfl_xor(v.i, m, 64)};
+}
+
 template <typename W, typename S>
 __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale) {
-  __shared__ W red[kThreads];
+  __shared__ W red[kThreads / 64];
   const RedArgs ra = src.get(blockIdx.y);
   const int o = blockIdx.x;
   if (o >= ra.no) return;
   const W* __restrict__ part = (const W*)ra.part;
-  W* __restrict__ out = (W*)ra.out;
   W s = W{};
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)o * nblk + b]);
-  red[threadIdx.x] = s;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)b * ra.no + o]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s = e_add(s, shfl_xor_w(s, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = e_add(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    W t = red[0];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) t = e_add(t, red[w]);
+    ((W*)ra.out)[o] = e_scale(t, scale);
   }
-  if (threadIdx.x == 0) out[o] = e_scale(red[0], scale);
+}
+
+template <typename W, typename S>
+void reduce_launch(S sr, int nout, int nsys, int nblk, double scale, hipStream_t s) {
+  dim3 rg(nout, nsys);
+  k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale);
 }
 
 // Cholesky of -M (Hermitised), L^{-H} and E_x in one wavefront, FP64.  Lane i holds row i of
 // the working matrix in registers (right-looking factorisation, pivots broadcast by
 // shuffles); L goes through LDS for the triangular inverse, lane c solving column c.
-template <typename W>
-__device__ __forceinline__ W shfl_w(W v, int src);
-template <>
-__device__ __forceinline__ double shfl_w<double>(double v, int src) { return __shfl(v, src, 64); }
-template <>
-__device__ __forceinline__ C2<double> shfl_w<C2<double>>(C2<double> v, int src) {
-  return {__shfl(v.r, src, 64), __shfl(v.i, src, 64)};
+template <typename W, typename S>
+__global__ __launch_bounds__(64) void k_chol_lanes(S src) {
+  const MolArgs ma = src.get(blockIdx.x);
+  chol_lanes_body<W>(ma, (const W*)ma.mred);
 }
-__device__ __forceinline__ double w_from_real(double r, double) { return r; }
-__device__ __forceinline__ C2<double> w_from_real(double r, C2<double>) { return {r, 0.0}; }
 
 template <typename W, int NMAX, typename S>
 __global__ __launch_bounds__(64) void k_chol(S src) {
@@ -600,18 +816,16 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
 }
 
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
-// groups of kVB vectors); the group's slice of Z is staged in LDS in the storage precision.
-constexpr int kVB = 16;
-
-template <typename E, int NMAX>
+// groups of VB vectors); the group's slice of Z is staged in LDS in the storage precision.
+template <typename E, int NMAX, int VB>
 __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi, int n, size_t ng,
                                                         const typename Elem<E>::wide* __restrict__ z,
                                                         int nv, E* __restrict__ out) {
-  __shared__ E zs[NMAX * kVB];
-  const int v0 = blockIdx.y * kVB;
-  for (int t = threadIdx.x; t < n * kVB; t += kThreads) {
-    const int k = t / kVB, vb = t % kVB;
-    zs[k * kVB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
+  __shared__ E zs[NMAX * VB];
+  const int v0 = blockIdx.y * VB;
+  for (int t = threadIdx.x; t < n * VB; t += kThreads) {
+    const int k = t / VB, vb = t % VB;
+    zs[k * VB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
   }
   __syncthreads();
   const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
@@ -620,13 +834,13 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) xr[k] = xi[(size_t)(k < n ? k : n - 1) * ng + r];
 #pragma unroll
-  for (int vb = 0; vb < kVB; ++vb) {
+  for (int vb = 0; vb < VB; ++vb) {
     const int v = v0 + vb;
     if (v < nv) {
       E s = e_zero<E>();
 #pragma unroll
       for (int k = 0; k < NMAX; ++k)
-        if (k < n) s = e_add(s, e_mul(xr[k], zs[k * kVB + vb]));
+        if (k < n) s = e_add(s, e_mul(xr[k], zs[k * VB + vb]));
       out[(size_t)v * ng + r] = e_neg(s);
     }
   }
@@ -635,21 +849,22 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
 // ta row tiles; tb column tiles (upper bounds over the systems of a launch); the B tiles of
 // a row tile are taken two at a time for single-precision storage
 template <typename E, typename S>
-void gram_impl(S src, int ta, int tb, int nsys, size_t ng, int nchunks, hipStream_t s) {
+void gram_impl(S src, int ta, int tb, int nsys, size_t ng, int nchunks, int skip8,
+               hipStream_t s) {
   constexpr bool SMALL = sizeof(typename Elem<E>::real) == 4;
   const bool vec = ng % 4 == 0;
   if (SMALL && tb >= 2) {
     dim3 grid(nchunks, ta * ((tb + 1) / 2), nsys);
     if (vec)
-      k_gram<E, S, 2, true><<<grid, kThreads, 0, s>>>(src, ng);
+      k_gram<E, S, 2, true><<<grid, kThreads, 0, s>>>(src, ng, skip8);
     else
-      k_gram<E, S, 2, false><<<grid, kThreads, 0, s>>>(src, ng);
+      k_gram<E, S, 2, false><<<grid, kThreads, 0, s>>>(src, ng, skip8);
   } else {
     dim3 grid(nchunks, ta * tb, nsys);
     if (vec)
-      k_gram<E, S, 1, true><<<grid, kThreads, 0, s>>>(src, ng);
+      k_gram<E, S, 1, true><<<grid, kThreads, 0, s>>>(src, ng, skip8);
     else
-      k_gram<E, S, 1, false><<<grid, kThreads, 0, s>>>(src, ng);
+      k_gram<E, S, 1, false><<<grid, kThreads, 0, s>>>(src, ng, skip8);
   }
 }
 
@@ -717,14 +932,27 @@ struct TrsmRun {
 template <typename E>
 struct GramRun {
   template <typename SG, typename SR>
-  static void run(SG sg, SR sr, int ta, int tb, int nout, int nsys, size_t ng, double scale,
-                  hipStream_t s) {
+  static void run(SG sg, SR sr, int namax, int nbmax, int nout, int nsys, size_t ng,
+                  double scale, hipStream_t s) {
     typedef typename Elem<E>::wide W;
     size_t chunk;
     const int nch = gram_blocks(ng, &chunk);
-    gram_impl<E, SG>(sg, ta, tb, nsys, ng, nch, s);
-    dim3 rg(nout, nsys);
-    k_gram_reduce<W, SR><<<rg, kThreads, 0, s>>>(sr, nch, scale);
+    // complex systems with at most 8 A rows (every one, when namax <= 8) take the stacked
+    // kernel; the others the general one
+    if constexpr (Elem<E>::cplx) {
+      const bool vec = ng % 4 == 0;
+      // four 8-column tiles per workgroup, eight wavefronts of 32 points (measured best of
+      // 4/8/16 wavefronts and 2/4 tiles at 48^3, 8 x 32)
+      const int groups = ((nbmax + 7) / 8 + 3) / 4;
+      dim3 grid(nch, groups, nsys);
+      if (vec)
+        k_gram_c8<E, SG, 4, true, 8><<<grid, 512, 0, s>>>(sg, ng);
+      else
+        k_gram_c8<E, SG, 4, false, 8><<<grid, 512, 0, s>>>(sg, ng);
+    }
+    if (!Elem<E>::cplx || namax > 8)
+      gram_impl<E, SG>(sg, (namax + 15) / 16, (nbmax + 15) / 16, nsys, ng, nch, 1, s);
+    reduce_launch<W, SR>(sr, nout, nsys, nch, scale, s);
   }
 };
 
@@ -734,7 +962,7 @@ struct CholRun {
   static void run(S src, int nmax, int nsys, hipStream_t s) {
     typedef typename std::conditional<CPLX, C2<double>, double>::type W;
     if (nmax <= 8)
-      k_chol<W, 8, S><<<nsys, 64, 0, s>>>(src);
+      k_chol_lanes<W, S><<<nsys, 64, 0, s>>>(src);
     else if (nmax <= 16)
       k_chol<W, 16, S><<<nsys, 64, 0, s>>>(src);
     else if (nmax <= 32 || CPLX)
@@ -785,29 +1013,34 @@ void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void*
   by_elem<WaccRun>(et, src, n, 1, ng, s);
 }
 
-void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
-                      void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
+template <typename S>
+static void reduce_any(int et, S src, int nout, int nsys, int nblk, double scale, hipStream_t s) {
+  if (et == ET_C128 || et == ET_C64)
+    reduce_launch<C2<double>, S>(src, nout, nsys, nblk, scale, s);
+  else
+    reduce_launch<double, S>(src, nout, nsys, nblk, scale, s);
+}
+
+void launch_wacc_gram_chol(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                           void* part, double scale, void* mred, void* m_out, double* ex_out,
+                           void* linvh, int* status, hipStream_t s, Trace* tr) {
+  MolArgs m = single(phi, v, w, nullptr, mred, linvh, m_out, ex_out, status, n);
+  m.part = part;
   bool done = false;
   {
     TraceScope ts(tr, TR_WACC);
-    MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n);
-    m.part = part;
     by_elem<WaccGramRun>(et, OneMol{m}, n, 1, ng, &done, s);
   }
-  if (done) {
+  if (!done) {
+    launch_wacc(et, phi, v, n, ng, w, s, tr);
+    launch_gram(et, phi, n, w, n, ng, part, scale, mred, s, tr);
+  } else {
     TraceScope ts(tr, TR_GRAM);
     size_t chunk;
     const int nch = gram_blocks(ng, &chunk);
-    if (et == ET_C128 || et == ET_C64)
-      k_gram_reduce<C2<double>, OneRed><<<dim3(n * n, 1), kThreads, 0, s>>>(
-          OneRed{RedArgs{part, n * n, mred}}, nch, scale);
-    else
-      k_gram_reduce<double, OneRed><<<dim3(n * n, 1), kThreads, 0, s>>>(
-          OneRed{RedArgs{part, n * n, mred}}, nch, scale);
-    return;
+    reduce_any(et, OneRed{RedArgs{part, n * n, mred}}, n * n, 1, nch, scale, s);
   }
-  launch_wacc(et, phi, v, n, ng, w, s, tr);
-  launch_gram(et, phi, n, w, n, ng, part, scale, mred, s, tr);
+  launch_chol(et, mred, n, m_out, ex_out, linvh, status, s, tr);
 }
 
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
@@ -824,13 +1057,12 @@ void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng
       k_gram_wide<double><<<nch, kThreads, 0, s>>>((const double*)A, na, (const double*)B, nb,
                                                    ng, (double*)part);
     OneRed sr{RedArgs{part, na * nb, out}};
-    dim3 rg(na * nb, 1);
-    k_gram_reduce<double, OneRed><<<rg, kThreads, 0, s>>>(sr, nch, scale);
+    reduce_launch<double, OneRed>(sr, na * nb, 1, nch, scale, s);
     return;
   }
   OneGram sg{GramArgs{A, na, B, nb, part}};
   OneRed sr{RedArgs{part, na * nb, out}};
-  by_elem<GramRun>(et, sg, sr, (na + 15) / 16, (nb + 15) / 16, na * nb, 1, ng, scale, s);
+  by_elem<GramRun>(et, sg, sr, na, nb, na * nb, 1, ng, scale, s);
 }
 
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
@@ -859,19 +1091,13 @@ void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nma
   }
   {
     TraceScope ts(tr, TR_GRAM);
-    if (fused) {
-      size_t chunk;
-      const int nch = gram_blocks(ng, &chunk);
-      dim3 rg(nmax * nmax, nmol);
-      if (et == ET_C128 || et == ET_C64)
-        k_gram_reduce<C2<double>, ManyRed><<<rg, kThreads, 0, s>>>(ManyRed{mols_dev}, nch, dv);
-      else
-        k_gram_reduce<double, ManyRed><<<rg, kThreads, 0, s>>>(ManyRed{mols_dev}, nch, dv);
-    } else {
-      const int t = (nmax + 15) / 16;
-      by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, t, t, nmax * nmax, nmol, ng, dv,
-                       s);
-    }
+    size_t chunk;
+    const int nch = gram_blocks(ng, &chunk);
+    if (fused)
+      reduce_any(et, ManyRed{mols_dev}, nmax * nmax, nmol, nch, dv, s);
+    else
+      by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, nmax, nmax, nmax * nmax, nmol,
+                       ng, dv, s);
   }
   {
     TraceScope ts(tr, TR_CHOL);
@@ -881,19 +1107,26 @@ void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nma
   by_elem<TrsmRun>(et, mm, nmax, nmol, ng, s);
 }
 
+template <typename E, int VB>
+static void apply_vb(const void* xi, int n, size_t ng, const void* z, int nv, void* out,
+                     hipStream_t s) {
+  typedef typename Elem<E>::wide W;
+  dim3 blocks((unsigned)((ng + kThreads - 1) / kThreads), (unsigned)((nv + VB - 1) / VB));
+  if (n <= 8)
+    k_apply_out<E, 8, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+  else if (n <= 16)
+    k_apply_out<E, 16, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+  else if (n <= 32 || Elem<E>::cplx)
+    k_apply_out<E, 32, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+  else if constexpr (!Elem<E>::cplx)
+    k_apply_out<E, 64, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+}
+
+// 8 vectors per workgroup row (measured against 4, 16 and 32 at 48^3, 8 orbitals, 32 vectors)
 template <typename E>
 static void apply_impl(const void* xi, int n, size_t ng, const void* z, int nv, void* out,
                        hipStream_t s) {
-  typedef typename Elem<E>::wide W;
-  dim3 blocks((unsigned)((ng + kThreads - 1) / kThreads), (unsigned)((nv + kVB - 1) / kVB));
-  if (n <= 8)
-    k_apply_out<E, 8><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
-  else if (n <= 16)
-    k_apply_out<E, 16><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
-  else if (n <= 32 || Elem<E>::cplx)
-    k_apply_out<E, 32><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
-  else if constexpr (!Elem<E>::cplx)
-    k_apply_out<E, 64><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+  apply_vb<E, 8>(xi, n, ng, z, nv, out, s);
 }
 
 void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, int nv, void* out,

@@ -16,7 +16,7 @@ struct MolArgs {
   const void* v;     // [n(n+1)/2][ng] pair potentials, pair (a<=b) at b(b+1)/2 + a
   void* w;           // [n][ng] W
   void* xi;          // [n][ng] output (may alias w)
-  void* part;        // Gram partials [n*n][gram_blocks(ng)] (FP64, complex or real)
+  void* part;        // Gram partials [gram_blocks(ng)][n*n] (FP64, complex or real)
   void* mred;        // [n*n] reduced M (FP64)
   void* linvh;       // [n*n] L^{-H} (FP64)
   void* m_out;       // [n*n] M for the caller, or null
@@ -31,12 +31,15 @@ enum { ET_C128 = 0, ET_C64 = 1, ET_R64 = 2, ET_R32 = 3 };
 // number of Gram partial chunks for ng points (and the points per chunk)
 int gram_blocks(size_t ng, size_t* chunk);
 
+
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr);
-// W accumulation followed by M = scale * Phi^H W into mred (n*n FP64, complex or real): one
-// fused kernel plus the partial reduction when the orbitals fit its LDS tile, else the
-// separate W and Gram kernels.  part: gram_blocks(ng) * n * n partials.
-void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
-                      void* part, double scale, void* mred, hipStream_t s, Trace* tr);
+// W accumulation, M = scale * Phi^H W into mred (n*n FP64, complex or real), then the
+// Cholesky step of launch_chol.  W and the Gram partials come from one fused kernel when the
+// orbitals fit its LDS tile (n <= 16; 8 for complex FP64), else from the separate kernels.
+// part: gram_blocks(ng) * n * n partials.
+void launch_wacc_gram_chol(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                           void* part, double scale, void* mred, void* m_out, double* ex_out,
+                           void* linvh, int* status, hipStream_t s, Trace* tr);
 // out[k*nb + l] = scale * sum_r conj(A_k(r)) B_l(r), FP64 (complex or real), any na, nb.
 // part: gram_blocks(ng) * na * nb FP64 elements.
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,

@@ -248,6 +248,22 @@ inline int run_pairs(ace_ctx* c, const void* pa, const void* pb, const int* pair
   return hip_check(hipGetLastError());
 }
 
+// Complex transforms of launch_pair_slots (4 ints per transform, absolute output indices),
+// in launches bounded like run_pairs.
+inline int run_slots(ace_ctx* c, const void* phi, const int* slots_dev, int nslots, void* vout) {
+  const bool fp64 = is_fp64(c->dtype);
+  const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
+  const size_t budget = size_t(1) << 30;
+  int batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)nslots, budget / per_item));
+  int rc = ensure(c, c->work, per_item * (size_t)batch);
+  if (rc) return rc;
+  for (int i0 = 0; i0 < nslots; i0 += batch) {
+    const int ni = std::min(batch, nslots - i0);
+    launch_pair_slots(c->n, fp64, phi, slots_dev + 4 * (size_t)i0, ni, c->work.p, vout, c->gpos,
+                      c->tw, c->stream, c->tr());
+  }
+  return hip_check(hipGetLastError());
+}
 
 }  // namespace host
 }  // namespace ace

@@ -53,11 +53,23 @@ void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
                          Trace* tr);
 
 // Pointers of one pair solve: v = G (*) (conj(a) b) (complex), or v = G (*) (a b) (real).
+// Complex mode only: kind 1 packs the two real densities |a|^2 and |b|^2 into one transform
+// (v and v2 receive them with zero imaginary part), kind 2 solves |a|^2 alone into v.
 struct PairPtrs {
   const void* a;
   const void* b;
   void* v;
+  void* v2 = nullptr;
+  int kind = 0;
 };
+
+// Complex pair solves from an index list of 4 ints per transform (a, b, out0, out1) into
+// v_out + out * ng: out1 == -1 is the pair v[out0] = G (*) (conj(phi_a) phi_b); out1 >= 0 packs
+// the real densities |phi_a|^2 -> v[out0] and |phi_b|^2 -> v[out1] (zero imaginary parts);
+// out1 == -2 solves |phi_a|^2 -> v[out0] alone.
+void launch_pair_slots(int n, bool fp64, const void* phi, const int* slots_dev, int nslots,
+                       void* work, void* v_out, const void* ghat, const void* tw, hipStream_t s,
+                       Trace* tr);
 
 // Same passes with explicit pointers per pair (pairs of many systems of one box edge in one
 // launch).  items: device array of np entries; real-packed mode pairs items 2p and 2p+1.

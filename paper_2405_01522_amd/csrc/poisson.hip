@@ -68,6 +68,37 @@ struct PairsByIndex {
   __device__ __forceinline__ E* v(int q, size_t ng) const {
     return reinterpret_cast<E*>(vout) + (size_t)q * ng;
   }
+  __device__ __forceinline__ int kind(int) const { return 0; }
+  template <typename E>
+  __device__ __forceinline__ E* v2(int, size_t) const { return nullptr; }
+};
+
+// Complex transforms of one system from 4 ints each (a, b, out0, out1); see launch_pair_slots.
+struct SlotsByIndex {
+  const void* pa;
+  const int* slots;
+  void* vout;
+  int np;
+  template <typename E>
+  __device__ __forceinline__ const E* a(int q, size_t ng) const {
+    return reinterpret_cast<const E*>(pa) + (size_t)slots[4 * q] * ng;
+  }
+  template <typename E>
+  __device__ __forceinline__ const E* b(int q, size_t ng) const {
+    return reinterpret_cast<const E*>(pa) + (size_t)slots[4 * q + 1] * ng;
+  }
+  template <typename E>
+  __device__ __forceinline__ E* v(int q, size_t ng) const {
+    return reinterpret_cast<E*>(vout) + (size_t)slots[4 * q + 2] * ng;
+  }
+  __device__ __forceinline__ int kind(int q) const {
+    const int o1 = slots[4 * q + 3];
+    return o1 == -1 ? 0 : (o1 == -2 ? 2 : 1);
+  }
+  template <typename E>
+  __device__ __forceinline__ E* v2(int q, size_t ng) const {
+    return reinterpret_cast<E*>(vout) + (size_t)slots[4 * q + 3] * ng;
+  }
 };
 
 struct PairsByPointer {
@@ -84,6 +115,11 @@ struct PairsByPointer {
   template <typename E>
   __device__ __forceinline__ E* v(int q, size_t) const {
     return reinterpret_cast<E*>(items[q].v);
+  }
+  __device__ __forceinline__ int kind(int q) const { return items[q].kind; }
+  template <typename E>
+  __device__ __forceinline__ E* v2(int q, size_t) const {
+    return reinterpret_cast<E*>(items[q].v2);
   }
 };
 
@@ -105,6 +141,8 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ wo
   const C2<T>* ca = nullptr;
   const C2<T>* cb = nullptr;
   const T *ra0 = nullptr, *rb0 = nullptr, *ra1 = nullptr, *rb1 = nullptr;
+  // complex mode: 0 pair density, 1 two real densities |a|^2 + i |b|^2, 2 one real density
+  const int kd = RP ? 0 : res.kind(p);
   if constexpr (RP) {
     const int q0 = 2 * p, q1 = 2 * p + 1;
     ra0 = res.template a<T>(q0, NG) + plane;
@@ -128,7 +166,13 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ wo
         v[n1].r = ra0[idx] * rb0[idx];
         v[n1].i = ra1 ? ra1[idx] * rb1[idx] : T(0);
       } else {
-        v[n1] = cmulc(ca[idx], cb[idx]);
+        // both orbitals are loaded for every kind (b = a for kind 2) and the kind selects the
+        // result, so the loads stay unconditional and issue back to back
+        const C2<T> xa = ca[idx], xb = cb[idx];
+        const C2<T> pd = cmulc(xa, xb);
+        const T da = xa.r * xa.r + xa.i * xa.i, db = xb.r * xb.r + xb.i * xb.i;
+        v[n1].r = kd == 0 ? pd.r : da;
+        v[n1].i = kd == 0 ? pd.i : (kd == 1 ? db : T(0));
       }
     }
     dft_in_half<T, P1, -1>(v);
@@ -292,9 +336,21 @@ __global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ wor
         for (int n1 = 0; n1 < H1; ++n1) o1[n1 * P2] = v[n1].i;
       }
     } else {
+      const int kd = res.kind(p);
       C2<T>* o = res.template v<C2<T>>(p, NG) + base;
+      if (kd == 0) {
 #pragma unroll
-      for (int n1 = 0; n1 < H1; ++n1) o[n1 * P2] = v[n1];
+        for (int n1 = 0; n1 < H1; ++n1) o[n1 * P2] = v[n1];
+      } else {
+        // real densities: the two potentials are the real and imaginary parts
+#pragma unroll
+        for (int n1 = 0; n1 < H1; ++n1) o[n1 * P2] = C2<T>{v[n1].r, T(0)};
+        if (kd == 1) {
+          C2<T>* o1 = res.template v2<C2<T>>(p, NG) + base;
+#pragma unroll
+          for (int n1 = 0; n1 < H1; ++n1) o1[n1 * P2] = C2<T>{v[n1].i, T(0)};
+        }
+      }
     }
   }
 }
@@ -476,6 +532,13 @@ void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
                          Trace* tr) {
   PairsByIndex res{phi_a, phi_b, pairs_dev, v_out, np};
   dispatch_poisson(n, fp64, real_packed, res, work, ghat, tw, s, tr);
+}
+
+void launch_pair_slots(int n, bool fp64, const void* phi, const int* slots_dev, int nslots,
+                       void* work, void* v_out, const void* ghat, const void* tw, hipStream_t s,
+                       Trace* tr) {
+  SlotsByIndex res{phi, slots_dev, v_out, nslots};
+  dispatch_poisson(n, fp64, false, res, work, ghat, tw, s, tr);
 }
 
 void launch_pair_poisson_ptrs(int n, bool fp64, bool real_packed, const PairPtrs* items, int np,
