@@ -30,9 +30,8 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of k_xy<float, 48> (32 transforms) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE, each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00);
-# valid for the kernel and launch as they stand (profiles/k_xy_c2_hbm_traffic.md); None until
-# measured for this launch
-XY48_F32_TRAFFIC_BYTES = None
+# valid for the kernel and launch as they stand (profiles/k_xy_c2_hbm_traffic.md)
+XY48_F32_TRAFFIC_BYTES = 2.00 * 29439 * 1024 + 1.00 * 55296 * 1024
 
 
 def xy_pass_flops(n):
