@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_dgemm(int ta, int tb, int M, int N, int
 // LDS.  Output: w ascending, V[i][k] = component i of eigenvector k (row-major, leading
 // dimension ldv).
 constexpr int JMAX = 64;
-constexpr int JT = 512;
+constexpr int JT = 1024;
 
 // 1 / x and 1 / sqrt(x) in FP64 from the hardware estimates plus two Newton steps
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
   __shared__ double v[JMAX][JMAX + 1];
   __shared__ double cs[JMAX / 2], sn[JMAX / 2];
   __shared__ int pp[JMAX / 2], qq[JMAX / 2];
-  __shared__ double red[2][JT];
+  __shared__ double red[2][JT / 64];
   __shared__ int rank_s[JMAX];
   const int m = n + (n & 1);  // even order; a padding index acts as an isolated zero row
   const int h = m / 2;
@@ -113,17 +113,21 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
       tot += x;
       if (i != j) off += x;
     }
-    red[0][threadIdx.x] = off;
-    red[1][threadIdx.x] = tot;
-    __syncthreads();
-    for (int st = JT / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + st];
-        red[1][threadIdx.x] += red[1][threadIdx.x + st];
-      }
-      __syncthreads();
+    // wavefront butterflies, then the JT / 64 wavefront sums in order (every thread)
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      tot += __shfl_xor(tot, o, 64);
     }
-    const double offn = red[0][0], totn = red[1][0];
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = off;
+      red[1][threadIdx.x >> 6] = tot;
+    }
+    __syncthreads();
+    double offn = 0.0, totn = 0.0;
+    for (int w = 0; w < JT / 64; ++w) {
+      offn += red[0][w];
+      totn += red[1][w];
+    }
     __syncthreads();
     if (offn <= tol * tol * totn || offn == 0.0) break;
     for (int round = 0; round < m - 1; ++round) {
