@@ -650,7 +650,9 @@ __global__ __launch_bounds__(kThreads) void k_gram_wide(const E* __restrict__ A,
 
 // out[o] = scale * sum_b part[b][o], one workgroup per output o: thread t adds blocks t,
 // t + kThreads, ... in order, each wavefront adds its 64 sums by a butterfly, and the
-// wavefront sums are added in order (a fixed summation for every launch).
+// wavefront sums are added in order (a fixed summation for every launch).  Many small
+// workgroups spread the partial rows over the whole chip; one workgroup reading all of them
+// (as a fused reduction + Cholesky would) measured three to four times slower.
 template <typename W>
 __device__ __forceinline__ W shfl_xor_w(W v, int m);
 template <>
@@ -929,11 +931,13 @@ struct TrsmRun {
   }
 };
 
+// c8_waves: wavefronts per workgroup of the stacked kernel (4 gives the fused W + M kernel's
+// summation order, for M of a build; 8 is faster for xi^H psi)
 template <typename E>
 struct GramRun {
   template <typename SG, typename SR>
   static void run(SG sg, SR sr, int namax, int nbmax, int nout, int nsys, size_t ng,
-                  double scale, hipStream_t s) {
+                  double scale, int c8_waves, hipStream_t s) {
     typedef typename Elem<E>::wide W;
     size_t chunk;
     const int nch = gram_blocks(ng, &chunk);
@@ -941,14 +945,21 @@ struct GramRun {
     // kernel; the others the general one
     if constexpr (Elem<E>::cplx) {
       const bool vec = ng % 4 == 0;
-      // four 8-column tiles per workgroup, eight wavefronts of 32 points (measured best of
-      // 4/8/16 wavefronts and 2/4 tiles at 48^3, 8 x 32)
+      // four 8-column tiles per workgroup (measured best of 2/4 tiles and 4/8/16 wavefronts
+      // at 48^3, 8 x 32: eight wavefronts of 32 points)
       const int groups = ((nbmax + 7) / 8 + 3) / 4;
       dim3 grid(nch, groups, nsys);
-      if (vec)
-        k_gram_c8<E, SG, 4, true, 8><<<grid, 512, 0, s>>>(sg, ng);
-      else
-        k_gram_c8<E, SG, 4, false, 8><<<grid, 512, 0, s>>>(sg, ng);
+      if (c8_waves == 8) {
+        if (vec)
+          k_gram_c8<E, SG, 4, true, 8><<<grid, 512, 0, s>>>(sg, ng);
+        else
+          k_gram_c8<E, SG, 4, false, 8><<<grid, 512, 0, s>>>(sg, ng);
+      } else {
+        if (vec)
+          k_gram_c8<E, SG, 4, true, 4><<<grid, 256, 0, s>>>(sg, ng);
+        else
+          k_gram_c8<E, SG, 4, false, 4><<<grid, 256, 0, s>>>(sg, ng);
+      }
     }
     if (!Elem<E>::cplx || namax > 8)
       gram_impl<E, SG>(sg, (namax + 15) / 16, (nbmax + 15) / 16, nsys, ng, nch, 1, s);
@@ -1062,7 +1073,7 @@ void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng
   }
   OneGram sg{GramArgs{A, na, B, nb, part}};
   OneRed sr{RedArgs{part, na * nb, out}};
-  by_elem<GramRun>(et, sg, sr, na, nb, na * nb, 1, ng, scale, s);
+  by_elem<GramRun>(et, sg, sr, na, nb, na * nb, 1, ng, scale, 8, s);
 }
 
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
@@ -1097,7 +1108,7 @@ void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nma
       reduce_any(et, ManyRed{mols_dev}, nmax * nmax, nmol, nch, dv, s);
     else
       by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, nmax, nmax, nmax * nmax, nmol,
-                       ng, dv, s);
+                       ng, dv, 4, s);
   }
   {
     TraceScope ts(tr, TR_CHOL);

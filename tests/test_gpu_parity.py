@@ -506,3 +506,50 @@ def test_ace_apply_many_vectors_chunked():
     kp = ctx.ace_apply(xi, _t(m.psi, torch.complex128)).cpu().numpy()
     xr, _, _, _ = exchange.ace_build(m.phi, m.h)
     assert _rel(kp, exchange.ace_apply(xr, m.psi, m.h)) < 1e-10
+
+
+@pytest.mark.parametrize("dt", [torch.complex128, torch.complex64])
+def test_ace_complex_eleven_orbitals(dt):
+    """More than 8 complex orbitals: the general Gram kernels for M and for xi^H psi, and an
+    odd count (one real diagonal density in a transform of its own)."""
+    rng = np.random.default_rng(77)
+    n, h, k = 10, 0.5, 11
+    x = synth.coords(n, h)
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    raw = (rng.normal(size=(k, n, n, n)) + 1j * rng.normal(size=(k, n, n, n))) * np.exp(-0.08 * r2)
+    m = synth.small_complex(6, n, h, 3, nvec=5)
+    m.phi = synth.mgs(raw, h ** 3)
+    g = _ace_case(m, dt)
+    xi, mm, _, ex = exchange.ace_build(m.phi, m.h)
+    single = dt == torch.complex64
+    assert abs(g["ex"] - ex) < (1e-6 if single else 1e-10 * abs(ex))
+    assert _rel(g["M"], mm) < (2e-6 if single else 1e-10)
+    assert _rel(g["kpsi"], exchange.ace_apply(xi, m.psi, m.h)) < (1e-5 if single else 1e-10)
+
+
+def test_batched_complex_more_than_sixteen_orbitals():
+    """A complex batch whose largest system has more than 16 orbitals takes the separate W,
+    Gram and Cholesky kernels for every system; each system still equals its one-system build
+    bit for bit, and E_x matches the oracle."""
+    import paper_2405_01522_amd as ace
+    dt = torch.complex64
+    rng = np.random.default_rng(91)
+    cases = []
+    for n, k in [(10, 3), (10, 20), (10, 11), (12, 7)]:
+        h = 0.5
+        x = synth.coords(n, h)
+        r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+        raw = (rng.normal(size=(k, n, n, n)) + 1j * rng.normal(size=(k, n, n, n))) * np.exp(-0.08 * r2)
+        cases.append((n, h, synth.mgs(raw, h ** 3)))
+    systems = [{"h": h, "phi": _t(synth.to_precision(phi, True), dt)} for (_, h, phi) in cases]
+    b = ace.AceBatch(dt)
+    b.build(systems)
+    st, mol, info = b.status()
+    assert st == 0, (st, mol, info)
+    for k, (n, h, phi) in enumerate(cases):
+        ctx = ace.AceContext(n, h, dt)
+        xi, _, ex = ctx.ace_build(systems[k]["phi"])
+        torch.cuda.synchronize()
+        assert torch.equal(xi, systems[k]["xi"]) and torch.equal(ex, systems[k]["ex"]), k
+        _, _, _, exr = exchange.ace_build(phi, h)
+        assert abs(float(ex.cpu()) - exr) < 1e-6, k
