@@ -114,40 +114,55 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // consecutive lanes read one row (4 consecutive points each, one 16-byte load when VEC), so
 // every load instruction covers four 256-byte row segments.  Loads are unconditional (row and
 // point clamped); rows >= M and points >= k1 are zeroed.
-template <bool VEC>
-__device__ __forceinline__ void stage_tile(const Op<float>& o, int m0, int M, size_t kt,
-                                           size_t k1, size_t ng, __bf16* H, __bf16* L) {
+// rows[r] (r < MT): element offsets of the tile row's first-factor row and second-factor row
+// (product mode), computed once per workgroup so that no index arithmetic beyond one add is
+// left in the K loop.
+__device__ __forceinline__ void tile_rows(const Op<float>& o, int m0, int M, size_t ng, int r,
+                                          longlong2* rows) {
+  const int m = m0 + r;
+  const int mc = m < M ? m : M - 1;
+  const int ip = o.q ? mc / o.div : mc, iq = o.q ? mc % o.div : 0;
+  rows[r] = longlong2{(long long)((size_t)ip * ng), (long long)((size_t)iq * ng)};
+}
+
+template <bool VEC, bool PROD>
+__device__ __forceinline__ void stage_tile(const Op<float>& o, const longlong2* rows, int m0, int M,
+                                           size_t kt, size_t k1, size_t ng, __bf16* H,
+                                           __bf16* L) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   const int c4 = (threadIdx.x & 15) * 4;
   const size_t k = kt + c4;
 #pragma unroll
   for (int pass = 0; pass < MT / 16; ++pass) {
     const int r = pass * 16 + (threadIdx.x >> 4);
-    const int m = m0 + r;
-    const bool valid = m < M;
-    const int mc = valid ? m : M - 1;
-    const float* p = o.q ? o.p + (size_t)(mc / o.div) * ng : o.p + (size_t)mc * ng;
-    const float* q = o.q ? o.q + (size_t)(mc % o.div) * ng : nullptr;
+    const bool valid = m0 + r < M;
+    const longlong2 rr = rows[r];
+    const float* p = o.p + rr.x;
     float x[4];
     if constexpr (VEC) {
       const size_t kc = k + 3 < ng ? k : ng - 4;
       const float4 a = *reinterpret_cast<const float4*>(p + kc);
       x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-      if (q) {
-        const float4 b = *reinterpret_cast<const float4*>(q + kc);
+      if constexpr (PROD) {
+        const float4 b = *reinterpret_cast<const float4*>(o.q + rr.y + kc);
         x[0] *= b.x; x[1] *= b.y; x[2] *= b.z; x[3] *= b.w;
       }
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const size_t kc = k + e < ng ? k + e : ng - 1;
-        x[e] = q ? p[kc] * q[kc] : p[kc];
+        if constexpr (PROD)
+          x[e] = p[kc] * o.q[rr.y + kc];
+        else
+          x[e] = p[kc];
       }
     }
     bf16x4 h, l;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float v = (valid && k + e < k1) ? x[e] : 0.f;
+      // zeroing by a 0 / 1 factor (all loaded values are finite), not a select the compiler
+      // may turn into a branch around the load
+      const float v = x[e] * ((valid && k + e < k1) ? 1.f : 0.f);
       const __bf16 vh = (__bf16)v;
       h[e] = vh;
       l[e] = (__bf16)(v - (float)vh);
@@ -167,6 +182,7 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
   __shared__ __align__(16) __bf16 Al[MT * LB];
   __shared__ __align__(16) __bf16 Bh[MT * LB];
   __shared__ __align__(16) __bf16 Bl[MT * LB];
+  __shared__ longlong2 rows_a[MT], rows_b[MT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // wave's 64 x 64 quadrant
   int bx = blockIdx.x, by = blockIdx.y;
@@ -181,6 +197,11 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
   const int m0 = bx * MT, n0 = by * MT;
   const size_t k0 = (size_t)blockIdx.z * kchunk;
   const size_t k1 = k0 + kchunk < ng ? k0 + kchunk : ng;
+  if (threadIdx.x < MT)
+    tile_rows(A, m0, M, ng, threadIdx.x, rows_a);
+  else if (threadIdx.x < 2 * MT)
+    tile_rows(B, n0, N, ng, threadIdx.x - MT, rows_b);
+  __syncthreads();
   f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -188,8 +209,15 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int li = lane & 15, lg = lane >> 4;
   for (size_t kt = k0; kt < k1; kt += KB) {
-    stage_tile<VEC>(A, m0, M, kt, k1, ng, Ah, Al);
-    stage_tile<VEC>(B, n0, N, kt, k1, ng, Bh, Bl);
+    // product (generated) operands load two rows; the choice is uniform per launch
+    if (A.q)
+      stage_tile<VEC, true>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
+    else
+      stage_tile<VEC, false>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
+    if (B.q)
+      stage_tile<VEC, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+    else
+      stage_tile<VEC, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KB; ks += 32) {
