@@ -47,6 +47,31 @@ def xy_pass_bytes(n, elem):
     return 2.0 * n * n * 2 * n * elem
 
 
+def pair_solve_model_bytes(n, s_work, s_orb):
+    """Minimum-pass HBM model of one pair solve: the three transform passes move 16 N^3 working
+    elements (z forward writes N^2 P, the xy pass reads and writes it, z inverse reads it) and
+    3 N^3 orbital / potential elements (two orbitals in, one potential out)."""
+    return 16.0 * n ** 3 * s_work + 3.0 * n ** 3 * s_orb
+
+
+def measure_copy_gbs(reps=10):
+    """Device-to-device copy bandwidth (256 MiB, read + write bytes) on this GPU."""
+    import torch
+    src = torch.empty(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9
+
+
 def run_gpu(mol, dtype, steps, warmup, trace, graph=True):
     import torch
     import paper_2405_01522_amd as ace
@@ -485,6 +510,15 @@ def main(argv=None):
                            "avg_launch_ms": avg_ms,
                            "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * per_launch / (avg_ms * 1e-3) / 1e9}
         out["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in kt.items()}
+    # whole pair-solve path against the minimum-pass HBM model (context beside the kernel roofline)
+    copy_gbs = measure_copy_gbs()
+    for key, sw, val in (("mixed", 8, out["value"]), ("fp64", 16, out["fp64"]["pair_solves_per_s"])):
+        b = pair_solve_model_bytes(mol.n, sw, sw)
+        gbs = b * val / 1e9
+        out.setdefault("path_roofline", {"model": "16 N^3 s_w + 3 N^3 s_o bytes per pair solve",
+                                         "copy_gbs": copy_gbs})[key] = {
+            "bytes_per_pair": b, "achieved_gbs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+            "frac_copy": gbs / copy_gbs}
         out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
 
     if not a.no_batched:
