@@ -24,11 +24,36 @@ struct Op {
   const T* p;   // rows of length ng, or first factor
   const T* q;   // second factor (product mode) or null
   int div;      // product mode: row -> (row / div, row % div)
+  int tri;      // product mode over pairs lo <= hi instead: row t = hi (hi + 1) / 2 + lo
 };
+
+// (lo, hi) of triangular pair index t = hi (hi + 1) / 2 + lo, lo <= hi
+__device__ __forceinline__ void tri_decode(int t, int* lo, int* hi) {
+  int h = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((h + 1) * (h + 2) / 2 <= t) ++h;
+  while (h * (h + 1) / 2 > t) --h;
+  *hi = h;
+  *lo = t - h * (h + 1) / 2;
+}
+
+// first- and second-factor rows of operand row `row` (product mode)
+template <typename T>
+__device__ __forceinline__ void op_rows(const Op<T>& o, int row, int* ip, int* iq) {
+  if (o.tri) {
+    tri_decode(row, ip, iq);
+  } else {
+    *ip = row / o.div;
+    *iq = row % o.div;
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T op_load(const Op<T>& o, int row, size_t k, size_t ng) {
-  if (o.q) return o.p[(size_t)(row / o.div) * ng + k] * o.q[(size_t)(row % o.div) * ng + k];
+  if (o.q) {
+    int ip, iq;
+    op_rows(o, row, &ip, &iq);
+    return o.p[(size_t)ip * ng + k] * o.q[(size_t)iq * ng + k];
+  }
   return o.p[(size_t)row * ng + k];
 }
 
@@ -121,7 +146,8 @@ __device__ __forceinline__ void tile_rows(const Op<float>& o, int m0, int M, siz
                                           longlong2* rows) {
   const int m = m0 + r;
   const int mc = m < M ? m : M - 1;
-  const int ip = o.q ? mc / o.div : mc, iq = o.q ? mc % o.div : 0;
+  int ip = mc, iq = 0;
+  if (o.q) op_rows(o, mc, &ip, &iq);
   rows[r] = longlong2{(long long)((size_t)ip * ng), (long long)((size_t)iq * ng)};
 }
 
@@ -278,20 +304,20 @@ __global__ void k_split_reduce(const double* __restrict__ part, int nsplit, size
 }
 
 // C[ia][jb] = delta_M CJ[ia][jb] - CK[ij][ab], symmetrised: CJ is taken from the computed
-// (upper) tile of the pair (ia, jb) / (jb, ia), averaged on diagonal tiles, and CK[ij] is
-// averaged over (a, b) / (b, a).  Both are symmetric in exact arithmetic for real orbitals.
+// (upper) tile of the pair (ia, jb) / (jb, ia), averaged on diagonal tiles.  CK holds the
+// pairs i <= j and a <= b only ((ij|ab) is symmetric in both for real orbitals).
 // tile > 0: only tiles with row-tile <= col-tile of CJ hold data.
 __global__ void k_tda_assemble(const double* __restrict__ cj, const double* __restrict__ ck,
                                int no, int nv, int delta_m, double* __restrict__ c, int tile) {
-  const size_t nov = (size_t)no * nv;
+  const size_t nov = (size_t)no * nv, nvt = (size_t)nv * (nv + 1) / 2;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nov * nov;
        idx += (size_t)gridDim.x * blockDim.x) {
     const size_t row = idx / nov, col = idx % nov;
     const int i = (int)(row / nv), a = (int)(row % nv), j = (int)(col / nv), b = (int)(col % nv);
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     const size_t q = (size_t)hi * (hi + 1) / 2 + lo;
-    const double* ckq = ck + q * (size_t)nv * nv;
-    const double k = 0.5 * (ckq[(size_t)a * nv + b] + ckq[(size_t)b * nv + a]);
+    const int alo = a < b ? a : b, ahi = a < b ? b : a;
+    const double k = ck[q * nvt + (size_t)ahi * (ahi + 1) / 2 + alo];
     double jv;
     const int tr = tile > 0 ? (int)row / tile : 0, tc = tile > 0 ? (int)col / tile : 0;
     if (tr < tc)
@@ -332,16 +358,16 @@ template <typename T>
 void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_ov,
               const void* v_oo, size_t ng, double dv, int delta_m, void* ws, const TdaWork& w,
               double* c_out, double* b_out, hipStream_t s, Trace* tr) {
-  const int nov = no * nv, noo = no * (no + 1) / 2, nvv = nv * nv;
+  const int nov = no * nv, noo = no * (no + 1) / 2, nvv = nv * (nv + 1) / 2;
   char* base = (char*)ws;
   double* pj = (double*)(base + w.off_pj);
   double* pk = (double*)(base + w.off_pk);
   double* cj = (double*)(base + w.off_cj);
   double* ck = (double*)(base + w.off_ck);
-  Op<T> a_ov{(const T*)occ, (const T*)virt, nv};
-  Op<T> b_ov{(const T*)v_ov, nullptr, 1};
-  Op<T> a_oo{(const T*)v_oo, nullptr, 1};
-  Op<T> b_vv{(const T*)virt, (const T*)virt, nv};
+  Op<T> a_ov{(const T*)occ, (const T*)virt, nv, 0};
+  Op<T> b_ov{(const T*)v_ov, nullptr, 1, 0};
+  Op<T> a_oo{(const T*)v_oo, nullptr, 1, 0};
+  Op<T> b_vv{(const T*)virt, (const T*)virt, nv, 1};  // pairs a <= b
   const size_t cntj = (size_t)nov * nov, cntk = (size_t)noo * nvv;
   const unsigned rbj = (unsigned)std::min<size_t>(4096, (cntj + 255) / 256);
   const unsigned rbk = (unsigned)std::min<size_t>(4096, (cntk + 255) / 256);
@@ -459,7 +485,8 @@ void launch_strength(const double* omega, const double* f, int k, double w0, dou
 }
 
 size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
-  const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2, nvv = (size_t)nv * nv;
+  const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2,
+               nvv = (size_t)nv * (nv + 1) / 2;
   // enough blocks for the GPU: at least ~1024 for the larger contraction
   const size_t tile = fp64 ? BM : MT;
   const size_t tiles = ((nov + tile - 1) / tile) * ((nov + tile - 1) / tile);
