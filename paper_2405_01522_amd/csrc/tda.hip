@@ -198,9 +198,57 @@ __device__ __forceinline__ void stage_tile(const Op<float>& o, const longlong2* 
   }
 }
 
+// The two halves of stage_tile for a plain (non-product) operand, so that the global loads of
+// the next tile can be in flight during the current tile's products: load_rows reads this
+// thread's 4-point segments of the tile's rows, store_rows splits and stores them.
+template <bool VEC>
+__device__ __forceinline__ void load_rows(const Op<float>& o, const longlong2* rows, size_t kt,
+                                          size_t ng, float4* x) {
+  const int c4 = (threadIdx.x & 15) * 4;
+  const size_t k = kt + c4;
+#pragma unroll
+  for (int pass = 0; pass < MT / 16; ++pass) {
+    const int r = pass * 16 + (threadIdx.x >> 4);
+    const float* p = o.p + rows[r].x;
+    if constexpr (VEC) {
+      const size_t kc = k + 3 < ng ? k : ng - 4;
+      x[pass] = *reinterpret_cast<const float4*>(p + kc);
+    } else {
+      float e4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) e4[e] = p[k + e < ng ? k + e : ng - 1];
+      x[pass] = float4{e4[0], e4[1], e4[2], e4[3]};
+    }
+  }
+}
+
+__device__ __forceinline__ void store_rows(const float4* x, int m0, int M, size_t kt, size_t k1,
+                                           __bf16* H, __bf16* L) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int c4 = (threadIdx.x & 15) * 4;
+  const size_t k = kt + c4;
+#pragma unroll
+  for (int pass = 0; pass < MT / 16; ++pass) {
+    const int r = pass * 16 + (threadIdx.x >> 4);
+    const bool valid = m0 + r < M;
+    const float xv[4] = {x[pass].x, x[pass].y, x[pass].z, x[pass].w};
+    bf16x4 h, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float v = xv[e] * ((valid && k + e < k1) ? 1.f : 0.f);
+      const __bf16 vh = (__bf16)v;
+      h[e] = vh;
+      l[e] = (__bf16)(v - (float)vh);
+    }
+    *reinterpret_cast<bf16x4*>(H + r * LB + c4) = h;
+    *reinterpret_cast<bf16x4*>(L + r * LB + c4) = l;
+  }
+}
+
 // tri != 0: M == N and the result is symmetric; blockIdx.x enumerates only the tiles (bx, by)
 // with bx <= by (blockIdx.y unused) and the lower tiles are never computed.
-template <bool VEC>
+// PREF: B is a plain operand whose next tile is prefetched into registers during the products
+template <bool VEC, bool PREF>
 __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<float> B, int N,
                                                       size_t ng, size_t kchunk,
                                                       float* __restrict__ part, int tri) {
@@ -234,16 +282,24 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int li = lane & 15, lg = lane >> 4;
+  float4 xb[MT / 16];
+  if constexpr (PREF) load_rows<VEC>(B, rows_b, k0, ng, xb);
   for (size_t kt = k0; kt < k1; kt += KB) {
+    if constexpr (PREF) {
+      store_rows(xb, n0, N, kt, k1, Bh, Bl);
+      if (kt + KB < k1) load_rows<VEC>(B, rows_b, kt + KB, ng, xb);
+    }
     // product (generated) operands load two rows; the choice is uniform per launch
     if (A.q)
       stage_tile<VEC, true>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
     else
       stage_tile<VEC, false>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
-    if (B.q)
-      stage_tile<VEC, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
-    else
-      stage_tile<VEC, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+    if constexpr (!PREF) {
+      if (B.q)
+        stage_tile<VEC, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+      else
+        stage_tile<VEC, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+    }
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < KB; ks += 32) {
@@ -377,14 +433,14 @@ void tda_impl(const void* occ, int no, const void* virt, int nv, const void* v_o
       TraceScope ts(tr, TR_TDA_GEMM);
       dim3 gj(tj * (tj + 1) / 2, 1, w.nsplit);  // upper tiles only: CJ is symmetric
       if (ng % 4 == 0)
-        k_gemm_nt_mfma<true><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
+        k_gemm_nt_mfma<true, true><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
       else
-        k_gemm_nt_mfma<false><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
+        k_gemm_nt_mfma<false, true><<<gj, 256, 0, s>>>(a_ov, nov, b_ov, nov, ng, w.kchunk, (float*)pj, 1);
       dim3 gk((noo + MT - 1) / MT, (nvv + MT - 1) / MT, w.nsplit);
       if (ng % 4 == 0)
-        k_gemm_nt_mfma<true><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
+        k_gemm_nt_mfma<true, false><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
       else
-        k_gemm_nt_mfma<false><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
+        k_gemm_nt_mfma<false, false><<<gk, 256, 0, s>>>(a_oo, noo, b_vv, nvv, ng, w.kchunk, (float*)pk, 0);
     }
     TraceScope ts(tr, TR_TDA_REDUCE);
     k_split_reduce_f32<<<rbj, 256, 0, s>>>((const float*)pj, w.nsplit, cntj, dv, cj, nov);
@@ -487,13 +543,28 @@ void launch_strength(const double* omega, const double* f, int k, double w0, dou
 size_t tda_workspace_bytes(int no, int nv, size_t ng, bool fp64, TdaWork* w) {
   const size_t nov = (size_t)no * nv, noo = (size_t)no * (no + 1) / 2,
                nvv = (size_t)nv * (nv + 1) / 2;
-  // enough blocks for the GPU: at least ~1024 for the larger contraction
-  const size_t tile = fp64 ? BM : MT;
-  const size_t tiles = ((nov + tile - 1) / tile) * ((nov + tile - 1) / tile);
-  size_t nsplit = (1024 + tiles - 1) / tiles;
-  size_t kchunk = (ng + nsplit - 1) / nsplit;
-  kchunk = ((kchunk + kSub - 1) / kSub) * kSub;
-  if (kchunk < kSub) kchunk = kSub;
+  size_t nsplit, kchunk;
+  if (fp64) {
+    // enough blocks for the GPU: at least ~1024 for the larger contraction
+    const size_t tiles = ((nov + BM - 1) / BM) * ((nov + BM - 1) / BM);
+    nsplit = (1024 + tiles - 1) / tiles;
+    kchunk = (ng + nsplit - 1) / nsplit;
+    kchunk = ((kchunk + kSub - 1) / kSub) * kSub;
+    if (kchunk < kSub) kchunk = kSub;
+  } else {
+    // matrix-core contractions: one wave of workgroups (two per CU, as their LDS allows) for
+    // the larger launch, so no partly filled second wave; K chunks of whole 64-point tiles
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    const size_t tj = (nov + MT - 1) / MT;
+    const size_t tiles = std::max(tj * (tj + 1) / 2, ((noo + MT - 1) / MT) * ((nvv + MT - 1) / MT));
+    nsplit = std::max<size_t>(1, (size_t)(2 * cus) / tiles);
+    kchunk = (ng + nsplit - 1) / nsplit;
+    kchunk = ((kchunk + KB - 1) / KB) * KB;
+  }
   nsplit = (ng + kchunk - 1) / kchunk;
   w->nsplit = (int)nsplit;
   w->kchunk = kchunk;
@@ -525,10 +596,18 @@ void gemm_full(Op<T> A, int M, Op<T> B, int N, size_t ng, const UhfWork& w, void
   const unsigned rb = (unsigned)std::min<size_t>(4096, (cnt + 255) / 256);
   if constexpr (sizeof(T) == 4) {
     dim3 g((M + MT - 1) / MT, (N + MT - 1) / MT, w.nsplit);
-    if (ng % 4 == 0)
-      k_gemm_nt_mfma<true><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
-    else
-      k_gemm_nt_mfma<false><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+    const bool pref = B.q == nullptr;
+    if (ng % 4 == 0) {
+      if (pref)
+        k_gemm_nt_mfma<true, true><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+      else
+        k_gemm_nt_mfma<true, false><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+    } else {
+      if (pref)
+        k_gemm_nt_mfma<false, true><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+      else
+        k_gemm_nt_mfma<false, false><<<g, 256, 0, s>>>(A, M, B, N, ng, w.kchunk, (float*)part, 0);
+    }
     k_split_reduce_f32<<<rb, 256, 0, s>>>((const float*)part, w.nsplit, cnt, scale, out, 0);
   } else {
     dim3 g((M + BM - 1) / BM, (N + BN - 1) / BN, w.nsplit);
