@@ -420,9 +420,14 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
   typedef typename Elem<E>::wide W;
   constexpr bool CPLX = Elem<E>::cplx;
   constexpr int LD = kThreads + 1;
-  __shared__ E lp[NMAX * LD];
-  __shared__ E lw[NMAX * LD];
-  __shared__ W red[kGramWaves][256];
+  // phi and W of the workgroup's points; the cross-wavefront sums reuse the same LDS once the
+  // products are done (halves the footprint: two workgroups per CU at 16 orbitals)
+  constexpr size_t kStage = 2 * (size_t)NMAX * LD * sizeof(E);
+  constexpr size_t kRed = (size_t)kGramWaves * 256 * sizeof(W);
+  __shared__ __align__(16) unsigned char smem[kStage > kRed ? kStage : kRed];
+  E* lp = reinterpret_cast<E*>(smem);
+  E* lw = lp + NMAX * LD;
+  W(*red)[256] = reinterpret_cast<W(*)[256]>(smem);
   const MolArgs m = src.get(blockIdx.y);
   const E* __restrict__ phi = (const E*)m.phi;
   const E* __restrict__ v = (const E*)m.v;
@@ -478,7 +483,8 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
         split_ri(lw[(ri < NMAX ? ri : 0) * LD + pt], br, bi);
         d = mma64(imag ? ai : ar, imag ? bi : br, d);
       }
-    double* rd = reinterpret_cast<double*>(&red[0][0]);
+    double* rd = reinterpret_cast<double*>(smem);
+    __syncthreads();  // every wavefront is done with lp / lw
 #pragma unroll
     for (int e = 0; e < 4; ++e) rd[wave * 256 + (g + 4 * e) * 16 + li] = d[e];
     __syncthreads();
@@ -517,6 +523,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
           t1 = mma64(ar, br, t1);
         }
       }
+    __syncthreads();  // every wavefront is done with lp / lw
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int tt = (g + 4 * e) * 16 + li;
