@@ -25,7 +25,12 @@ namespace ace {
 
 namespace {
 
-constexpr int kThreads = 256;  // z passes
+// threads of the z passes: their plane of N x (P + 1) elements limits them to two or three
+// workgroups per CU from N = 56 on, so those edges use 512 threads to keep enough wavefronts
+template <int N>
+constexpr int z_threads() {
+  return N >= 56 ? 512 : 256;
+}
 #ifndef ACE_XY_THREADS
 #define ACE_XY_THREADS 1024
 #endif
@@ -126,7 +131,7 @@ struct PairsByPointer {
 // ---------------------------------------------------------------------------------------
 // Z-forward pass
 template <typename T, int N, bool RP, typename R>
-__global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ work,
+__global__ __launch_bounds__(z_threads<N>()) void k_zfwd(R res, C2<T>* __restrict__ work,
                                                    const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ wo
     cb = res.template b<C2<T>>(p, NG) + plane;
   }
 
-  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P2; it += z_threads<N>()) {
     const int n2 = it % P2, y = it / P2;
     C2<T> v[P1];
 #pragma unroll
@@ -182,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(R res, C2<T>* __restrict__ wo
   }
   __syncthreads();
   C2<T>* dst0 = work + (size_t)p * P * N * N + (size_t)x * N;
-  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P1; it += z_threads<N>()) {
     const int y = it % N, k1 = it / N;
     C2<T> v[P2];
 #pragma unroll
@@ -298,7 +303,7 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
 // ---------------------------------------------------------------------------------------
 // Z-inverse pass
 template <typename T, int N, bool RP, typename R>
-__global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ work, R res,
+__global__ __launch_bounds__(z_threads<N>()) void k_zinv(const C2<T>* __restrict__ work, R res,
                                                    const C2<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
@@ -307,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ wor
   const C2<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
   const int x = blockIdx.x, p = blockIdx.y;
   const C2<T>* src0 = work + (size_t)p * P * N * N + (size_t)x * N;
-  for (int it = threadIdx.x; it < N * P1; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P1; it += z_threads<N>()) {
     const int y = it % N, k1 = it / N;
     C2<T> v[P2];
 #pragma unroll
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_zinv(const C2<T>* __restrict__ wor
     for (int k2 = 0; k2 < P2; ++k2) buf[y * RS + k1 * P2 + k2] = v[k2];
   }
   __syncthreads();
-  for (int it = threadIdx.x; it < N * P2; it += kThreads) {
+  for (int it = threadIdx.x; it < N * P2; it += z_threads<N>()) {
     const int n2 = it % P2, y = it / P2;
     C2<T> v[P1];
     v[0] = buf[y * RS + n2];
@@ -439,9 +444,9 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
   {
     TraceScope ts(tr, TR_ZFWD);
     if (rp)
-      k_zfwd<T, N, true, R><<<gz, kThreads, lds_z, s>>>(res, w, t);
+      k_zfwd<T, N, true, R><<<gz, z_threads<N>(), lds_z, s>>>(res, w, t);
     else
-      k_zfwd<T, N, false, R><<<gz, kThreads, lds_z, s>>>(res, w, t);
+      k_zfwd<T, N, false, R><<<gz, z_threads<N>(), lds_z, s>>>(res, w, t);
   }
   {
     TraceScope ts(tr, TR_XY);
@@ -450,9 +455,9 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
   {
     TraceScope ts(tr, TR_ZINV);
     if (rp)
-      k_zinv<T, N, true, R><<<gz, kThreads, lds_z, s>>>(w, res, t);
+      k_zinv<T, N, true, R><<<gz, z_threads<N>(), lds_z, s>>>(w, res, t);
     else
-      k_zinv<T, N, false, R><<<gz, kThreads, lds_z, s>>>(w, res, t);
+      k_zinv<T, N, false, R><<<gz, z_threads<N>(), lds_z, s>>>(w, res, t);
   }
 }
 
