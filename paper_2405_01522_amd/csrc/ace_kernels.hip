@@ -271,49 +271,62 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng) {
   if ((int)blockIdx.y * TB >= tiles_l || na > 8) return;  // beyond this system, or k_gram's
   constexpr int CHUNK = kGramPoints / WAVES;  // points per wavefront
   constexpr int NQ = CHUNK / 16;
-  static_assert(NQ >= 1 && CHUNK % 16 == 0, "whole 16-point steps per wavefront");
+  static_assert(NQ >= 2 && NQ % 2 == 0 && CHUNK % 16 == 0, "even number of 16-point steps");
+  constexpr int NH = NQ / 2;
   __shared__ double red[WAVES][TB * 256];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int ri = li & 7;
   const bool imag = li >= 8;
-  const E* ra = A + (size_t)(ri < na ? ri : na - 1) * ng;
   const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * CHUNK;
-  E av[NQ][4];
+  // Lanes li and li + 8 work on the same row (real and imaginary part).  Each loads half of the
+  // wavefront's steps (li < 8 the first NH, li >= 8 the last NH) and gets the other half's
+  // component from its partner lane (li ^ 8), so every element is loaded once.
+  const int q0 = imag ? NH : 0;
+  auto operands = [&](const E (*v)[4], int row, int nrow, double (*op)[4]) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) load4<E, VEC>(ra, start + 16 * q + 4 * g, ng, av[q]);
+    for (int j = 0; j < NH; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const size_t r = start + 16 * (q0 + j) + 4 * g + s;
+        typedef typename Elem<E>::real Rl;
+        const bool ok = row < nrow && r < ng;
+        const Rl xr = ok ? v[j][s].r : Rl(0), xi = ok ? v[j][s].i : Rl(0);
+        // first half: li < 8 own real part, li >= 8 the partner's imaginary part
+        const Rl gi = __shfl_xor(xi, 8, 64);
+        // second half: li >= 8 own imaginary part, li < 8 the partner's real part
+        const Rl gr = __shfl_xor(xr, 8, 64);
+        op[j][s] = imag ? (double)gi : (double)xr;
+        op[NH + j][s] = imag ? (double)xi : (double)gr;
+      }
+  };
+  const E* ra = A + (size_t)(ri < na ? ri : na - 1) * ng;
+  E av[NH][4];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) load4<E, VEC>(ra, start + 16 * (q0 + j) + 4 * g, ng, av[j]);
   double ao[NQ][4];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const size_t r = start + 16 * q + 4 * g + s;
-      ao[q][s] = (ri < na && r < ng) ? (imag ? (double)av[q][s].i : (double)av[q][s].r) : 0.0;
-    }
+  operands(av, ri, na, ao);
   // every B tile's loads are issued before the first product
-  E bv[TB][NQ][4];
+  E bv[TB][NH][4];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
     if (l0 >= nb) break;  // uniform
     const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) load4<E, VEC>(rb, start + 16 * q + 4 * g, ng, bv[t][q]);
+    for (int j = 0; j < NH; ++j) load4<E, VEC>(rb, start + 16 * (q0 + j) + 4 * g, ng, bv[t][j]);
   }
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
     if (l0 >= nb) break;  // uniform; these outputs are not written
+    double bo[NQ][4];
+    operands(bv[t], lb, nb, bo);
     gf64x4 d = {};
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const size_t r = start + 16 * q + 4 * g + s;
-        const double bo =
-            (lb < nb && r < ng) ? (imag ? (double)bv[t][q][s].i : (double)bv[t][q][s].r) : 0.0;
-        d = mma64(ao[q][s], bo, d);
-      }
+      for (int s = 0; s < 4; ++s) d = mma64(ao[q][s], bo[q][s], d);
 #pragma unroll
     for (int e = 0; e < 4; ++e) red[wave][t * 256 + (g + 4 * e) * 16 + li] = d[e];
   }
