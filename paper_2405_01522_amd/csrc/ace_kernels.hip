@@ -818,14 +818,17 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
   const int n = ma.n;
   const typename Elem<E>::wide* __restrict__ linvh = (const typename Elem<E>::wide*)ma.linvh;
   __shared__ E lh[NMAX * NMAX];
+  // this thread's W values are requested before the staging of L^{-H}, so the two loads
+  // overlap (points past the end read the last point and are not stored)
+  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t rc = r < ng ? r : ng - 1;
+  E wr[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + rc];
   for (int t = threadIdx.x; t < n * n; t += kThreads)
     lh[(t / n) * NMAX + t % n] = e_narrow<E>(linvh[t]);
   __syncthreads();
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
-  E wr[NMAX];
-#pragma unroll
-  for (int i = 0; i < NMAX; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + r];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) {
     if (k < n) {
@@ -845,16 +848,19 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
                                                         int nv, E* __restrict__ out) {
   __shared__ E zs[NMAX * VB];
   const int v0 = blockIdx.y * VB;
+  // xi is requested before the staging of Z, so the two loads overlap (points past the end
+  // read the last point and are not stored)
+  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t rc = r < ng ? r : ng - 1;
+  E xr[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) xr[k] = xi[(size_t)(k < n ? k : n - 1) * ng + rc];
   for (int t = threadIdx.x; t < n * VB; t += kThreads) {
     const int k = t / VB, vb = t % VB;
     zs[k * VB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
   }
   __syncthreads();
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= ng) return;
-  E xr[NMAX];
-#pragma unroll
-  for (int k = 0; k < NMAX; ++k) xr[k] = xi[(size_t)(k < n ? k : n - 1) * ng + r];
 #pragma unroll
   for (int vb = 0; vb < VB; ++vb) {
     const int v = v0 + vb;
