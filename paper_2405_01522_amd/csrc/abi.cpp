@@ -223,10 +223,10 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   if (rc) return rc;
   char* mred = (char*)c->small.p;
   char* linvh = mred + wide * (size_t)n * n;
-  launch_wacc_gram_chol(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p,
-                        c->h * c->h * c->h, mred, M_out, ex_out, linvh, c->status, c->stream,
-                        c->tr());
-  launch_trsm(c->dtype, c->wbuf.p, n, ng, linvh, xi_out, c->stream, c->tr());
+  launch_wacc_gram(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p, c->h * c->h * c->h,
+                   mred, c->stream, c->tr());
+  launch_chol_trsm(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->wbuf.p, ng, xi_out,
+                   c->stream, c->tr());
   return hip_check(hipGetLastError());
 }
 
@@ -250,8 +250,8 @@ int ace_build_targets(ace_ctx* c, const void* phi_occ, int no, const void* psi, 
   char* linvh = mred + wide * (size_t)nt * nt;
   launch_gram(c->dtype, psi, nt, c->wbuf.p, nt, ng, c->part.p, c->h * c->h * c->h, mred, c->stream,
               c->tr());
-  launch_chol(c->dtype, mred, nt, M_out, nullptr, linvh, c->status, c->stream, c->tr());
-  launch_trsm(c->dtype, c->wbuf.p, nt, ng, linvh, xi_out, c->stream, c->tr());
+  launch_chol_trsm(c->dtype, mred, nt, M_out, nullptr, linvh, c->status, c->wbuf.p, ng, xi_out,
+                   c->stream, c->tr());
   return hip_check(hipGetLastError());
 }
 

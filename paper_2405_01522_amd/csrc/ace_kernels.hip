@@ -367,13 +367,16 @@ __device__ __forceinline__ C2<double> w_from_real(double r, C2<double>) { return
 // elimination step is one pivot broadcast and one rank-1 update across the whole wavefront,
 // and L^{-1} is formed the same way, one column step at a time, so the dependent chain is
 // O(n) broadcasts instead of O(n^2) serial multiply-adds per lane.
+// lds_linvh (optional): L^{-H} also into LDS (same layout); globals: write M, E_x, L^{-H} and
+// the status to memory (false in all but one of the workgroups that factorise redundantly).
 template <typename W>
-__device__ __forceinline__ void chol_lanes_body(const MolArgs& ma, const W* msrc) {
+__device__ __forceinline__ void chol_lanes_body(const MolArgs& ma, const W* msrc,
+                                                W* lds_linvh = nullptr, bool globals = true) {
   const int n = ma.n;
-  W* __restrict__ m_out = (W*)ma.m_out;
-  double* __restrict__ ex_out = ma.ex_out;
+  W* __restrict__ m_out = globals ? (W*)ma.m_out : nullptr;
+  double* __restrict__ ex_out = globals ? ma.ex_out : nullptr;
   W* __restrict__ linvh = (W*)ma.linvh;
-  int* __restrict__ status = ma.status;
+  int* __restrict__ status = globals ? ma.status : nullptr;
   const int lane = threadIdx.x & 63, i = lane >> 3, k = lane & 7;
   const bool in = i < n && k < n;
   W a = W{};
@@ -415,7 +418,11 @@ __device__ __forceinline__ void chol_lanes_body(const MolArgs& ma, const W* msrc
   }
   const bool ok = fail < 0 && !any_bad;
   // L^{-H}[c][r] = conj(X[r][c]); this lane holds X[i][k]
-  if (in) linvh[k * n + i] = ok ? e_conj(x) : W{};
+  if (in) {
+    const W v = ok ? e_conj(x) : W{};
+    if (globals) linvh[k * n + i] = v;
+    if (lds_linvh) lds_linvh[k * n + i] = v;
+  }
   if (lane == 0 && !ok && status && status[0] == 0) {
     status[0] = any_bad ? -6 : -5;
     status[1] = any_bad ? -1 : fail;
@@ -840,6 +847,39 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
   }
 }
 
+// Cholesky (n <= 8) and xi = W L^{-H} in one launch: every workgroup factorises M itself in
+// its first wavefront (the same arithmetic as k_chol_lanes, so the same bits) while its W
+// values load; workgroup 0 writes M, E_x, L^{-H} and the status.
+template <typename E, typename S>
+__global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng) {
+  typedef typename Elem<E>::wide W;
+  const MolArgs ma = src.get(blockIdx.y);
+  const E* w = (const E*)ma.w;  // xi may alias w
+  E* xi = (E*)ma.xi;
+  const int n = ma.n;
+  __shared__ W lw[64];
+  __shared__ E lh[64];
+  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t rc = r < ng ? r : ng - 1;
+  E wr[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + rc];
+  if (threadIdx.x < 64) chol_lanes_body<W>(ma, (const W*)ma.mred, lw, blockIdx.x == 0);
+  __syncthreads();
+  for (int t = threadIdx.x; t < n * n; t += kThreads) lh[(t / n) * 8 + t % n] = e_narrow<E>(lw[t]);
+  __syncthreads();
+  if (r >= ng) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < n) {
+      E s = e_zero<E>();
+#pragma unroll
+      for (int i = 0; i <= k; ++i) s = e_add(s, e_mul(wr[i], lh[i * 8 + k]));
+      xi[(size_t)k * ng + r] = s;
+    }
+  }
+}
+
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
 // groups of VB vectors); the group's slice of Z is staged in LDS in the storage precision.
 template <typename E, int NMAX, int VB>
@@ -1058,10 +1098,9 @@ static void reduce_any(int et, S src, int nout, int nsys, int nblk, double scale
     reduce_launch<double, S>(src, nout, nsys, nblk, scale, s);
 }
 
-void launch_wacc_gram_chol(int et, const void* phi, const void* v, int n, size_t ng, void* w,
-                           void* part, double scale, void* mred, void* m_out, double* ex_out,
-                           void* linvh, int* status, hipStream_t s, Trace* tr) {
-  MolArgs m = single(phi, v, w, nullptr, mred, linvh, m_out, ex_out, status, n);
+void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                      void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
+  MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n);
   m.part = part;
   bool done = false;
   {
@@ -1077,7 +1116,25 @@ void launch_wacc_gram_chol(int et, const void* phi, const void* v, int n, size_t
     const int nch = gram_blocks(ng, &chunk);
     reduce_any(et, OneRed{RedArgs{part, n * n, mred}}, n * n, 1, nch, scale, s);
   }
-  launch_chol(et, mred, n, m_out, ex_out, linvh, status, s, tr);
+}
+
+void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
+                      int* status, const void* w, size_t ng, void* xi, hipStream_t s, Trace* tr) {
+  if (n > 8) {
+    launch_chol(et, mred, n, m_out, ex_out, linvh, status, s, tr);
+    launch_trsm(et, w, n, ng, linvh, xi, s, tr);
+    return;
+  }
+  TraceScope ts(tr, TR_TRSM);
+  OneMol src{single(nullptr, nullptr, const_cast<void*>(w), xi, const_cast<void*>(mred), linvh,
+                    m_out, ex_out, status, n)};
+  dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), 1);
+  switch (et) {
+    case ET_C128: k_chol_trsm<C2<double>, OneMol><<<grid, kThreads, 0, s>>>(src, ng); break;
+    case ET_C64: k_chol_trsm<C2<float>, OneMol><<<grid, kThreads, 0, s>>>(src, ng); break;
+    case ET_R64: k_chol_trsm<double, OneMol><<<grid, kThreads, 0, s>>>(src, ng); break;
+    case ET_R32: k_chol_trsm<float, OneMol><<<grid, kThreads, 0, s>>>(src, ng); break;
+  }
 }
 
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,

@@ -33,13 +33,14 @@ int gram_blocks(size_t ng, size_t* chunk);
 
 
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr);
-// W accumulation, M = scale * Phi^H W into mred (n*n FP64, complex or real), then the
-// Cholesky step of launch_chol.  W and the Gram partials come from one fused kernel when the
-// orbitals fit its LDS tile (n <= 16; 8 for complex FP64), else from the separate kernels.
-// part: gram_blocks(ng) * n * n partials.
-void launch_wacc_gram_chol(int et, const void* phi, const void* v, int n, size_t ng, void* w,
-                           void* part, double scale, void* mred, void* m_out, double* ex_out,
-                           void* linvh, int* status, hipStream_t s, Trace* tr);
+// W accumulation and M = scale * Phi^H W into mred (n*n FP64, complex or real).  W and the
+// Gram partials come from one fused kernel when the orbitals fit its LDS tile (n <= 16; 8 for
+// complex FP64), else from the separate kernels.  part: gram_blocks(ng) * n * n partials.
+void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                      void* part, double scale, void* mred, hipStream_t s, Trace* tr);
+// launch_chol followed by launch_trsm (one fused kernel for n <= 8).
+void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
+                      int* status, const void* w, size_t ng, void* xi, hipStream_t s, Trace* tr);
 // out[k*nb + l] = scale * sum_r conj(A_k(r)) B_l(r), FP64 (complex or real), any na, nb.
 // part: gram_blocks(ng) * na * nb FP64 elements.
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
