@@ -880,6 +880,22 @@ __global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng) {
   }
 }
 
+// Streaming (nontemporal) store: the K psi outputs are not read again by this step, and the
+// hint keeps them from displacing cached data (measured 11.7 -> 9.8 us at 48^3, 32 vectors).
+template <typename E>
+__device__ __forceinline__ void store_stream(E* p, E v) {
+  if constexpr (Elem<E>::cplx) {
+    typedef typename Elem<E>::real R;
+    typedef R R2 __attribute__((ext_vector_type(2)));
+    R2 x;
+    x.x = v.r;
+    x.y = v.i;
+    __builtin_nontemporal_store(x, reinterpret_cast<R2*>(p));
+  } else {
+    __builtin_nontemporal_store(v, p);
+  }
+}
+
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
 // groups of VB vectors); the group's slice of Z is staged in LDS in the storage precision.
 template <typename E, int NMAX, int VB>
@@ -909,7 +925,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
 #pragma unroll
       for (int k = 0; k < NMAX; ++k)
         if (k < n) s = e_add(s, e_mul(xr[k], zs[k * VB + vb]));
-      out[(size_t)v * ng + r] = e_neg(s);
+      store_stream(out + (size_t)v * ng + r, e_neg(s));
     }
   }
 }
