@@ -212,6 +212,7 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   const size_t wide = cplx ? 16 : 8;
   size_t chunk;
   const int nblk = gram_blocks(ng, &chunk);
+  // (upload_pairs counts 2-int records: a 4-int slot is two of them)
   int rc = upload_pairs(c, pl.data(), (int)(pl.size() / 2));
   if (!rc) rc = ensure(c, c->vbuf, eb * ng * (size_t)np);
   if (!rc) rc = ensure(c, c->wbuf, eb * ng * (size_t)n);

@@ -664,13 +664,13 @@ void uhf_impl(const UhfSpin* sp, size_t ng, double dv, void* ws, const UhfWork& 
     TraceScope ts(tr, TR_TDA_GEMM);
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
-        Op<T> rho{(const T*)sp[a].occ, (const T*)sp[a].virt, sp[a].nv};
-        Op<T> vt{(const T*)sp[b].v_ov, nullptr, 1};
+        Op<T> rho{(const T*)sp[a].occ, (const T*)sp[a].virt, sp[a].nv, 0};
+        Op<T> vt{(const T*)sp[b].v_ov, nullptr, 1, 0};
         gemm_full<T>(rho, sp[a].no * sp[a].nv, vt, sp[b].no * sp[b].nv, ng, w, part, dv, g1[a][b], s);
       }
     for (int a = 0; a < 2; ++a) {
-      Op<T> voo{(const T*)sp[a].v_oo, nullptr, 1};
-      Op<T> rvv{(const T*)sp[a].virt, (const T*)sp[a].virt, sp[a].nv};
+      Op<T> voo{(const T*)sp[a].v_oo, nullptr, 1, 0};
+      Op<T> rvv{(const T*)sp[a].virt, (const T*)sp[a].virt, sp[a].nv, 0};  // all nv^2 pairs
       gemm_full<T>(voo, sp[a].no * (sp[a].no + 1) / 2, rvv, sp[a].nv * sp[a].nv, ng, w, part, dv,
                    g2[a], s);
     }
