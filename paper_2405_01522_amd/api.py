@@ -23,6 +23,14 @@ MAX_ORBITALS = 64           # real orbitals
 MAX_ORBITALS_COMPLEX = 32   # complex orbitals
 
 
+def _device(device):
+    """torch.device with an explicit GPU index (the current device when none is given)."""
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    if d.type != "cuda":
+        raise ValueError("device must be a GPU, got %s" % d)
+    return d if d.index is not None else torch.device("cuda", torch.cuda.current_device())
+
+
 def dtype_code(dtype):
     if dtype not in _DTYPES:
         raise TypeError("unsupported orbital dtype %s" % dtype)
@@ -46,7 +54,7 @@ class AceContext:
         self.h = float(h)
         self.dtype = dtype
         self.code = dtype_code(dtype)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _device(device)
         with torch.cuda.device(self.device):
             handle = ctypes.c_void_p()
             check(lib().ace_ctx_create(self.n, self.h, self.code, _stream_handle(),
@@ -76,6 +84,8 @@ class AceContext:
     def _vol(self, t, name, count=None):
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError("%s must be a CUDA/HIP tensor" % name)
+        if t.device != self.device:
+            raise ValueError("%s is on %s, the context on %s" % (name, t.device, self.device))
         if t.dtype != self.dtype:
             raise TypeError("%s has dtype %s, context expects %s" % (name, t.dtype, self.dtype))
         if t.dim() != 4 or tuple(t.shape[1:]) != (self.n,) * 3:
@@ -162,7 +172,8 @@ class AceContext:
         eo = np.ascontiguousarray(eps_occ, dtype=np.float64)
         ev = np.ascontiguousarray(eps_virt, dtype=np.float64)
         nov = eo.size * ev.size
-        if not (c.is_cuda and c.dtype == torch.float64 and c.shape == (nov, nov) and c.is_contiguous()):
+        if not (c.is_cuda and c.device == self.device and c.dtype == torch.float64 and
+                c.shape == (nov, nov) and c.is_contiguous()):
             raise ValueError("c must be the (no*nv, no*nv) FP64 GPU coupling block")
         omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
         x = torch.empty((nstates, nov), dtype=torch.float64, device=self.device)
@@ -366,8 +377,8 @@ class AceContext:
         if record is not None:
             rin, rtg = record
             for t in (rin, rtg):
-                if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or \
-                        tuple(t.shape[1:]) != (self.n,) * 3:
+                if t.dtype != torch.float32 or not t.is_cuda or t.device != self.device or \
+                        not t.is_contiguous() or tuple(t.shape[1:]) != (self.n,) * 3:
                     raise ValueError("record tensors must be contiguous FP32 (cap, N, N, N)")
             o.rec_in, o.rec_tgt, o.rec_cap = rin.data_ptr(), rtg.data_ptr(), min(rin.shape[0], rtg.shape[0])
             o.rec_stride = int(record_stride)
@@ -428,7 +439,7 @@ class AceBatch:
     def __init__(self, dtype, device=None):
         self.dtype = dtype
         self.code = dtype_code(dtype)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _device(device)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self._stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -459,7 +470,8 @@ class AceBatch:
         arr = (AceMol * len(systems))()
         for k, sysd in enumerate(systems):
             phi = sysd["phi"]
-            if phi.dtype != self.dtype or not phi.is_cuda or not phi.is_contiguous() or phi.dim() != 4:
+            if phi.dtype != self.dtype or not phi.is_cuda or phi.device != self.device or \
+                    not phi.is_contiguous() or phi.dim() != 4:
                 raise ValueError("system %d: phi must be a contiguous (norb, n, n, n) %s GPU tensor"
                                  % (k, self.dtype))
             norb, n = phi.shape[0], phi.shape[1]
@@ -522,7 +534,7 @@ class ConvNet:
     parameters live on the device.  Calls run on the stream current at creation."""
 
     def __init__(self, params=None, device=None):
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _device(device)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(lib().convnet_create(_stream_handle(), ctypes.byref(handle)), "convnet_create")

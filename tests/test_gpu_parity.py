@@ -188,6 +188,21 @@ def test_exchange_direct_and_ace_identical_on_occupied():
     assert _rel(k_dir_psi, ref) < 1e-10
 
 
+def test_context_device_without_index():
+    """A context made for device "cuda" (no index) takes the current GPU and accepts its
+    tensors; a CPU tensor is refused before any launch."""
+    ace = _ace()
+    m = synth.small_complex(11, 12, 0.4, 3)
+    ctx = ace.AceContext(m.n, m.h, torch.complex128, "cuda")
+    assert ctx.device.index == torch.cuda.current_device()
+    xi, _, ex = ctx.ace_build(_t(m.phi, torch.complex128))
+    _, _, _, ex_ref = exchange.ace_build(m.phi, m.h)
+    assert abs(float(ex.cpu()) - ex_ref) < 1e-10 * abs(ex_ref)
+    with pytest.raises(TypeError):
+        ctx.ace_build(torch.from_numpy(m.phi))
+    ctx.close()
+
+
 def test_not_posdef_reported():
     ace = _ace()
     m = synth.small_complex(10, 12, 0.4, 3)
