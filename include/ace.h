@@ -377,7 +377,9 @@ typedef struct ace_eig_opts {
  * k lowest eigenpairs of F = T + v_local (+ K_ACE with nxi vectors xi, Eq. (13), if nxi > 0)
  * by LOBPCG: Rayleigh-Ritz over [X, M R, P] (current vectors, preconditioned residuals --
  * two blocks with ACE_PRECOND_NET --, previous directions; P is left out when the order would
- * pass 64), canonical orthonormalisation in FP64.
+ * pass 64), orthonormalisation in FP64 (Cholesky when the overlap is provably well conditioned,
+ * else canonical with small directions dropped); in FP32 storage F x is recomputed every 10
+ * steps.
  * The non-self-consistent run with a fixed Hamiltonian of Sec. 3.1.
  * phi: k start vectors, overwritten by the Ritz vectors (dV-orthonormal); eigval, resnorm
  * (host, k, may be NULL); *steps (host, may be NULL) = steps taken.  Synchronises.

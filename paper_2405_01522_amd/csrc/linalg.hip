@@ -88,7 +88,9 @@ __device__ __forceinline__ double rsq_nr(double x) {
 
 __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__ Ain, int lda,
                                                double* __restrict__ w, double* __restrict__ V,
-                                               int ldv, int max_sweeps, double tol) {
+                                               int ldv, int max_sweeps, double tol,
+                                               const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;  // the caller's result is already in place
   __shared__ double a[JMAX][JMAX + 1];
   __shared__ double v[JMAX][JMAX + 1];
   __shared__ double cs[JMAX / 2], sn[JMAX / 2];
@@ -200,6 +202,84 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
     V[(size_t)i * ldv + rank_s[k]] = v[i][k];
   }
   for (int k = threadIdx.x; k < n; k += JT) w[rank_s[k]] = a[k][k];
+}
+
+// Orthonormalisation of a basis from its Gram matrix S (n <= JMAX, symmetrised on load) by
+// Cholesky: S = L L^T, T = L^{-T}, so that T^T S T = I.  Accepted only when the smallest
+// eigenvalue of S is provably above thr: lambda_min >= 1 / tr(S^{-1}) = 1 / ||L^{-1}||_F^2.  On
+// acceptance T (row-major n x n) is written, w[0:n] = 1 and *ok = 1; otherwise only *ok = 0.
+// Right-looking factorisation with one barrier per column (the scaling of column j is deferred
+// to the next column's pass, which no longer reads it), then one thread per column of L^{-1}
+// by forward substitution.
+__global__ __launch_bounds__(JT) void k_chol_orth(int n, const double* __restrict__ S, double thr,
+                                                  double* __restrict__ T, double* __restrict__ w,
+                                                  int* __restrict__ ok) {
+  __shared__ double l[JMAX][JMAX + 1];
+  __shared__ double x[JMAX][JMAX + 1];
+  __shared__ double red[JT / 64];
+  for (int e = threadIdx.x; e < n * n; e += JT) {
+    const int i = e / n, j = e % n;
+    l[i][j] = 0.5 * (S[(size_t)i * n + j] + S[(size_t)j * n + i]);
+    x[i][j] = 0.0;
+  }
+  __syncthreads();
+  bool good = true;
+  double dprev = 0.0;  // pivot of the previous column, kept for its deferred scaling
+  for (int j = 0; j < n; ++j) {
+    const double d = l[j][j];  // same value in every thread: uniform control flow
+    if (!(d > 0.0) || !isfinite(d)) {
+      good = false;
+      break;
+    }
+    const double rd = 1.0 / d;
+    const int t = n - j - 1;
+    for (int e = threadIdx.x; e < t * t; e += JT) {
+      const int i = j + 1 + e / t, k = j + 1 + e % t;
+      if (k <= i) l[i][k] -= l[i][j] * l[k][j] * rd;
+    }
+    if (j > 0) {
+      const double sq = sqrt(dprev), rs = 1.0 / sq;
+      for (int i = j - 1 + threadIdx.x; i < n; i += JT)
+        l[i][j - 1] = (i == j - 1) ? sq : l[i][j - 1] * rs;
+    }
+    dprev = d;
+    __syncthreads();
+  }
+  if (!good) {
+    if (threadIdx.x == 0) *ok = 0;
+    return;
+  }
+  if (threadIdx.x == 0) l[n - 1][n - 1] = sqrt(dprev);
+  __syncthreads();
+  // column c of L^{-1}: x[i][c] = (delta_ic - sum_{k<i} l[i][k] x[k][c]) / l[i][i]; zeros above
+  // the diagonal make the loops uniform across the wavefront
+  if ((int)threadIdx.x < n) {
+    const int c = threadIdx.x;
+    for (int i = 0; i < n; ++i) {
+      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
+      int k = 0;
+      for (; k + 1 < i; k += 2) {
+        s0 -= l[i][k] * x[k][c];
+        s1 -= l[i][k + 1] * x[k + 1][c];
+      }
+      if (k < i) s0 -= l[i][k] * x[k][c];
+      x[i][c] = (s0 + s1) / l[i][i];
+    }
+  }
+  __syncthreads();
+  double fr = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += JT) fr += x[e / n][e % n] * x[e / n][e % n];
+  for (int o = 32; o > 0; o >>= 1) fr += __shfl_xor(fr, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fr;
+  __syncthreads();
+  double tr = 0.0;
+  for (int v = 0; v < JT / 64; ++v) tr += red[v];
+  const bool accept = isfinite(tr) && tr * thr < 1.0;
+  if (accept) {
+    for (int e = threadIdx.x; e < n * n; e += JT) T[e] = x[e % n][e / n];  // T[i][j] = L^{-1}[j][i]
+    for (int j = threadIdx.x; j < n; j += JT) w[j] = 1.0;
+  }
+  if (threadIdx.x == 0) *ok = accept ? 1 : 0;
 }
 
 // A = C + diag(d) (copy); n x n row-major
@@ -377,8 +457,13 @@ void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const doubl
 }
 
 void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
-                   int max_sweeps, double tol, hipStream_t s) {
-  k_jacobi<<<1, JT, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol);
+                   int max_sweeps, double tol, hipStream_t s, const int* skip) {
+  k_jacobi<<<1, JT, 0, s>>>(n, A, lda, w, V, ldv, max_sweeps, tol, skip);
+}
+
+void launch_chol_orth(int n, const double* S, double thr, double* T, double* w, int* ok,
+                      hipStream_t s) {
+  k_chol_orth<<<1, JT, 0, s>>>(n, S, thr, T, w, ok);
 }
 
 }  // namespace ace

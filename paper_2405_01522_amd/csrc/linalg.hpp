@@ -12,8 +12,14 @@ void launch_dgemm(int ta, int tb, int M, int N, int K, double alpha, const doubl
                   const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
 
 // eigenvalues ascending in w[n], eigenvectors in the columns of V (ld ldv); n <= kJacobiMax
+// (a non-null skip pointing at a nonzero device int makes the launch a no-op)
 void launch_jacobi(int n, const double* A, int lda, double* w, double* V, int ldv,
-                   int max_sweeps, double tol, hipStream_t s);
+                   int max_sweeps, double tol, hipStream_t s, const int* skip = nullptr);
+// Cholesky orthonormalisation from a Gram matrix S (n <= kJacobiMax): T = L^{-T} with
+// S = L L^T, accepted (*ok = 1, w[0:n] = 1, T written) only when the smallest eigenvalue of S
+// is provably above thr; otherwise *ok = 0 and T, w untouched.  ok is device memory.
+void launch_chol_orth(int n, const double* S, double thr, double* T, double* w, int* ok,
+                      hipStream_t s);
 
 // Davidson helpers (rows of length n are vectors)
 void launch_add_diag(const double* C, const double* d, int n, double* A, hipStream_t s);

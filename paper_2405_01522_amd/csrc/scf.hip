@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kT) void k_sym_scale(const double* __restrict__ S,
 
 __global__ __launch_bounds__(kT) void k_canon(const double* __restrict__ w,
                                               const double* __restrict__ U, int m, double rel,
-                                              double* __restrict__ T) {
+                                              double* __restrict__ T, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;  // T already holds an accepted orthonormalisation
   const double wmax = w[m - 1];
   for (int e = threadIdx.x; e < m * m; e += kT) {
     const int j = e % m;
@@ -494,8 +495,9 @@ void launch_sym_scale(const double* S, const double* G, int m, double* Ss, doubl
   k_sym_scale<<<1, kT, 0, s>>>(S, G, m, Ss, Gs, D);
 }
 
-void launch_canon(const double* w, const double* U, int m, double rel, double* T, hipStream_t s) {
-  k_canon<<<1, kT, 0, s>>>(w, U, m, rel, T);
+void launch_canon(const double* w, const double* U, int m, double rel, double* T, hipStream_t s,
+                  const int* skip) {
+  k_canon<<<1, kT, 0, s>>>(w, U, m, rel, T, skip);
 }
 
 void launch_drop_diag(double* A, int m, const double* w, double rel, hipStream_t s) {

@@ -69,7 +69,8 @@ void launch_inv_rms(const double* G, int ld, int nv, double ng, double* scale, h
 void launch_sym_scale(const double* S, const double* G, int m, double* Ss, double* Gs,
                       double* D, hipStream_t s);
 // T[:, j] = U[:, j] / sqrt(w_j) if w_j > rel * max(w) else 0   (w ascending)
-void launch_canon(const double* w, const double* U, int m, double rel, double* T, hipStream_t s);
+void launch_canon(const double* w, const double* U, int m, double rel, double* T, hipStream_t s,
+                  const int* skip = nullptr);
 // for every dropped j (w_j <= rel * max(w)): A[j][j] = 1 + max_i sum_l |A[i][l]|, above the
 // spectrum of the kept block
 void launch_drop_diag(double* A, int m, const double* w, double rel, hipStream_t s);

@@ -62,6 +62,9 @@ struct Recorder {
   long long tick = 0;  // residual evaluations seen
 };
 
+// steps between explicit recomputations of F V in the FP32 block eigensolver
+constexpr int kRefresh = 10;
+
 // Workspace and steps of the block eigensolver for k vectors.
 struct Eig {
   ace_ctx* c = nullptr;
@@ -72,7 +75,7 @@ struct Eig {
   double h = 0, dv = 0;
   hipStream_t s = nullptr;
   Mem V, HV, V2, HV2, R, tmp, nin, nout;
-  Mem S, G, Ss, Gs, D, ws, U, T, TG, A, th, Y, Cm, Gr, rd, scale, part, zl;
+  Mem S, G, Ss, Gs, D, ws, U, T, TG, A, th, Y, Cm, Gr, rd, scale, part, zl, cholok;
   const void* lock = nullptr;  // converged vectors the search space is kept orthogonal to
   int nlock = 0;
   std::vector<double> h_rd;
@@ -110,6 +113,7 @@ struct Eig {
     for (Mem* m : {&D, &ws, &th, &rd, &scale})
       if (!rc) rc = m->alloc(sizeof(double) * kJacobiMax);
     if (!rc) rc = Gr.alloc(sizeof(double) * k * k);
+    if (!rc) rc = cholok.alloc(sizeof(int));
     size_t chunk;
     const int nblk = gram_blocks(ng, &chunk);
     nlock = nlock_;
@@ -146,15 +150,21 @@ struct Eig {
   }
 
   // Rayleigh-Ritz over m basis vectors with Gram S and projected operator G (both in S, G):
-  // scaled canonical orthonormalisation, Ritz values in th (ascending), coefficients of the
-  // k lowest Ritz vectors in Cm (m x k, row-major).
+  // scaled orthonormalisation, Ritz values in th (ascending), coefficients of the k lowest
+  // Ritz vectors in Cm (m x k, row-major).  The orthonormalisation is by Cholesky when the
+  // scaled Gram matrix is provably far from singular (its smallest eigenvalue above
+  // max(m rel, 1e-5): canonical orthonormalisation would drop nothing, so both span the same
+  // space and give the same Ritz pairs); otherwise, decided on the device, by the canonical
+  // one (Jacobi eigenvectors, directions below rel * max dropped).
   void rr(int m) {
     const double rel = fp64 ? 1e-12 : 1e-6;
     // Jacobi off-diagonal tolerance: far below the rounding of the grid vectors
     const double jtol = fp64 ? 1e-14 : 1e-11;
     launch_sym_scale(S.d(), G.d(), m, Ss.d(), Gs.d(), D.d(), s);
-    launch_jacobi(m, Ss.d(), m, ws.d(), U.d(), m, 60, jtol, s);
-    launch_canon(ws.d(), U.d(), m, rel, T.d(), s);
+    int* ok = (int*)cholok.p;
+    launch_chol_orth(m, Ss.d(), std::max(m * rel, 1e-5), T.d(), ws.d(), ok, s);
+    launch_jacobi(m, Ss.d(), m, ws.d(), U.d(), m, 60, jtol, s, ok);
+    launch_canon(ws.d(), U.d(), m, rel, T.d(), s, ok);
     launch_dgemm(1, 0, m, m, m, 1.0, T.d(), m, Gs.d(), m, 0.0, TG.d(), m, s);
     launch_dgemm(0, 0, m, m, m, 1.0, TG.d(), m, T.d(), m, 0.0, A.d(), m, s);
     launch_drop_diag(A.d(), m, ws.d(), rel, s);
@@ -246,6 +256,14 @@ struct Eig {
       std::swap(V.p, V2.p);
       std::swap(HV.p, HV2.p);
       ++steps;
+      // F V of the kept blocks is carried along by the same combinations as V.  In FP32
+      // storage the two drift apart by rounding, step after step, until the computed
+      // residuals stall near 1e-4 (64^3, h = 0.2); every kRefresh steps F V is recomputed.
+      if (!fp64 && steps % kRefresh == 0) {
+        rc = fock(vloc, xi, nxi, V.p, k, HV.p);
+        if (!rc && haveP) rc = fock(vloc, xi, nxi, vec(V, pb), k, vec(HV, pb));
+        if (rc) return rc;
+      }
     }
     rc = hip_check(hipMemcpyAsync(X, V.p, vb * k, hipMemcpyDeviceToDevice, s));
     *steps_out = steps;
