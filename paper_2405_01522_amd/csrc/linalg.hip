@@ -208,23 +208,24 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
 // Cholesky: S = L L^T, T = L^{-T}, so that T^T S T = I.  Accepted only when the smallest
 // eigenvalue of S is provably above thr: lambda_min >= 1 / tr(S^{-1}) = 1 / ||L^{-1}||_F^2.  On
 // acceptance T (row-major n x n) is written, w[0:n] = 1 and *ok = 1; otherwise only *ok = 0.
-// Right-looking factorisation with one barrier per column (the scaling of column j is deferred
-// to the next column's pass, which no longer reads it), then one thread per column of L^{-1}
-// by forward substitution.
+// Right-looking elimination, one barrier per column: step j updates the Schur complement of
+// the pivot d_j = l[j][j] and, in the same pass, eliminates column j from the right-hand side
+// Y (started at I, lower triangular): y_i -= l_ij y_j / d_j for i > j.  Then
+// L^{-1} = diag(d)^{-1/2} Y, and L itself is never formed.
 __global__ __launch_bounds__(JT) void k_chol_orth(int n, const double* __restrict__ S, double thr,
                                                   double* __restrict__ T, double* __restrict__ w,
                                                   int* __restrict__ ok) {
   __shared__ double l[JMAX][JMAX + 1];
-  __shared__ double x[JMAX][JMAX + 1];
+  __shared__ double y[JMAX][JMAX + 1];
+  __shared__ double piv[JMAX];
   __shared__ double red[JT / 64];
   for (int e = threadIdx.x; e < n * n; e += JT) {
     const int i = e / n, j = e % n;
     l[i][j] = 0.5 * (S[(size_t)i * n + j] + S[(size_t)j * n + i]);
-    x[i][j] = 0.0;
+    y[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   bool good = true;
-  double dprev = 0.0;  // pivot of the previous column, kept for its deferred scaling
   for (int j = 0; j < n; ++j) {
     const double d = l[j][j];  // same value in every thread: uniform control flow
     if (!(d > 0.0) || !isfinite(d)) {
@@ -232,43 +233,32 @@ __global__ __launch_bounds__(JT) void k_chol_orth(int n, const double* __restric
       break;
     }
     const double rd = 1.0 / d;
-    const int t = n - j - 1;
-    for (int e = threadIdx.x; e < t * t; e += JT) {
-      const int i = j + 1 + e / t, k = j + 1 + e % t;
-      if (k <= i) l[i][k] -= l[i][j] * l[k][j] * rd;
+    const int t = n - j - 1, c1 = j + 1;
+    // step j writes rows / columns > j of l and rows > j of y; it reads only column j of l
+    // and row j of y, which no thread writes in this step
+    for (int e = threadIdx.x; e < t * t + t * c1; e += JT) {
+      if (e < t * t) {
+        const int i = j + 1 + e / t, k = j + 1 + e % t;
+        if (k <= i) l[i][k] -= l[i][j] * l[k][j] * rd;
+      } else {
+        const int f = e - t * t;
+        const int i = j + 1 + f / c1, c = f % c1;
+        y[i][c] -= l[i][j] * y[j][c] * rd;
+      }
     }
-    if (j > 0) {
-      const double sq = sqrt(dprev), rs = 1.0 / sq;
-      for (int i = j - 1 + threadIdx.x; i < n; i += JT)
-        l[i][j - 1] = (i == j - 1) ? sq : l[i][j - 1] * rs;
-    }
-    dprev = d;
+    if (threadIdx.x == 0) piv[j] = d;
     __syncthreads();
   }
   if (!good) {
     if (threadIdx.x == 0) *ok = 0;
     return;
   }
-  if (threadIdx.x == 0) l[n - 1][n - 1] = sqrt(dprev);
-  __syncthreads();
-  // column c of L^{-1}: x[i][c] = (delta_ic - sum_{k<i} l[i][k] x[k][c]) / l[i][i]; zeros above
-  // the diagonal make the loops uniform across the wavefront
-  if ((int)threadIdx.x < n) {
-    const int c = threadIdx.x;
-    for (int i = 0; i < n; ++i) {
-      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
-      int k = 0;
-      for (; k + 1 < i; k += 2) {
-        s0 -= l[i][k] * x[k][c];
-        s1 -= l[i][k + 1] * x[k + 1][c];
-      }
-      if (k < i) s0 -= l[i][k] * x[k][c];
-      x[i][c] = (s0 + s1) / l[i][i];
-    }
-  }
-  __syncthreads();
+  // ||L^{-1}||_F^2 = sum_i |y_i|^2 / d_i (y lower triangular)
   double fr = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += JT) fr += x[e / n][e % n] * x[e / n][e % n];
+  for (int e = threadIdx.x; e < n * n; e += JT) {
+    const int i = e / n, c = e % n;
+    if (c <= i) fr += y[i][c] * y[i][c] / piv[i];
+  }
   for (int o = 32; o > 0; o >>= 1) fr += __shfl_xor(fr, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = fr;
   __syncthreads();
@@ -276,7 +266,11 @@ __global__ __launch_bounds__(JT) void k_chol_orth(int n, const double* __restric
   for (int v = 0; v < JT / 64; ++v) tr += red[v];
   const bool accept = isfinite(tr) && tr * thr < 1.0;
   if (accept) {
-    for (int e = threadIdx.x; e < n * n; e += JT) T[e] = x[e % n][e / n];  // T[i][j] = L^{-1}[j][i]
+    // T[i][j] = L^{-1}[j][i] = y[j][i] / sqrt(d_j) (zero above the diagonal of L^{-1})
+    for (int e = threadIdx.x; e < n * n; e += JT) {
+      const int i = e / n, j = e % n;
+      T[e] = i <= j ? y[j][i] / sqrt(piv[j]) : 0.0;
+    }
     for (int j = threadIdx.x; j < n; j += JT) w[j] = 1.0;
   }
   if (threadIdx.x == 0) *ok = accept ? 1 : 0;

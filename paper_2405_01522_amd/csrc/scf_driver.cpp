@@ -152,17 +152,20 @@ struct Eig {
   // Rayleigh-Ritz over m basis vectors with Gram S and projected operator G (both in S, G):
   // scaled orthonormalisation, Ritz values in th (ascending), coefficients of the k lowest
   // Ritz vectors in Cm (m x k, row-major).  The orthonormalisation is by Cholesky when the
-  // scaled Gram matrix is provably far from singular (its smallest eigenvalue above
-  // max(m rel, 1e-5): canonical orthonormalisation would drop nothing, so both span the same
-  // space and give the same Ritz pairs); otherwise, decided on the device, by the canonical
-  // one (Jacobi eigenvectors, directions below rel * max dropped).
+  // scaled Gram matrix is provably far from singular (its smallest eigenvalue above chol_min:
+  // canonical orthonormalisation would drop nothing, so both span the same space and give the
+  // same Ritz pairs); otherwise, decided on the device, by the canonical one (Jacobi
+  // eigenvectors, directions below rel * max dropped).  The Cholesky form loses about
+  // eps * cond(S) of orthonormality: chol_min keeps that below 1e-9 for FP32 storage and below
+  // 1e-13 for FP64.
   void rr(int m) {
     const double rel = fp64 ? 1e-12 : 1e-6;
     // Jacobi off-diagonal tolerance: far below the rounding of the grid vectors
     const double jtol = fp64 ? 1e-14 : 1e-11;
     launch_sym_scale(S.d(), G.d(), m, Ss.d(), Gs.d(), D.d(), s);
     int* ok = (int*)cholok.p;
-    launch_chol_orth(m, Ss.d(), std::max(m * rel, 1e-5), T.d(), ws.d(), ok, s);
+    const double chol_min = fp64 ? 1e-2 : std::max(m * rel, 1e-5);
+    launch_chol_orth(m, Ss.d(), chol_min, T.d(), ws.d(), ok, s);
     launch_jacobi(m, Ss.d(), m, ws.d(), U.d(), m, 60, jtol, s, ok);
     launch_canon(ws.d(), U.d(), m, rel, T.d(), s, ok);
     launch_dgemm(1, 0, m, m, m, 1.0, T.d(), m, Gs.d(), m, 0.0, TG.d(), m, s);
