@@ -134,6 +134,30 @@ def test_lowest_states_anisotropic_oscillator(precond):
         assert np.sqrt(np.sum(r * r) * h ** 3) < 2e-8
 
 
+def test_lowest_states_fp32_long_run():
+    """FP32 storage, a run long enough for the periodic recomputation of F x (every 10 steps)
+    and both orthonormalisation forms of the Rayleigh-Ritz step: 12 states of the anisotropic
+    oscillator to 1e-4 residuals, eigenvalues against the oracle's FP64 Lanczos values and the
+    Ritz vectors orthonormal to FP32 accuracy."""
+    ace = _ace()
+    n, h, k = 24, 0.3, 12
+    w = (1.0, 1.3, 1.6)
+    x = synth.coords(n, h)
+    v = 0.5 * (w[0] ** 2 * x[:, None, None] ** 2 + w[1] ** 2 * x[None, :, None] ** 2
+               + w[2] ** 2 * x[None, None, :] ** 2)
+    ref, _ = scf.lowest_states(lambda f: scf.kinetic(f, h) + v * f, n, k, h)
+    rng = np.random.default_rng(8)
+    ctx = ace.AceContext(n, h, torch.float32)
+    phi = _t(_orthonormal(rng, k, n, h), torch.float32)
+    opts = ace.eig_opts(max_steps=300, tol=1e-4, precond="kinetic", shift=1.0, sweeps=4)
+    ev, rn, steps = ctx.fock_lowest_states(_t(v[None], torch.float32), phi, opts=opts)
+    assert np.all(rn < 1e-4) and 10 < steps < 300, (rn, steps)
+    assert np.allclose(ev, ref, atol=2e-5), (ev, ref)
+    p = phi.cpu().numpy().astype(np.float64)
+    s = np.einsum("ixyz,jxyz->ij", p, p) * h ** 3
+    assert np.abs(s - np.eye(k)).max() < 1e-5
+
+
 def test_lowest_states_with_exchange_match_direct_operator():
     """With K_ACE built from orbitals phi, the lowest states of T + v + K_ACE restricted to...
     the occupied space coincide with the direct operator there (ACE exactness on the occupied
