@@ -156,8 +156,8 @@ struct Eig {
   // canonical orthonormalisation would drop nothing, so both span the same space and give the
   // same Ritz pairs); otherwise, decided on the device, by the canonical one (Jacobi
   // eigenvectors, directions below rel * max dropped).  The Cholesky form loses about
-  // eps * cond(S) of orthonormality: chol_min keeps that below 1e-9 for FP32 storage and below
-  // 1e-13 for FP64.
+  // eps * cond(S) of orthonormality (cond(S) <= m / lambda_min, the diagonal being 1):
+  // chol_min keeps that below 1e-9 for FP32 storage and below 2e-12 for FP64.
   void rr(int m) {
     const double rel = fp64 ? 1e-12 : 1e-6;
     // Jacobi off-diagonal tolerance: far below the rounding of the grid vectors
