@@ -118,6 +118,29 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
   }
   const int gx = x0 + lx, gy = y0 + ly;
   if (gx >= n || gy >= n) return;
+  // with n a multiple of 4 the thread's ZP = 4 points are one aligned 16-byte run (z0 + lz is
+  // a multiple of 4): one vector store per channel instead of four scattered ones
+  static_assert(ZP == 4 && TZ % 4 == 0, "four z-points per thread");
+  const bool vec4 = (n & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) |
+                                      (MASK ? reinterpret_cast<uintptr_t>(mask) : 0)) & 15) == 0;
+  if (vec4) {
+    const int gz = z0 + lz;
+    if (gz >= n) return;
+    const size_t pt = ((size_t)gx * n + gy) * n + gz;
+#pragma unroll
+    for (int o = 0; o < CO; ++o) {
+      float4 v = make_float4(acc[o][0], acc[o][1], acc[o][2], acc[o][3]);
+      if (RELU) v = make_float4(fmaxf(v.x, 0.f), fmaxf(v.y, 0.f), fmaxf(v.z, 0.f), fmaxf(v.w, 0.f));
+      const size_t oi = (sb * CO + o) * ng + pt;
+      if (MASK) {
+        const float4 m = *reinterpret_cast<const float4*>(mask + oi);
+        v = make_float4(m.x > 0.f ? v.x : 0.f, m.y > 0.f ? v.y : 0.f, m.z > 0.f ? v.z : 0.f,
+                        m.w > 0.f ? v.w : 0.f);
+      }
+      *reinterpret_cast<float4*>(out + oi) = v;
+    }
+    return;
+  }
 #pragma unroll
   for (int p = 0; p < ZP; ++p) {
     const int gz = z0 + lz + p;
