@@ -61,13 +61,17 @@ __device__ __forceinline__ void stage_halo(float* tile, const float* __restrict_
   }
 }
 
-// out[o](p) = act(b[o] + sum_i sum_t w[o][i][t] in[i](p + d_t)) (* (mask[o](p) > 0))
+// out[o](p) = act(b[o] + sum_i sum_t w[o][i][t] in[i](p + d_t)) (* (mask[o](p) > 0)).
+// The input channels pass through LDS four at a time (a 4-channel halo tile is 28.8 KB, so
+// five workgroups fit on a CU instead of two for all eight channels at once).
 template <int CI, int CO, bool BIAS, bool RELU, bool MASK>
 __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const float* __restrict__ w,
                                              const float* __restrict__ b,
                                              const float* __restrict__ mask, float* __restrict__ out,
                                              int n, int tny, int tnz) {
-  __shared__ float tile[CI * HVOL];
+  constexpr int CH = CI < 4 ? CI : 4;  // input channels per LDS stage
+  static_assert(CI % CH == 0, "whole stages");
+  __shared__ float tile[CH * HVOL];
   // weights re-laid out [i][t][o] (o fastest) so a tap's CO weights are one broadcast read
   constexpr int COP = CO < 4 ? 4 : CO;
   __shared__ __align__(16) float wl[CI * 27 * COP];
@@ -75,12 +79,10 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
   int x0, y0, z0;
   tile_origin(blockIdx.x, tny, tnz, &x0, &y0, &z0);
   const size_t sb = blockIdx.y;
-  stage_halo<CI>(tile, in + sb * CI * ng, n, ng, x0, y0, z0);
   for (int e = threadIdx.x; e < CI * 27 * COP; e += kT) {
     const int o = e % COP, it = e / COP;  // it = i * 27 + t
     wl[e] = o < CO ? w[(o * CI + it / 27) * 27 + it % 27] : 0.f;
   }
-  __syncthreads();
   const int lz = (threadIdx.x % 4) * ZP, ly = (threadIdx.x / 4) % TY, lx = threadIdx.x / 32;
   float acc[CO][ZP];
 #pragma unroll
@@ -88,33 +90,40 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
 #pragma unroll
     for (int p = 0; p < ZP; ++p) acc[o][p] = BIAS ? b[o] : 0.f;
 #pragma unroll 1
-  for (int i = 0; i < CI; ++i) {
+  for (int c0 = 0; c0 < CI; c0 += CH) {
+    if (c0 > 0) __syncthreads();  // every thread is done with the previous stage
+    stage_halo<CH>(tile, in + (sb * CI + c0) * ng, n, ng, x0, y0, z0);
+    __syncthreads();
 #pragma unroll 1
-    for (int dx = 0; dx < 3; ++dx)
+    for (int ii = 0; ii < CH; ++ii) {
+      const int i = c0 + ii;
+#pragma unroll 1
+      for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const float* col = tile + i * HVOL + ((lx + dx) * HY + (ly + dy)) * HZ + lz;
-        float c[ZP + 2];
+        for (int dy = 0; dy < 3; ++dy) {
+          const float* col = tile + ii * HVOL + ((lx + dx) * HY + (ly + dy)) * HZ + lz;
+          float c[ZP + 2];
 #pragma unroll
-        for (int u = 0; u < ZP + 2; ++u) c[u] = col[u];
+          for (int u = 0; u < ZP + 2; ++u) c[u] = col[u];
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-          const float* wt = wl + ((i * 27) + dx * 9 + dy * 3 + dz) * COP;
-          float wv[COP];
+          for (int dz = 0; dz < 3; ++dz) {
+            const float* wt = wl + ((i * 27) + dx * 9 + dy * 3 + dz) * COP;
+            float wv[COP];
 #pragma unroll
-          for (int q = 0; q < COP; q += 4) {
-            const float4 v4 = *reinterpret_cast<const float4*>(wt + q);
-            wv[q] = v4.x;
-            wv[q + 1] = v4.y;
-            wv[q + 2] = v4.z;
-            wv[q + 3] = v4.w;
+            for (int q = 0; q < COP; q += 4) {
+              const float4 v4 = *reinterpret_cast<const float4*>(wt + q);
+              wv[q] = v4.x;
+              wv[q + 1] = v4.y;
+              wv[q + 2] = v4.z;
+              wv[q + 3] = v4.w;
+            }
+#pragma unroll
+            for (int o = 0; o < CO; ++o)
+#pragma unroll
+              for (int p = 0; p < ZP; ++p) acc[o][p] += wv[o] * c[p + dz];
           }
-#pragma unroll
-          for (int o = 0; o < CO; ++o)
-#pragma unroll
-            for (int p = 0; p < ZP; ++p) acc[o][p] += wv[o] * c[p + dz];
         }
-      }
+    }
   }
   const int gx = x0 + lx, gy = y0 + ly;
   if (gx >= n || gy >= n) return;
