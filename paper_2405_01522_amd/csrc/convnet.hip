@@ -168,24 +168,41 @@ __global__ __launch_bounds__(kT) void k_conv(const float* __restrict__ in, const
 
 // Weight and bias gradient partials of one tile: gw[o][i][t] = sum_p g[o](p) in[i](p + d_t),
 // gb[o] = sum_p g[o](p).  The input tile (with halo) and the tile of g (zero outside the box,
-// stored [point][o]) are staged in LDS; thread (i, t[, o-group]) runs over the tile's points
-// reading its input value and the (broadcast) g values of the point.
-template <int CI, int CO>
-__global__ __launch_bounds__(kT) void k_wgrad(const float* __restrict__ in, const float* __restrict__ g,
-                                              float* __restrict__ part, int n, int tny, int tnz) {
+// stored [point][o]) are staged in LDS.  kwg(CI) groups of kT threads split the tile's x-rows;
+// in each group thread (i, t[, o-group]) runs over its points reading its input value and the
+// (broadcast) g values of the point, and the group partials are added in group order (four
+// groups for 8 input channels: 347 against 498 us at 64^3 for 8 -> 8; one group for a single
+// input channel, whose threads already carry 8 outputs each).
+constexpr int kwg(int ci) { return ci == 1 ? 1 : 4; }
+template <int CI, int CO, int KWG = kwg(CI)>
+__global__ __launch_bounds__(kT * KWG) void k_wgrad(const float* __restrict__ in, const float* __restrict__ g,
+                                                    float* __restrict__ part, int n, int tny, int tnz) {
   __shared__ float tile[CI * HVOL];
   __shared__ __align__(16) float gt[TX * TY * TZ * CO];
   constexpr int OG = (CI == 1) ? CO : 1, OPT = CO / OG, NACT = CI * 27 * OG;
   constexpr int NPL = CO * CI * 27 + CO;
   constexpr int TP = TX * TY * TZ;
   static_assert(NACT + CO <= kT, "threads");
+  static_assert(TX % KWG == 0, "x-rows split evenly");
+  __shared__ float red[KWG > 1 ? KWG - 1 : 1][kT * OPT];
   const size_t ng = (size_t)n * n * n;
   int x0, y0, z0;
   tile_origin(blockIdx.x, tny, tnz, &x0, &y0, &z0);
   const size_t sb = blockIdx.y;
-  stage_halo<CI>(tile, in + sb * CI * ng, n, ng, x0, y0, z0);
+  {
+    const float* inb = in + sb * CI * ng;
+    for (int e = threadIdx.x; e < CI * HVOL; e += kT * KWG) {
+      const int i = e / HVOL, q = e % HVOL;
+      const int hz = q % HZ, hy = (q / HZ) % HY, hx = q / (HZ * HY);
+      const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+      const bool ok = (unsigned)gx < (unsigned)n && (unsigned)gy < (unsigned)n && (unsigned)gz < (unsigned)n;
+      const size_t idx = ok ? (size_t)i * ng + ((size_t)gx * n + gy) * n + gz : 0;
+      const float v = inb[idx];
+      tile[e] = ok ? v : 0.f;
+    }
+  }
   const float* gb = g + sb * CO * ng;
-  for (int e = threadIdx.x; e < TP * CO; e += kT) {
+  for (int e = threadIdx.x; e < TP * CO; e += kT * KWG) {
     const int o = e / TP, pt = e % TP;  // consecutive threads: consecutive z (coalesced)
     const int pz = pt % TZ, py = (pt / TZ) % TY, px = pt / (TZ * TY);
     const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
@@ -195,16 +212,16 @@ __global__ __launch_bounds__(kT) void k_wgrad(const float* __restrict__ in, cons
     gt[pt * CO + o] = ok ? v : 0.f;
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  float* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NPL;
+  const int grp = threadIdx.x / kT, t = threadIdx.x % kT;
+  constexpr int XG = TX / KWG;  // x-rows per group
+  float acc[OPT];
+#pragma unroll
+  for (int q = 0; q < OPT; ++q) acc[q] = 0.f;
   if (t < NACT) {
     const int og = t % OG, id = t / OG;
     const int i = id / 27, tap = id % 27;
     const int dx = tap / 9, dy = (tap / 3) % 3, dz = tap % 3;
-    float acc[OPT];
-#pragma unroll
-    for (int q = 0; q < OPT; ++q) acc[q] = 0.f;
-    for (int px = 0; px < TX; ++px)
+    for (int px = grp * XG; px < (grp + 1) * XG; ++px)
       for (int py = 0; py < TY; ++py) {
         const float* trow = tile + i * HVOL + ((px + dx) * HY + (py + dy)) * HZ + dz;
         const float* grow = gt + ((px * TY + py) * TZ) * CO + og * OPT;
@@ -215,13 +232,28 @@ __global__ __launch_bounds__(kT) void k_wgrad(const float* __restrict__ in, cons
           for (int q = 0; q < OPT; ++q) acc[q] += grow[pz * CO + q] * v;
         }
       }
+  } else if (t < NACT + CO) {
+    const int o = t - NACT;
+    for (int pt = grp * XG * TY * TZ; pt < (grp + 1) * XG * TY * TZ; ++pt) acc[0] += gt[pt * CO + o];
+  }
+  if (grp > 0) {
+#pragma unroll
+    for (int q = 0; q < OPT; ++q) red[grp - 1][t * OPT + q] = acc[q];
+  }
+  __syncthreads();
+  if (grp > 0) return;
+#pragma unroll
+  for (int gq = 0; gq < KWG - 1; ++gq)
+#pragma unroll
+    for (int q = 0; q < OPT; ++q) acc[q] += red[gq][t * OPT + q];
+  float* pb = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NPL;
+  if (t < NACT) {
+    const int og = t % OG, id = t / OG;
+    const int i = id / 27, tap = id % 27;
 #pragma unroll
     for (int q = 0; q < OPT; ++q) pb[((og * OPT + q) * CI + i) * 27 + tap] = acc[q];
   } else if (t < NACT + CO) {
-    const int o = t - NACT;
-    float sum = 0.f;
-    for (int pt = 0; pt < TP; ++pt) sum += gt[pt * CO + o];
-    pb[CO * CI * 27 + o] = sum;
+    pb[CO * CI * 27 + (t - NACT)] = acc[0];
   }
 }
 
@@ -417,15 +449,15 @@ void backward(ace_convnet* net, int n, const float* x, const float* t, int nb) {
   k_transpose_flip<<<1, kT, 0, s>>>(net->weff + W1, C, C, net->wt1);
   k_transpose_flip<<<1, kT, 0, s>>>(net->weff + W2, 1, C, net->wt2);
   // layer 2 (8 -> 1)
-  k_wgrad<C, 1><<<grid, kT, 0, s>>>(a2, g, part, n, tl.ny, tl.nz);
+  k_wgrad<C, 1><<<grid, kT * kwg(C), 0, s>>>(a2, g, part, n, tl.ny, tl.nz);
   k_part_reduce<<<C * 27 + 1, kT, 0, s>>>(part, rows, C * 27 + 1, net->grad + W2);
   k_conv<1, C, false, false, true><<<grid, kT, 0, s>>>(g, net->wt2, nullptr, a2, g2, n, tl.ny, tl.nz);
   // layer 1 (8 -> 8)
-  k_wgrad<C, C><<<grid, kT, 0, s>>>(a1, g2, part, n, tl.ny, tl.nz);
+  k_wgrad<C, C><<<grid, kT * kwg(C), 0, s>>>(a1, g2, part, n, tl.ny, tl.nz);
   k_part_reduce<<<C * C * 27 + C, kT, 0, s>>>(part, rows, C * C * 27 + C, net->grad + W1);
   k_conv<C, C, false, false, true><<<grid, kT, 0, s>>>(g2, net->wt1, nullptr, a1, g1, n, tl.ny, tl.nz);
   // layer 0 (1 -> 8)
-  k_wgrad<1, C><<<grid, kT, 0, s>>>(x, g1, part, n, tl.ny, tl.nz);
+  k_wgrad<1, C><<<grid, kT * kwg(1), 0, s>>>(x, g1, part, n, tl.ny, tl.nz);
   k_part_reduce<<<C * 27 + C, kT, 0, s>>>(part, rows, C * 27 + C, net->grad + W0);
 }
 
