@@ -712,8 +712,47 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, doubl
   }
 }
 
+// The same sums for many outputs (large Gram matrices): a workgroup takes 16 consecutive
+// outputs, so each partial row is read as one contiguous 16-entry run instead of one entry per
+// cache line; thread (block group bg, output ol) adds blocks bg, bg + 16, ... in order and the
+// 16 group sums are added in order.
+template <typename W, typename S>
+__global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, double scale) {
+  constexpr int NO = 16, NG = kThreads / NO;
+  __shared__ W red[NG][NO];
+  const RedArgs ra = src.get(blockIdx.y);
+  const int ol = threadIdx.x % NO, bg = threadIdx.x / NO;
+  const int o = blockIdx.x * NO + ol;
+  const W* __restrict__ part = (const W*)ra.part;
+  W acc = W{};
+  if (o < ra.no) {
+    // loads batched eight at a time; the additions keep their order
+    int b = bg;
+    for (; b + 7 * NG < nblk; b += 8 * NG) {
+      W v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u * NG) * ra.no + o];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = e_add(acc, v[u]);
+    }
+    for (; b < nblk; b += NG) acc = e_add(acc, part[(size_t)b * ra.no + o]);
+  }
+  red[bg][ol] = acc;
+  __syncthreads();
+  if (threadIdx.x < NO && o < ra.no) {
+    W t = red[0][ol];
+    for (int g2 = 1; g2 < NG; ++g2) t = e_add(t, red[g2][ol]);
+    ((W*)ra.out)[o] = e_scale(t, scale);
+  }
+}
+
 template <typename W, typename S>
 void reduce_launch(S sr, int nout, int nsys, int nblk, double scale, hipStream_t s) {
+  if (nout >= 1024) {
+    dim3 rg((nout + 15) / 16, nsys);
+    k_gram_reduce_cols<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale);
+    return;
+  }
   dim3 rg(nout, nsys);
   k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale);
 }
