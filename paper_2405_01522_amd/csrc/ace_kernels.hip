@@ -575,18 +575,38 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
 // FP64 MFMA contraction and the same partial layout part[block][o] as k_gram.
 constexpr int kWideRows = 64;
 
+// 16-row tile pair (row tile, column tile) of tile index `tile`: all ta x tb pairs, or for a
+// symmetric Gram (A = B) the pairs with row <= column only
+__device__ __forceinline__ void wide_tile_rc(int tile, int tb, bool sym, int* tr, int* tc) {
+  if (!sym) {
+    *tr = tile / tb;
+    *tc = tile % tb;
+    return;
+  }
+  for (int r = 0; r < tb; ++r) {  // row r holds tiles (r, r .. tb - 1)
+    if (tile < tb - r) {
+      *tr = r;
+      *tc = r + tile;
+      return;
+    }
+    tile -= tb - r;
+  }
+  *tr = *tc = tb - 1;  // not reached for tile < tb (tb + 1) / 2
+}
+
 // NT tiles of one wavefront over one staged pass (unconditional, fully unrolled chains)
 template <typename E, int NT, int SC>
-__device__ __forceinline__ void wide_tiles(const E* la, const E* lb, int wave, int tb, int li,
-                                           int g, gf64x4* acc) {
+__device__ __forceinline__ void wide_tiles(const E* la, const E* lb, int wave, int tb, bool sym,
+                                           int ntile, int li, int g, gf64x4* acc) {
   constexpr int LD = SC + 1;
   const E* pa[NT];
   const E* pb[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    const int tile = wave + 4 * u;
-    pa[u] = la + ((tile / tb) * 16 + li) * LD + g;
-    pb[u] = lb + ((tile % tb) * 16 + li) * LD + g;
+    int tr, tc;  // a wavefront without a tile of its own works on a valid one, writing nothing
+    wide_tile_rc(min(wave + 4 * u, ntile - 1), tb, sym, &tr, &tc);
+    pa[u] = la + (tr * 16 + li) * LD + g;
+    pb[u] = lb + (tc * 16 + li) * LD + g;
   }
   gf64x4 t[NT];
 #pragma unroll
@@ -602,7 +622,8 @@ __device__ __forceinline__ void wide_tiles(const E* la, const E* lb, int wave, i
 template <typename E, int NT>
 __device__ __forceinline__ void k_gram_wide_body(const E* __restrict__ A, int na,
                                                  const E* __restrict__ B, int nb, size_t ng,
-                                                 double* __restrict__ part, E* la, E* lb) {
+                                                 double* __restrict__ part, E* la, E* lb,
+                                                 bool sym, int ntile) {
   // points per pass: small enough (about 33 KiB of LDS) for several workgroups per CU
   constexpr int SC = sizeof(E) == 4 ? kGramPoints / 4 : kGramPoints / 8;
   constexpr int LD = SC + 1;
@@ -619,6 +640,7 @@ __device__ __forceinline__ void k_gram_wide_body(const E* __restrict__ A, int na
     constexpr int U = 8;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      if (side == 1 && sym) break;  // B = A: the staged A rows serve both sides (uniform)
       const E* X = side ? B : A;
       E* lx = side ? lb : la;
       const int nx = side ? nb : na, rx = side ? rb : ra;
@@ -641,17 +663,23 @@ __device__ __forceinline__ void k_gram_wide_body(const E* __restrict__ A, int na
       }
     }
     __syncthreads();
-    wide_tiles<E, NT, SC>(la, lb, wave, tb, li, g, acc);
+    wide_tiles<E, NT, SC>(la, sym ? la : lb, wave, tb, sym, ntile, li, g, acc);
     __syncthreads();
   }
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    const int tile = wave + 4 * u;
-    const int k0 = (tile / tb) * 16, l0 = (tile % tb) * 16;
+    if (wave + 4 * u >= ntile) break;  // uniform: no tile of this wavefront
+    int tr, tc;
+    wide_tile_rc(wave + 4 * u, tb, sym, &tr, &tc);
+    const int k0 = tr * 16, l0 = tc * 16;
+    double* pw = part + (size_t)blockIdx.x * na * nb;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int k = k0 + g + 4 * e, l = l0 + li;
-      if (k < na && l < nb) part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l] = acc[u][e];
+      if (k < na && l < nb) {
+        pw[(size_t)k * nb + l] = acc[u][e];
+        if (sym && tr != tc) pw[(size_t)l * nb + k] = acc[u][e];  // the mirrored tile
+      }
     }
   }
 }
@@ -664,14 +692,18 @@ __global__ __launch_bounds__(kThreads) void k_gram_wide(const E* __restrict__ A,
   __shared__ E la[kWideRows * (SC + 1)];
   __shared__ E lb[kWideRows * (SC + 1)];
   const int wave = threadIdx.x >> 6;
-  const int ntile = ((na + 15) / 16) * ((nb + 15) / 16);
-  const int nt = (ntile - wave + 3) / 4;  // tiles of this wavefront (uniform), 1..4
-  // every wavefront takes part in the staging barriers whatever its tile count
+  // a Gram of a block with itself is symmetric: its upper tiles are computed and mirrored
+  const bool sym = A == B && na == nb;
+  const int ta = (na + 15) / 16, tb = (nb + 15) / 16;
+  const int ntile = sym ? ta * (ta + 1) / 2 : ta * tb;
+  const int nt = (ntile - wave + 3) / 4;  // tiles of this wavefront (uniform), 0..4
+  // every wavefront takes part in the staging barriers whatever its tile count (none: the
+  // one-tile body, which writes nothing)
   switch (nt) {
-    case 4: k_gram_wide_body<E, 4>(A, na, B, nb, ng, part, la, lb); break;
-    case 3: k_gram_wide_body<E, 3>(A, na, B, nb, ng, part, la, lb); break;
-    case 2: k_gram_wide_body<E, 2>(A, na, B, nb, ng, part, la, lb); break;
-    default: k_gram_wide_body<E, 1>(A, na, B, nb, ng, part, la, lb); break;
+    case 4: k_gram_wide_body<E, 4>(A, na, B, nb, ng, part, la, lb, sym, ntile); break;
+    case 3: k_gram_wide_body<E, 3>(A, na, B, nb, ng, part, la, lb, sym, ntile); break;
+    case 2: k_gram_wide_body<E, 2>(A, na, B, nb, ng, part, la, lb, sym, ntile); break;
+    default: k_gram_wide_body<E, 1>(A, na, B, nb, ng, part, la, lb, sym, ntile); break;
   }
 }
 
