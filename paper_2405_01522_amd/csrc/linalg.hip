@@ -132,15 +132,28 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
     }
     __syncthreads();
     if (offn <= tol * tol * totn || offn == 0.0) break;
+    // tournament pairing: position 0 fixed, the others rotate by one each round.  Every thread
+    // keeps the indices at the positions of its work items in registers and advances them
+    // (no LDS reads, no divisions); at round 0 the index at position pos is pos.
+    constexpr int KI = (JMAX / 2 * JMAX / 2 + JMAX * JMAX / 2 + JT - 1) / JT;  // items per thread
+    const int nitem = h * h + m * h;
+    int ia[KI][4];  // A items: positions k, m-1-k, l, m-1-l; V items: l, m-1-l
+#pragma unroll
+    for (int u = 0; u < KI; ++u) {
+      const int e = threadIdx.x + u * JT;
+      const int k = e < h * h ? e / h : (e - h * h) / m;
+      const int l = e < h * h ? e % h : 0;
+      ia[u][0] = k;
+      ia[u][1] = m - 1 - k;
+      ia[u][2] = l;
+      ia[u][3] = m - 1 - l;
+    }
+    int ra = (int)threadIdx.x, rb = m - 1 - (int)threadIdx.x;  // rotation phase (thread < h)
+    auto adv = [&](int x) { return x == 0 ? 0 : (x == m - 1 ? 1 : x + 1); };
     for (int round = 0; round < m - 1; ++round) {
-      // tournament pairing: position 0 fixed, the others rotate
       if ((int)threadIdx.x < h) {
         const int k = threadIdx.x;
-        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (m - 1); };
-        int p = at(k), q = at(m - 1 - k);
-        if (p > q) { const int t = p; p = q; q = t; }
-        pp[k] = p;
-        qq[k] = q;
+        const int p = ra < rb ? ra : rb, q = ra < rb ? rb : ra;
         const double apq = a[p][q];
         double c = 1.0, sv = 0.0;
         if (fabs(apq) > 1e-290) {  // below that the rotation is the identity to rounding
@@ -161,30 +174,40 @@ __global__ __launch_bounds__(JT) void k_jacobi(int n, const double* __restrict__
         }
         cs[k] = c;
         sn[k] = sv;
+        ra = adv(ra);
+        rb = adv(rb);
       }
       __syncthreads();
       // A <- J^T A J by 2x2 blocks; V <- V J by column pairs
-      for (int e = threadIdx.x; e < h * h + m * h; e += JT) {
-        if (e < h * h) {
-          const int k = e / h, l = e % h;
-          const int p = pp[k], q = qq[k], r = pp[l], t = qq[l];
-          const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-          const double b00 = a[p][r], b01 = a[p][t], b10 = a[q][r], b11 = a[q][t];
-          const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
-          const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
-          a[p][r] = cl * r00 - sl * r01;
-          a[p][t] = sl * r00 + cl * r01;
-          a[q][r] = cl * r10 - sl * r11;
-          a[q][t] = sl * r10 + cl * r11;
-        } else {
-          const int f = e - h * h;
-          const int l = f / m, i = f % m;
-          const int p = pp[l], q = qq[l];
-          const double c = cs[l], sv = sn[l];
-          const double vx = v[i][p], vy = v[i][q];
-          v[i][p] = c * vx - sv * vy;
-          v[i][q] = sv * vx + c * vy;
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        const int e = threadIdx.x + u * JT;
+        if (e < nitem) {
+          const int a0 = ia[u][0], b0 = ia[u][1];
+          const int p = a0 < b0 ? a0 : b0, q = a0 < b0 ? b0 : a0;
+          if (e < h * h) {
+            const int k = e / h, l = e % h;
+            const int a1 = ia[u][2], b1 = ia[u][3];
+            const int r = a1 < b1 ? a1 : b1, t = a1 < b1 ? b1 : a1;
+            const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
+            const double b00 = a[p][r], b01 = a[p][t], b10 = a[q][r], b11 = a[q][t];
+            const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+            const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+            a[p][r] = cl * r00 - sl * r01;
+            a[p][t] = sl * r00 + cl * r01;
+            a[q][r] = cl * r10 - sl * r11;
+            a[q][t] = sl * r10 + cl * r11;
+          } else {
+            const int f = e - h * h;
+            const int l = f / m, i = f % m;
+            const double c = cs[l], sv = sn[l];
+            const double vx = v[i][p], vy = v[i][q];
+            v[i][p] = c * vx - sv * vy;
+            v[i][q] = sv * vx + c * vy;
+          }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ia[u][j] = adv(ia[u][j]);
       }
       __syncthreads();
     }
