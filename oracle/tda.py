@@ -28,6 +28,10 @@ grids, the 8-fold symmetry of real integrals, Hermiticity of C, singlet - triple
 form omega = sqrt(A^2 - B^2), B = 0 giving the Tamm-Dancoff eigenvalues, agreement with the
 Hermitian half-size form (A-B)^{1/2} (A+B) (A-B)^{1/2} for real orbitals, and the closed-shell
 UHF spectrum being the union of the RHF singlet and triplet spectra (TDA and full TDHF).
+Transition dipoles and oscillator strengths (Eqs. (8)-(9)): harmonic-oscillator eigenstates
+sampled on the grid, whose matrix elements <0|x|1> = 1/sqrt(2 w) and <1|x|2> = 1/sqrt(w) are
+closed forms, give f = 1/3 per axis from the ground state (summing to 1, the Thomas-Reiche-
+Kuhn rule for one electron), with two occupied orbitals so that the ia layout matters.
 """
 
 import scipy.linalg

@@ -161,3 +161,67 @@ def test_closed_shell_uhf_is_union_of_singlets_and_triplets(small):
     rhf_rpa = [tda.rpa_excitations(np.diag(de) + tda.coupling_block(occ, virt, h, dm),
                                    tda.b_block(occ, virt, h, dm)) for dm in (2, 0)]
     assert np.allclose(uhf_rpa, np.sort(np.concatenate(rhf_rpa)), atol=1e-9)
+
+
+def _oscillator_states(n, h, w):
+    """Eigenfunctions of the anisotropic harmonic oscillator V = 1/2 sum_c w_c c^2, sampled
+    on the grid: psi(n_x, n_y, n_z) = prod_c H_{n_c}-type factors times the ground Gaussian,
+    normalised analytically (no grid renormalisation).  Returned as a dict keyed by
+    (n_x, n_y, n_z) for quanta 0..2 per axis."""
+    x = grid.coords(n, h)
+    c = np.meshgrid(x, x, x, indexing="ij")
+    g = np.ones((n, n, n))
+    for k in range(3):
+        g = g * (w[k] / math.pi) ** 0.25 * np.exp(-0.5 * w[k] * c[k] ** 2)
+
+    def factor(k, q):
+        u = math.sqrt(w[k]) * c[k]
+        if q == 0:
+            return 1.0
+        if q == 1:
+            return math.sqrt(2.0) * u
+        return (2.0 * u * u - 1.0) / math.sqrt(2.0)
+
+    out = {}
+    for q in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 0, 2)]:
+        out[q] = g * factor(0, q[0]) * factor(1, q[1]) * factor(2, q[2])
+    return out, c
+
+
+def test_dipoles_and_oscillator_strengths_harmonic_closed_forms():
+    """Eqs. (8)-(9) on harmonic-oscillator states, where every matrix element is known:
+    <0|x|1_x> = 1/sqrt(2 w_x), <1_z|z|2_z> = 1/sqrt(w_z), and the ground-state strengths
+    f = 2/3 w |d|^2 are 1/3 per axis, summing to 1 (the Thomas-Reiche-Kuhn sum rule for one
+    electron).  Two occupied orbitals and four virtual ones make the ia = i * n_virt + a
+    index layout matter; the dipole operator uses the grid coordinates of the oracle."""
+    w = (0.8, 1.1, 1.4)
+    n, h = 56, 0.25   # box +-6.9 bohr: Gaussian tails below 1e-15
+    st, coords = _oscillator_states(n, h, w)
+    occ = np.stack([st[(0, 0, 0)], st[(0, 0, 1)]])
+    virt = np.stack([st[(1, 0, 0)], st[(0, 1, 0)], st[(0, 0, 2)], st[(2, 0, 0)]])
+    dip = tda.dipole_elements(occ, virt, h, coords)
+    nv = 4
+    expect = np.zeros((3, 2, nv))
+    expect[0, 0, 0] = 1.0 / math.sqrt(2.0 * w[0])     # <0|x|1x>
+    expect[1, 0, 1] = 1.0 / math.sqrt(2.0 * w[1])     # <0|y|1y>
+    expect[2, 1, 2] = 1.0 / math.sqrt(w[2])           # <1z|z|2z>
+    assert np.max(np.abs(dip - expect)) < 1e-12
+    # pure transitions (unit TDA vectors) and their energies
+    omega = np.array([w[0], w[1], w[2], 2.0 * w[0]])
+    x = np.zeros((2 * nv, 4))
+    for k, ia in enumerate([0 * nv + 0, 0 * nv + 1, 1 * nv + 2, 0 * nv + 3]):
+        x[ia, k] = 1.0
+    f = tda.oscillator_strengths(omega, x, dip)
+    assert np.allclose(f, [1.0 / 3.0, 1.0 / 3.0, 2.0 / 3.0, 0.0], atol=1e-12)
+    # the ground state alone against every excited state of the set: the strengths sum to 1
+    virt0 = np.stack([st[q] for q in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 0, 2)]])
+    dip0 = tda.dipole_elements(occ[:1], virt0, h, coords)
+    om0 = np.array([w[0], w[1], w[2], 2.0 * w[0], 2.0 * w[2]])
+    f0 = tda.oscillator_strengths(om0, np.eye(5), dip0)
+    assert np.sum(f0) == pytest.approx(1.0, abs=1e-12)
+    # a mixed state: d = (d_x, d_y, 0) / sqrt(2), f = 2/3 w (1/(2 w_x) + 1/(2 w_y)) / 2
+    xm = np.zeros((2 * nv, 1))
+    xm[0 * nv + 0, 0] = xm[0 * nv + 1, 0] = 1.0 / math.sqrt(2.0)
+    fm = tda.oscillator_strengths(np.array([0.9]), xm, dip)
+    ref = 2.0 / 3.0 * 0.9 * 0.5 * (1.0 / (2.0 * w[0]) + 1.0 / (2.0 * w[1]))
+    assert fm[0] == pytest.approx(ref, rel=1e-12)
