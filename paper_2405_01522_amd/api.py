@@ -41,6 +41,22 @@ def _stream_handle():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def check_out(t, name, shape, dtype, device):
+    """Validate a caller-supplied result tensor before its pointer goes to the library (the C
+    side cannot see its size or type): exact dtype and shape, contiguous, on the given GPU."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def size_supported(n, dtype):
     return bool(lib().ace_size_supported(int(n), dtype_code(dtype)))
 
@@ -126,11 +142,13 @@ class AceContext:
                                 device=self.device)
         if ex_out is None:
             ex_out = torch.empty((), dtype=torch.float64, device=self.device)
+        mp = check_out(m_out, "m_out", (n, n), torch.complex128 if cplx else torch.float64,
+                       self.device)
+        ep = check_out(ex_out, "ex_out", (), torch.float64, self.device)
         p = self._vol(phi, "phi")
         x = self._vol(xi_out, "xi_out", n)
         self._sync_stream()
-        check(lib().ace_build(self._h, p, n, x, ctypes.c_void_p(m_out.data_ptr()),
-                              ctypes.c_void_p(ex_out.data_ptr())), "ace_build")
+        check(lib().ace_build(self._h, p, n, x, mp, ep), "ace_build")
         return xi_out, m_out, ex_out
 
     def ace_apply(self, xi, psi, out=None):
@@ -158,11 +176,11 @@ class AceContext:
         no, nv = phi_occ.shape[0], phi_virt.shape[0]
         if out is None:
             out = torch.empty((no * nv, no * nv), dtype=torch.float64, device=self.device)
+        op = check_out(out, "out", (no * nv, no * nv), torch.float64, self.device)
         po = self._vol(phi_occ, "phi_occ")
         pv = self._vol(phi_virt, "phi_virt")
         self._sync_stream()
-        check(lib().tda_coupling(self._h, po, no, pv, nv, int(delta_m),
-                                 ctypes.c_void_p(out.data_ptr())), "tda_coupling")
+        check(lib().tda_coupling(self._h, po, no, pv, nv, int(delta_m), op), "tda_coupling")
         return out
 
     def tda_excitations(self, c, eps_occ, eps_virt, nstates, tol=1e-8, max_iter=200):
@@ -195,11 +213,12 @@ class AceContext:
             c_out = torch.empty((n, n), dtype=torch.float64, device=self.device)
         if b_out is None:
             b_out = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        cp = check_out(c_out, "c_out", (n, n), torch.float64, self.device)
+        bp = check_out(b_out, "b_out", (n, n), torch.float64, self.device)
+        po = self._vol(phi_occ, "phi_occ")
+        pv = self._vol(phi_virt, "phi_virt")
         self._sync_stream()
-        check(lib().tdhf_coupling(self._h, self._vol(phi_occ, "phi_occ"), no,
-                                  self._vol(phi_virt, "phi_virt"), nv, int(delta_m),
-                                  ctypes.c_void_p(c_out.data_ptr()),
-                                  ctypes.c_void_p(b_out.data_ptr())), "tdhf_coupling")
+        check(lib().tdhf_coupling(self._h, po, no, pv, nv, int(delta_m), cp, bp), "tdhf_coupling")
         return c_out, b_out
 
     def uhf_coupling(self, occ_a, virt_a, occ_b, virt_b, with_b=True):
@@ -222,6 +241,7 @@ class AceContext:
         import numpy as np
         dd = np.ascontiguousarray(d, dtype=np.float64)
         n = dd.size
+        check_out(c, "c", (n, n), torch.float64, self.device)
         omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
         x = torch.empty((nstates, n), dtype=torch.float64, device=self.device)
         it = ctypes.c_int()
@@ -238,6 +258,8 @@ class AceContext:
         import numpy as np
         dd = np.ascontiguousarray(d, dtype=np.float64)
         n = dd.size
+        check_out(c, "c", (n, n), torch.float64, self.device)
+        check_out(b, "b", (n, n), torch.float64, self.device)
         omega = torch.empty(nstates, dtype=torch.float64, device=self.device)
         xpy = torch.empty((nstates, n), dtype=torch.float64, device=self.device)
         it = ctypes.c_int()
@@ -253,6 +275,8 @@ class AceContext:
     def tda_oscillator_strengths(self, phi_occ, phi_virt, x, omega):
         """(f, d): oscillator strengths (k,) and transition dipoles (k, 3) of TDA states."""
         k = omega.shape[0]
+        check_out(omega, "omega", (k,), torch.float64, self.device)
+        check_out(x, "x", (k, phi_occ.shape[0] * phi_virt.shape[0]), torch.float64, self.device)
         f = torch.empty(k, dtype=torch.float64, device=self.device)
         d = torch.empty((k, 3), dtype=torch.float64, device=self.device)
         po = self._vol(phi_occ, "phi_occ")
@@ -333,10 +357,14 @@ class AceContext:
         if m_out is None:
             m_out = torch.empty((nt, nt), dtype=torch.complex128 if self.dtype.is_complex
                                 else torch.float64, device=self.device)
+        mp = check_out(m_out, "m_out", (nt, nt),
+                       torch.complex128 if self.dtype.is_complex else torch.float64, self.device)
+        po = self._vol(phi_occ, "phi_occ")
+        ps = self._vol(psi, "psi")
+        xo = self._vol(xi_out, "xi_out", nt)
         self._sync_stream()
-        check(lib().ace_build_targets(self._h, self._vol(phi_occ, "phi_occ"), phi_occ.shape[0],
-                                      self._vol(psi, "psi"), nt, self._vol(xi_out, "xi_out", nt),
-                                      ctypes.c_void_p(m_out.data_ptr())), "ace_build_targets")
+        check(lib().ace_build_targets(self._h, po, phi_occ.shape[0], ps, nt, xo, mp),
+              "ace_build_targets")
         return xi_out, m_out
 
     def unocc_states(self, v_local, phi_occ, psi, opts=None, max_outer=50, nconv=0):
@@ -485,8 +513,10 @@ class AceBatch:
             if sysd.get("ex") is None:
                 sysd["ex"] = torch.empty((), dtype=torch.float64, device=phi.device)
             xi = sysd["xi"]
-            if xi.shape != phi.shape or xi.dtype != phi.dtype or not xi.is_contiguous():
-                raise ValueError("system %d: xi must match phi" % k)
+            check_out(xi, "system %d: xi" % k, tuple(phi.shape), phi.dtype, self.device)
+            check_out(sysd["M"], "system %d: M" % k, (norb, norb),
+                      torch.complex128 if self.dtype.is_complex else torch.float64, self.device)
+            check_out(sysd["ex"], "system %d: ex" % k, (), torch.float64, self.device)
             arr[k] = AceMol(n, float(sysd["h"]), norb, phi.data_ptr(), xi.data_ptr(),
                             sysd["M"].data_ptr(), sysd["ex"].data_ptr())
         self._sync_stream()
@@ -618,8 +648,14 @@ def dense_gemm(a, b, ta=False, tb=False, alpha=1.0, beta=0.0, out=None):
     m = a.shape[1] if ta else a.shape[0]
     k = a.shape[0] if ta else a.shape[1]
     n = b.shape[0] if tb else b.shape[1]
+    kb = b.shape[1] if tb else b.shape[0]
+    if kb != k:
+        raise ValueError("inner dimensions differ: %d and %d" % (k, kb))
+    for t, nm in ((a, "a"), (b, "b")):
+        check_out(t, nm, tuple(t.shape), torch.float64, a.device)
     if out is None:
         out = torch.zeros((m, n), dtype=torch.float64, device=a.device)
+    check_out(out, "out", (m, n), torch.float64, a.device)
     check(lib().dense_gemm(int(ta), int(tb), m, n, k, float(alpha), ctypes.c_void_p(a.data_ptr()),
                            a.shape[1], ctypes.c_void_p(b.data_ptr()), b.shape[1], float(beta),
                            ctypes.c_void_p(out.data_ptr()), n, _stream_handle()), "dense_gemm")

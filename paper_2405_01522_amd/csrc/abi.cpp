@@ -94,20 +94,21 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
       cosw[(size_t)k * ho + a] = w * cossin_2pi((long long)k * a, p).c;
     }
   const bool fp64 = is_fp64(dtype);
-  std::vector<double> tw64(2 * (size_t)p);
-  std::vector<float> tw32(2 * (size_t)p);
+  // table twiddles exp(-2 pi i m / P): FP64, or FP32 hi + lo parts (see TwE in common.hpp)
+  std::vector<TwE<double>> tw64((size_t)p);
+  std::vector<TwE<float>> tw32((size_t)p);
   for (int m = 0; m < p; ++m) {
     CosSin cs = cossin_2pi(m, p);
-    tw64[2 * m] = cs.c;
-    tw64[2 * m + 1] = -cs.s;
-    tw32[2 * m] = (float)cs.c;
-    tw32[2 * m + 1] = (float)-cs.s;
+    tw64[m] = {cs.c, -cs.s};
+    const SplitF kc = split_f(cs.c), ks = split_f(-cs.s);
+    tw32[m] = {kc.hi, ks.hi, kc.lo, ks.lo};
   }
+  static_assert(sizeof(TwE<double>) == 16 && sizeof(TwE<float>) == 16, "16-byte twiddles");
   double *d_cos = nullptr, *t0 = nullptr, *t1 = nullptr;
   int rc = ACE_OK;
   if (hipMalloc(&c->ghat64, oct * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->ghat32, oct * sizeof(float)) != hipSuccess ||
-      hipMalloc(&c->tw, (fp64 ? 16 : 8) * (size_t)p) != hipSuccess ||
+      hipMalloc(&c->tw, 16 * (size_t)p) != hipSuccess ||
       hipMalloc(&c->gpos, (fp64 ? 8 : 4) * (size_t)p * p * p) != hipSuccess ||
       hipMalloc(&c->status, 4 * sizeof(int)) != hipSuccess ||
       hipMalloc(&d_cos, cosw.size() * sizeof(double)) != hipSuccess ||
@@ -119,7 +120,7 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
   if (!rc) {
     if (hipMemcpy(d_cos, cosw.data(), cosw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->tw, fp64 ? (const void*)tw64.data() : (const void*)tw32.data(),
-                  (fp64 ? 16 : 8) * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
+                  16 * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemsetAsync(c->status, 0, 4 * sizeof(int), c->stream) != hipSuccess)
       rc = ACE_ERR_HIP;
   }

@@ -723,12 +723,19 @@ __device__ __forceinline__ C2<double> shfl_xor_w<C2<double>>(C2<double> v, int m
   return {__shfl_xor(v.r, m, 64), __shfl_xor(v.i, m, 64)};
 }
 
+// Gram matrices of at least this many entries are reduced by k_gram_reduce_cols, smaller ones
+// by k_gram_reduce; the choice is made per system so that a system's sums are the same
+// whether it is reduced alone or in a batch (only_cols: -1 any, 0 small ones only, 1 large
+// ones only).
+constexpr int kColsMin = 1024;
+
 template <typename W, typename S>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale) {
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale,
+                                                          int only_cols) {
   __shared__ W red[kThreads / 64];
   const RedArgs ra = src.get(blockIdx.y);
   const int o = blockIdx.x;
-  if (o >= ra.no) return;
+  if (o >= ra.no || (only_cols == 0 && ra.no >= kColsMin)) return;
   const W* __restrict__ part = (const W*)ra.part;
   W s = W{};
   for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)b * ra.no + o]);
@@ -749,10 +756,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, doubl
 // cache line; thread (block group bg, output ol) adds blocks bg, bg + 16, ... in order and the
 // 16 group sums are added in order.
 template <typename W, typename S>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, double scale) {
+__global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, double scale,
+                                                               int only_cols) {
   constexpr int NO = 16, NG = kThreads / NO;
   __shared__ W red[NG][NO];
   const RedArgs ra = src.get(blockIdx.y);
+  if (only_cols == 1 && ra.no < kColsMin) return;
   const int ol = threadIdx.x % NO, bg = threadIdx.x / NO;
   const int o = blockIdx.x * NO + ol;
   const W* __restrict__ part = (const W*)ra.part;
@@ -778,15 +787,22 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, 
   }
 }
 
+// nout: the largest output count over the nsys systems.  One system takes the kernel its
+// size selects; a batch whose largest system is large runs both kernels, each skipping the
+// systems of the other size class.
 template <typename W, typename S>
 void reduce_launch(S sr, int nout, int nsys, int nblk, double scale, hipStream_t s) {
-  if (nout >= 1024) {
-    dim3 rg((nout + 15) / 16, nsys);
-    k_gram_reduce_cols<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale);
+  if (nout < kColsMin) {
+    dim3 rg(nout, nsys);
+    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, -1);
     return;
   }
-  dim3 rg(nout, nsys);
-  k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale);
+  if (nsys > 1) {
+    dim3 rg(kColsMin - 1, nsys);
+    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, 0);
+  }
+  dim3 rg((nout + 15) / 16, nsys);
+  k_gram_reduce_cols<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, nsys > 1 ? 1 : -1);
 }
 
 // Cholesky of -M (Hermitised), L^{-H} and E_x in one wavefront, FP64.  Lane i holds row i of

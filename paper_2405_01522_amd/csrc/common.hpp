@@ -101,20 +101,118 @@ struct TwTable {
 template <int N>
 inline constexpr TwTable<N> kTw{};
 
+// ---------------------------------------------------------------------------------------
+// Constants of the single-precision transforms.
+//
+// Rounding a DFT constant (a twiddle cos / sin) to FP32 changes the transform itself, not just
+// one result: the forward transform and its conjugate inverse then miss each other by a fixed
+// O(2^-24) matrix, and a pair energy <rho|G (*) rho> picks up a first-order bias that does not
+// average out over the grid (about 1e-7 relative in the exchange energy, measured by emulating
+// the passes in NumPy).  The rounding of the data in the arithmetic itself is unbiased and
+// costs about 100 times less.  So every constant of the FP32 transforms is carried as an
+// unevaluated sum hi + lo of two floats (hi = RNE(c), lo = RNE(c - hi)), and x * c is formed as
+// fma(x, hi, x * lo): one rounding of the product with the constant correct to about 2^-48.
+// ACE_FFT_SPLIT_CONSTANTS = 0 keeps the plain rounded constants (for measurement only).
+#ifndef ACE_FFT_SPLIT_CONSTANTS
+#define ACE_FFT_SPLIT_CONSTANTS 1
+#endif
+constexpr bool kSplitConstants = ACE_FFT_SPLIT_CONSTANTS != 0;
+
+struct SplitF {
+  float hi, lo;
+};
+__host__ __device__ constexpr SplitF split_f(double c) {
+  return {float(c), kSplitConstants ? float(c - double(float(c))) : 0.0f};
+}
+
+// x * c for a compile-time constant c (T = double: the double product)
+template <typename T>
+__host__ __device__ __forceinline__ T mul_k(T x, double c) {
+  if constexpr (sizeof(T) == 4) {
+    const SplitF k = split_f(c);
+    return k.lo == 0.0f ? x * k.hi : fmaf(x, k.hi, x * k.lo);
+  } else {
+    return x * T(c);
+  }
+}
+// acc + x * c for a compile-time constant c
+template <typename T>
+__host__ __device__ __forceinline__ T fma_k(T x, double c, T acc) {
+  if constexpr (sizeof(T) == 4) {
+    const SplitF k = split_f(c);
+    return k.lo == 0.0f ? fmaf(x, k.hi, acc) : fmaf(x, k.hi, fmaf(x, k.lo, acc));
+  } else {
+    return acc + x * T(c);
+  }
+}
+
 // a * (c + i s) for compile-time constants c, s (branches fold after unrolling).
 template <typename T>
 __host__ __device__ __forceinline__ C2<T> cmul_k(C2<T> a, double c, double s) {
   if (s == 0.0) {
     if (c == 1.0) return a;
     if (c == -1.0) return {-a.r, -a.i};
-    return {a.r * T(c), a.i * T(c)};
+    return {mul_k(a.r, c), mul_k(a.i, c)};
   }
   if (c == 0.0) {
     if (s == 1.0) return {-a.i, a.r};
     if (s == -1.0) return {a.i, -a.r};
-    return {-a.i * T(s), a.r * T(s)};
+    return {-mul_k(a.i, s), mul_k(a.r, s)};
+  }
+  if constexpr (sizeof(T) == 4) {
+    const SplitF kc = split_f(c), ks = split_f(s);
+    if (c == s || c == -s) {
+      // (1 +- i) c: one sum and one difference, then two constant products
+      const float u = a.r - (c == s ? a.i : -a.i), w = a.i + (c == s ? a.r : -a.r);
+      return {mul_k(u, c), mul_k(w, c)};
+    }
+    if (kc.lo != 0.0f && ks.lo != 0.0f) {
+      // correction terms first (products with the small parts), then the main products
+      const float cr = fmaf(a.r, kc.lo, -a.i * ks.lo);
+      const float ci = fmaf(a.r, ks.lo, a.i * kc.lo);
+      return {fmaf(a.r, kc.hi, fmaf(-a.i, ks.hi, cr)), fmaf(a.r, ks.hi, fmaf(a.i, kc.hi, ci))};
+    }
+    if (kc.lo != 0.0f) {
+      return {fmaf(a.r, kc.hi, fmaf(-a.i, ks.hi, a.r * kc.lo)),
+              fmaf(a.r, ks.hi, fmaf(a.i, kc.hi, a.i * kc.lo))};
+    }
+    if (ks.lo != 0.0f) {
+      return {fmaf(a.r, kc.hi, fmaf(-a.i, ks.hi, -a.i * ks.lo)),
+              fmaf(a.r, ks.hi, fmaf(a.i, kc.hi, a.r * ks.lo))};
+    }
   }
   return {a.r * T(c) - a.i * T(s), a.r * T(s) + a.i * T(c)};
+}
+
+// Twiddle table entry exp(-2 pi i m / P) of the two-factor transforms: FP64 as is, FP32 as
+// hi + lo parts of cos and sin (16 bytes either way).
+template <typename T>
+struct TwE;
+template <>
+struct alignas(16) TwE<double> {
+  double c, s;
+};
+template <>
+struct alignas(16) TwE<float> {
+  float c, s, cl, sl;
+};
+
+// a * w and a * conj(w) for a table twiddle w
+__host__ __device__ __forceinline__ C2<double> tw_mul(C2<double> a, TwE<double> w) {
+  return {a.r * w.c - a.i * w.s, a.r * w.s + a.i * w.c};
+}
+__host__ __device__ __forceinline__ C2<double> tw_mul_conj(C2<double> a, TwE<double> w) {
+  return {a.r * w.c + a.i * w.s, a.i * w.c - a.r * w.s};
+}
+__host__ __device__ __forceinline__ C2<float> tw_mul(C2<float> a, TwE<float> w) {
+  const float cr = fmaf(a.r, w.cl, -a.i * w.sl);
+  const float ci = fmaf(a.r, w.sl, a.i * w.cl);
+  return {fmaf(a.r, w.c, fmaf(-a.i, w.s, cr)), fmaf(a.r, w.s, fmaf(a.i, w.c, ci))};
+}
+__host__ __device__ __forceinline__ C2<float> tw_mul_conj(C2<float> a, TwE<float> w) {
+  const float cr = fmaf(a.r, w.cl, a.i * w.sl);
+  const float ci = fmaf(a.i, w.cl, -a.r * w.sl);
+  return {fmaf(a.r, w.c, fmaf(a.i, w.s, cr)), fmaf(a.i, w.c, fmaf(-a.r, w.s, ci))};
 }
 
 // W_N^{m} with sign DIR: exp(DIR * 2 pi i m / N); DIR = -1 forward, +1 inverse.
@@ -164,16 +262,21 @@ __host__ __device__ __forceinline__ void butterfly(C2<T>* x) {
     out[0] = tot;
 #pragma unroll
     for (int k = 1; k <= Hh; ++k) {
-      C2<T> re = x0, im = {T(0), T(0)};
+      C2<T> re = x0, im;
 #pragma unroll
       for (int m = 1; m <= Hh; ++m) {
         const int mk = (m * k) % R;
-        const T c = T(kTw<R>.c[mk]);
-        const T s = T(kTw<R>.s[mk]);
-        re.r += sp[m - 1].r * c;
-        re.i += sp[m - 1].i * c;
-        im.r += sm[m - 1].r * s;
-        im.i += sm[m - 1].i * s;
+        const double c = kTw<R>.c[mk];
+        const double s = kTw<R>.s[mk];
+        re.r = fma_k(sp[m - 1].r, c, re.r);
+        re.i = fma_k(sp[m - 1].i, c, re.i);
+        if (m == 1) {
+          im.r = mul_k(sm[0].r, s);
+          im.i = mul_k(sm[0].i, s);
+        } else {
+          im.r = fma_k(sm[m - 1].r, s, im.r);
+          im.i = fma_k(sm[m - 1].i, s, im.i);
+        }
       }
       // DIR * i * im
       C2<T> jim = (DIR < 0) ? C2<T>{im.i, -im.r} : C2<T>{-im.i, im.r};

@@ -52,11 +52,22 @@ __device__ __forceinline__ C2<T>* lds() {
   return reinterpret_cast<C2<T>*>(ace_smem);
 }
 
-// Copy the P twiddles exp(-2 pi i m / P) into LDS (after `off` elements of the LDS array).
+// LDS bytes of `elems` complex values followed by the P table twiddles (16-byte aligned).
+template <typename T>
+constexpr size_t tw_offset(size_t elems) {
+  return (elems * sizeof(C2<T>) + 15) / 16 * 16;
+}
 template <typename T, int P>
-__device__ __forceinline__ const C2<T>* stage_twiddles(C2<T>* base, int off,
-                                                       const C2<T>* __restrict__ tw) {
-  C2<T>* s = base + off;
+constexpr size_t lds_with_twiddles(size_t elems) {
+  return tw_offset<T>(elems) + (size_t)P * sizeof(TwE<T>);
+}
+
+// Copy the P twiddles exp(-2 pi i m / P) into LDS after `elems` complex values.
+template <typename T, int P>
+__device__ __forceinline__ const TwE<T>* stage_twiddles(C2<T>* base, size_t elems,
+                                                        const TwE<T>* __restrict__ tw) {
+  TwE<T>* s = reinterpret_cast<TwE<T>*>(reinterpret_cast<unsigned char*>(base) +
+                                        tw_offset<T>(elems));
   for (int m = threadIdx.x; m < P; m += blockDim.x) s[m] = tw[m];
   return s;
 }
@@ -142,12 +153,12 @@ struct PairsByPointer {
 // Z-forward pass
 template <typename T, int N, bool RP, typename R>
 __global__ __launch_bounds__(zf_threads<N>()) void k_zfwd(R res, C2<T>* __restrict__ work,
-                                                   const C2<T>* __restrict__ twg) {
+                                                   const TwE<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   constexpr size_t NG = (size_t)N * N * N;
   C2<T>* buf = lds<T>();
-  const C2<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
+  const TwE<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
   __syncthreads();
   const int x = blockIdx.x;
   const int p = blockIdx.y;
@@ -193,7 +204,7 @@ __global__ __launch_bounds__(zf_threads<N>()) void k_zfwd(R res, C2<T>* __restri
     dft_in_half<T, P1, -1>(v);
     buf[y * RS + n2] = v[0];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) buf[y * RS + k1 * P2 + n2] = cmul(v[k1], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) buf[y * RS + k1 * P2 + n2] = tw_mul(v[k1], tw[n2 * k1]);
   }
   __syncthreads();
   C2<T>* dst0 = work + (size_t)p * P * N * N + (size_t)x * N;
@@ -213,11 +224,11 @@ __global__ __launch_bounds__(zf_threads<N>()) void k_zfwd(R res, C2<T>* __restri
 template <typename T, int N>
 __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
                                                  const T* __restrict__ gpos,
-                                                 const C2<T>* __restrict__ twg) {
+                                                 const TwE<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   C2<T>* pl = lds<T>();
-  const C2<T>* tw = stage_twiddles<T, P>(pl, P * RS, twg);
+  const TwE<T>* tw = stage_twiddles<T, P>(pl, P * RS, twg);
   __syncthreads();
   const int qz = blockIdx.x, p = blockIdx.y;
   C2<T>* g = work + ((size_t)p * P + qz) * N * N;
@@ -232,7 +243,7 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
     dft_in_half<T, P1, -1>(v);
     pl[x * RS + n2] = v[0];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) pl[x * RS + k1 * P2 + n2] = cmul(v[k1], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) pl[x * RS + k1 * P2 + n2] = tw_mul(v[k1], tw[n2 * k1]);
   }
   __syncthreads();
   // 2. y forward, second factor
@@ -256,7 +267,7 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
     dft_in_half<T, P1, -1>(v);
     pl[n2 * RS + qy] = v[0];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) pl[(k1 * P2 + n2) * RS + qy] = cmul(v[k1], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) pl[(k1 * P2 + n2) * RS + qy] = tw_mul(v[k1], tw[n2 * k1]);
   }
   __syncthreads();
   // 4. x forward second factor, kernel multiply, x inverse first factor (in registers)
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
     C2<T> v[P1];
     v[0] = pl[n2 * RS + qy];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(pl[(k1 * P2 + n2) * RS + qy], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = tw_mul_conj(pl[(k1 * P2 + n2) * RS + qy], tw[n2 * k1]);
     dft_out_half<T, P1, 1>(v);
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) pl[(n1 * P2 + n2) * RS + qy] = v[n1];
@@ -303,7 +314,7 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
     C2<T> v[P1];
     v[0] = pl[x * RS + n2];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(pl[x * RS + k1 * P2 + n2], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = tw_mul_conj(pl[x * RS + k1 * P2 + n2], tw[n2 * k1]);
     dft_out_half<T, P1, 1>(v);
 #pragma unroll
     for (int n1 = 0; n1 < H1; ++n1) g[x * N + n1 * P2 + n2] = v[n1];
@@ -314,12 +325,12 @@ __global__ __launch_bounds__(kXyThreads) void k_xy(C2<T>* __restrict__ work,
 // Z-inverse pass
 template <typename T, int N, bool RP, typename R>
 __global__ __launch_bounds__(zi_threads<N>()) void k_zinv(const C2<T>* __restrict__ work, R res,
-                                                   const C2<T>* __restrict__ twg) {
+                                                   const TwE<T>* __restrict__ twg) {
   typedef Plan<N> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1;
   constexpr size_t NG = (size_t)N * N * N;
   C2<T>* buf = lds<T>();
-  const C2<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
+  const TwE<T>* tw = stage_twiddles<T, P>(buf, N * RS, twg);
   const int x = blockIdx.x, p = blockIdx.y;
   const C2<T>* src0 = work + (size_t)p * P * N * N + (size_t)x * N;
   for (int it = threadIdx.x; it < N * P1; it += zi_threads<N>()) {
@@ -337,7 +348,7 @@ __global__ __launch_bounds__(zi_threads<N>()) void k_zinv(const C2<T>* __restric
     C2<T> v[P1];
     v[0] = buf[y * RS + n2];
 #pragma unroll
-    for (int k1 = 1; k1 < P1; ++k1) v[k1] = cmul_conjb(buf[y * RS + k1 * P2 + n2], tw[n2 * k1]);
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = tw_mul_conj(buf[y * RS + k1 * P2 + n2], tw[n2 * k1]);
     dft_out_half<T, P1, 1>(v);
     const size_t base = ((size_t)x * N + y) * N + n2;
     if constexpr (RP) {
@@ -437,10 +448,10 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
   const int np = res.np;
   const int items = rp ? (np + 1) / 2 : np;
   if (items <= 0) return;
-  const size_t lds_z = ((size_t)N * (P + 1) + P) * sizeof(C2<T>);
-  const size_t lds_xy = ((size_t)P * (P + 1) + P) * sizeof(C2<T>);
+  const size_t lds_z = lds_with_twiddles<T, P>((size_t)N * (P + 1));
+  const size_t lds_xy = lds_with_twiddles<T, P>((size_t)P * (P + 1));
   C2<T>* w = reinterpret_cast<C2<T>*>(work);
-  const C2<T>* t = reinterpret_cast<const C2<T>*>(tw);
+  const TwE<T>* t = reinterpret_cast<const TwE<T>*>(tw);
   const T* gh = reinterpret_cast<const T*>(ghat);
   if (rp) {
     allow_lds(k_zfwd<T, N, true, R>, lds_z);
@@ -475,7 +486,7 @@ constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename T, int N>
 constexpr bool fits() {
-  return ((size_t)(2 * N) * (2 * N + 1) + 2 * N) * sizeof(C2<T>) <= kMaxLds;
+  return lds_with_twiddles<T, 2 * N>((size_t)(2 * N) * (2 * N + 1)) <= kMaxLds;
 }
 
 #define ACE_SIZES(X) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(24) X(32) X(40) X(48) X(56) X(64)

@@ -87,6 +87,22 @@ static void test_dft(std::mt19937_64& rng, double tol) {
   }
 }
 
+// Table twiddles exp(-2 pi i m / P) as the library builds them (FP32: hi + lo parts).
+template <typename T, int P>
+static std::vector<TwE<T>> twiddle_table() {
+  std::vector<TwE<T>> tw(P);
+  for (int m = 0; m < P; ++m) {
+    CosSin cs = cossin_2pi(m, P);
+    if constexpr (sizeof(T) == 8) {
+      tw[m] = {cs.c, -cs.s};
+    } else {
+      const SplitF kc = split_f(cs.c), ks = split_f(-cs.s);
+      tw[m] = {kc.hi, ks.hi, kc.lo, ks.lo};
+    }
+  }
+  return tw;
+}
+
 // Two-step forward transform of a length-P signal whose upper half is zero, left in position
 // order; then the two-step inverse with cropped output, exactly as the passes do it.
 template <typename T, int NB>
@@ -94,11 +110,7 @@ static void test_two_step(std::mt19937_64& rng, double tol) {
   typedef Plan<NB> PL;
   constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1;
   std::normal_distribution<double> nd;
-  std::vector<C2<T>> tw(P);
-  for (int m = 0; m < P; ++m) {
-    CosSin cs = cossin_2pi(m, P);
-    tw[m] = {T(cs.c), T(-cs.s)};
-  }
+  std::vector<TwE<T>> tw = twiddle_table<T, P>();
   std::vector<cld> x(P, 0);
   std::vector<C2<T>> buf(P);
   for (int z = 0; z < NB; ++z) x[z] = cld(nd(rng), nd(rng));
@@ -110,7 +122,7 @@ static void test_two_step(std::mt19937_64& rng, double tol) {
       v[n1] = {T(a.real()), T(a.imag())};
     }
     dft_in_half<T, P1, -1>(v);
-    for (int k1 = 0; k1 < P1; ++k1) buf[k1 * P2 + n2] = cmul(v[k1], tw[n2 * k1]);
+    for (int k1 = 0; k1 < P1; ++k1) buf[k1 * P2 + n2] = tw_mul(v[k1], tw[n2 * k1]);
   }
   // step B (per k1): P2-point DFT of the contiguous block
   for (int k1 = 0; k1 < P1; ++k1) {
@@ -137,7 +149,7 @@ static void test_two_step(std::mt19937_64& rng, double tol) {
   err = 0; mx = 0;
   for (int n2 = 0; n2 < P2; ++n2) {
     C2<T> v[P1];
-    for (int k1 = 0; k1 < P1; ++k1) v[k1] = cmul_conjb(buf[k1 * P2 + n2], tw[n2 * k1]);
+    for (int k1 = 0; k1 < P1; ++k1) v[k1] = tw_mul_conj(buf[k1 * P2 + n2], tw[n2 * k1]);
     dft_out_half<T, P1, 1>(v);
     for (int n1 = 0; n1 < H1; ++n1) {
       cld got(v[n1].r / T(P), v[n1].i / T(P));
@@ -146,6 +158,67 @@ static void test_two_step(std::mt19937_64& rng, double tol) {
     }
   }
   check("two_step_roundtrip", P, err / mx, tol);
+}
+
+// Systematic error of the single-precision round trip that the pair energies see: for smooth
+// positive inputs x (Gaussians at random centres and widths, like pair densities) and a
+// positive even spectral weight g (like the Coulomb kernel), E = <x | IDFT(g DFT(x))> computed
+// with the FP32 two-step transforms, relative to the long-double value, averaged over many
+// inputs.  Rounding of the data averages out; rounded constants do not.  Returns the mean
+// relative error.
+template <int NB>
+static double roundtrip_energy_bias(std::mt19937_64& rng, int samples) {
+  typedef Plan<NB> PL;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1;
+  std::vector<TwE<float>> tw = twiddle_table<float, P>();
+  std::uniform_real_distribution<double> ud(0.0, 1.0);
+  // the weights (with the 1/P of the inverse folded in) are FP32 numbers, used as such by both
+  // sides, so that only the transforms differ
+  std::vector<float> g(P);
+  for (int k = 0; k < P; ++k) {
+    const int kk = k <= P - k ? k : P - k;
+    g[k] = float(1.0 / ((1.0 + 0.5 * kk * kk) * P));
+  }
+  double sum = 0.0;
+  for (int smp = 0; smp < samples; ++smp) {
+    const double c0 = NB * (0.3 + 0.4 * ud(rng)), w = NB * (0.05 + 0.1 * ud(rng));
+    std::vector<float> x(NB);
+    for (int z = 0; z < NB; ++z) x[z] = float(std::exp(-((z - c0) * (z - c0)) / (2 * w * w)));
+    // exact energy in long double
+    std::vector<cld> xl(P, 0);
+    for (int z = 0; z < NB; ++z) xl[z] = cld(x[z], 0);
+    std::vector<cld> xh = naive(xl, -1);
+    long double e_ref = 0;
+    for (int k = 0; k < P; ++k) e_ref += (long double)g[k] * std::norm(xh[k]);
+    // FP32 two-step forward, weight (in position order), two-step inverse, crop
+    std::vector<C2<float>> buf(P);
+    for (int n2 = 0; n2 < P2; ++n2) {
+      C2<float> v[P1];
+      for (int n1 = 0; n1 < H1; ++n1) v[n1] = {x[n1 * P2 + n2], 0.f};
+      dft_in_half<float, P1, -1>(v);
+      for (int k1 = 0; k1 < P1; ++k1) buf[k1 * P2 + n2] = tw_mul(v[k1], tw[n2 * k1]);
+    }
+    for (int k1 = 0; k1 < P1; ++k1) {
+      C2<float> v[P2];
+      for (int k2 = 0; k2 < P2; ++k2) v[k2] = buf[k1 * P2 + k2];
+      dft<float, P2, -1>(v);
+      for (int k2 = 0; k2 < P2; ++k2) {
+        const float gk = g[PL::freq(k1 * P2 + k2)];
+        v[k2] = {v[k2].r * gk, v[k2].i * gk};
+      }
+      dft<float, P2, 1>(v);
+      for (int k2 = 0; k2 < P2; ++k2) buf[k1 * P2 + k2] = v[k2];
+    }
+    long double e = 0;
+    for (int n2 = 0; n2 < P2; ++n2) {
+      C2<float> v[P1];
+      for (int k1 = 0; k1 < P1; ++k1) v[k1] = tw_mul_conj(buf[k1 * P2 + n2], tw[n2 * k1]);
+      dft_out_half<float, P1, 1>(v);
+      for (int n1 = 0; n1 < H1; ++n1) e += (long double)x[n1 * P2 + n2] * v[n1].r;
+    }
+    sum += double((e - e_ref) / e_ref);
+  }
+  return sum / samples;
 }
 
 int main() {
@@ -164,6 +237,20 @@ int main() {
   test_two_step<double, 40>(rng, t64); test_two_step<double, 48>(rng, t64);
   test_two_step<double, 56>(rng, t64); test_two_step<double, 64>(rng, t64);
   test_two_step<float, 48>(rng, t32); test_two_step<float, 64>(rng, t32);
+  {
+    // FP32 round-trip energy bias of the padded lengths of the benchmark boxes
+    const double b48 = roundtrip_energy_bias<48>(rng, 400);
+    const double b64 = roundtrip_energy_bias<64>(rng, 400);
+    const double b40 = roundtrip_energy_bias<40>(rng, 400);
+    const double b56 = roundtrip_energy_bias<56>(rng, 400);
+    std::printf("fp32 round-trip energy bias: P=80 %.2e  P=96 %.2e  P=112 %.2e  P=128 %.2e\n", b40,
+                b48, b56, b64);
+    const double lim = kSplitConstants ? 1e-8 : 1.0;
+    check("roundtrip_bias", 80, std::fabs(b40), lim);
+    check("roundtrip_bias", 96, std::fabs(b48), lim);
+    check("roundtrip_bias", 112, std::fabs(b56), lim);
+    check("roundtrip_bias", 128, std::fabs(b64), lim);
+  }
   if (failures) {
     std::printf("%d failures\n", failures);
     return 1;

@@ -73,3 +73,25 @@ def test_register_dft_and_two_step_transform_on_host(tmp_path):
     assert res.returncode == 0, res.stderr[-3000:]
     run = subprocess.run([str(exe)], capture_output=True, text=True)
     assert run.returncode == 0 and "OK" in run.stdout, run.stdout
+
+
+def test_binding_rejects_wrong_result_tensors():
+    """Caller-supplied result tensors are checked before their pointers reach the library:
+    a wrong dtype for M or a result block of the wrong shape is a ValueError, not a write past
+    the end of an allocation."""
+    import torch
+    from paper_2405_01522_amd import api
+    dev = torch.device("cpu")
+    ok = torch.zeros((8, 8), dtype=torch.complex128)
+    assert api.check_out(ok, "m_out", (8, 8), torch.complex128, dev) is not None
+    with pytest.raises(ValueError, match="dtype"):
+        api.check_out(torch.zeros((8, 8), dtype=torch.float32), "m_out", (8, 8),
+                      torch.complex128, dev)
+    with pytest.raises(ValueError, match="shape"):
+        api.check_out(torch.zeros((16, 16), dtype=torch.float64), "out", (512, 512),
+                      torch.float64, dev)
+    with pytest.raises(ValueError, match="contiguous"):
+        api.check_out(torch.zeros((8, 16), dtype=torch.float64)[:, ::2], "out", (8, 8),
+                      torch.float64, dev)
+    with pytest.raises(ValueError, match="expected cuda"):
+        api.check_out(ok, "m_out", (8, 8), torch.complex128, torch.device("cuda", 0))

@@ -414,8 +414,8 @@ def c4():
 
 def test_config4_batched_full_size(c4):
     """64 molecules of edges 32..64 and 2..16 orbitals in one FP32 batched build; every system
-    equals its one-system build bit for bit, and four systems are checked against the oracle
-    (E_x within 1e-6 Ha)."""
+    equals its one-system build bit for bit (the oracle comparison of every system is in
+    test_gpu_fullsize.py)."""
     ace = _ace()
     dt = torch.complex64
     systems = [{"h": m.h, "phi": _t(synth.to_precision(m.phi, True), dt)} for m in c4]
@@ -423,14 +423,11 @@ def test_config4_batched_full_size(c4):
     b.build(systems)
     st, mol, info = b.status()
     assert st == 0, (st, mol, info)
-    order = sorted(range(len(c4)), key=lambda k: c4[k].n ** 3 * c4[k].phi.shape[0] ** 2)
-    for k in order[:2] + order[len(order) // 2:len(order) // 2 + 2]:
-        m = c4[k]
-        _, _, _, ex = exchange.ace_build(m.phi, m.h)
-        assert abs(float(systems[k]["ex"].cpu()) - ex) < 1e-6, k
     contexts = {}
     for k, m in enumerate(c4):
-        ctx = contexts.setdefault(m.n, ace.AceContext(m.n, m.h, dt))
+        if (m.n, m.h) not in contexts:
+            contexts[(m.n, m.h)] = ace.AceContext(m.n, m.h, dt)
+        ctx = contexts[(m.n, m.h)]
         xi, _, ex = ctx.ace_build(systems[k]["phi"])
         torch.cuda.synchronize()
         assert torch.equal(xi, systems[k]["xi"]) and torch.equal(ex, systems[k]["ex"]), k
@@ -545,12 +542,14 @@ def test_ace_complex_eleven_orbitals(dt):
 def test_batched_complex_more_than_sixteen_orbitals():
     """A complex batch whose largest system has more than 16 orbitals takes the separate W,
     Gram and Cholesky kernels for every system; each system still equals its one-system build
-    bit for bit, and E_x matches the oracle."""
+    bit for bit, and E_x matches the oracle.  The 32-orbital system's M (1024 entries) is
+    reduced by the many-output kernel, the smaller ones' by the one-output kernel, in the batch
+    as in their single builds."""
     import paper_2405_01522_amd as ace
     dt = torch.complex64
     rng = np.random.default_rng(91)
     cases = []
-    for n, k in [(10, 3), (10, 20), (10, 11), (12, 7)]:
+    for n, k in [(10, 3), (10, 20), (10, 32), (10, 11), (12, 7)]:
         h = 0.5
         x = synth.coords(n, h)
         r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
