@@ -50,7 +50,8 @@ enum {
   ACE_ERR_HIP = -3,         /* a HIP runtime call failed */
   ACE_ERR_OOM = -4,         /* device allocation failed */
   ACE_ERR_NOT_POSDEF = -5,  /* -M not positive definite (device status; info = pivot) */
-  ACE_ERR_NONFINITE = -6    /* M not finite (device status) */
+  ACE_ERR_NONFINITE = -6,   /* M not finite (device status) */
+  ACE_ERR_SCRATCH = -7      /* ace_apply_noalloc: one vector's sums exceed the static scratch */
 };
 
 /* Largest orbital count accepted by ace_build / ace_apply: real orbitals, complex orbitals. */
@@ -121,6 +122,23 @@ int ace_build_targets(ace_ctx* ctx, const void* phi_occ, int no, const void* psi
  * xi: [n][N^3] from ace_build; psi: [nv][N^3]; kpsi_out: [nv][N^3] (may not alias psi).
  */
 int ace_apply(ace_ctx* ctx, const void* xi, int n, const void* psi, int nv, void* kpsi_out);
+
+/*
+ * ace_apply without any allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results as ace_apply (the same kernels and passes, so the same bits); its
+ * Gram partial sums and the reduced xi^H psi block live in a static device array of
+ * ACE_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends) instead of a context
+ * workspace, and the call makes no hipMalloc / hipFree.  The array's address on each device
+ * is looked up when a context is created there.  Needs 8 * (1 + complex) * n * (ceil(N^3 /
+ * 256) + 1) bytes per vector (every supported edge and orbital count fits; vectors are taken
+ * in passes of as many as fit, at most 64); ACE_ERR_SCRATCH otherwise.  All calls on one GPU
+ * share its array: calls that overlap in time on one GPU (other streams, other contexts, other
+ * threads) race and must be serialised by the caller.  Nothing in the array needs clearing.
+ */
+#define ACE_NOALLOC_SCRATCH_BYTES (8u << 20)
+int ace_apply_noalloc(ace_ctx* ctx, const void* xi, int n, const void* psi, int nv,
+                      void* kpsi_out);
 
 /*
  * Direct exact exchange (Eq. (2)), the operator ACE compresses:

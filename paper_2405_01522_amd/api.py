@@ -161,6 +161,17 @@ class AceContext:
         check(lib().ace_apply(self._h, x, xi.shape[0], p, psi.shape[0], o), "ace_apply")
         return out
 
+    def ace_apply_noalloc(self, xi, psi, out):
+        """ace_apply through the entry point that allocates nothing (static device scratch);
+        the caller provides ``out``."""
+        x = self._vol(xi, "xi")
+        p = self._vol(psi, "psi")
+        o = self._vol(out, "kpsi_out", psi.shape[0])
+        self._sync_stream()
+        check(lib().ace_apply_noalloc(self._h, x, xi.shape[0], p, psi.shape[0], o),
+              "ace_apply_noalloc")
+        return out
+
     def exchange_apply_direct(self, phi, psi, out=None):
         if out is None:
             out = self._empty(psi.shape[0])

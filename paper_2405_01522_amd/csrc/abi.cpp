@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -42,6 +43,39 @@ int solve_pair_list(ace_ctx* c, const std::vector<PairPtrs>& items) {
                              c->stream, c->tr());
   }
   return hip_check(hipGetLastError());
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Static scratch of ace_apply_noalloc: the Gram partial sums and the reduced xi^H psi block
+// live in this array instead of a context workspace.  Host code never uses the symbol itself
+// as an address; the per-device address comes from hipGetSymbolAddress once per device.
+namespace {
+constexpr size_t kNoallocScratch = ACE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratch];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch` (looked up once, with `dev` current).
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return ACE_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return ACE_ERR_HIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return ACE_ERR_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return ACE_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ACE_OK;
 }
 }  // namespace
 
@@ -84,6 +118,15 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
   c->ng = (size_t)n * n * n;
   c->stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&c->device);
+  {
+    // set-up of the no-allocation entry point's scratch on this device
+    void* sp = nullptr;
+    const int src = scratch_address(c->device, &sp);
+    if (src) {
+      delete c;
+      return src;
+    }
+  }
   const int p = 2 * n, ho = p / 2 + 1;
   const size_t oct = (size_t)ho * ho * ho;
   // cosine weights w(a) cos(2 pi k a / P) for the real-even kernel transform
@@ -279,6 +322,36 @@ int ace_apply(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* 
   return hip_check(hipGetLastError());
 }
 
+int ace_apply_noalloc(ace_ctx* c, const void* xi, int n, const void* psi, int nv, void* out) {
+  if (!c || !xi || !psi || !out || n < 1 || n > max_orbitals(c->dtype) || nv < 1)
+    return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+  size_t chunk;
+  const int nblk = gram_blocks(ng, &chunk);
+  // per vector: nblk partial rows of n entries and the reduced column of Z (each part
+  // 256-byte aligned); as many vectors per pass as the scratch holds, at most 64 as in
+  // ace_apply (so both give the same passes and the same bits)
+  const size_t per_vec = wide * (size_t)n * ((size_t)nblk + 1);
+  const size_t room = kNoallocScratch - 512;
+  if (per_vec > room) return ACE_ERR_SCRATCH;
+  const int chunk_v = (int)std::min<size_t>({(size_t)nv, 64, room / per_vec});
+  void* base = nullptr;
+  int rc = scratch_address(c->device, &base);
+  if (rc) return rc;
+  char* part = (char*)base;
+  const size_t part_bytes = (wide * (size_t)nblk * n * chunk_v + 255) / 256 * 256;
+  char* z = part + part_bytes;
+  for (int v0 = 0; v0 < nv; v0 += chunk_v) {
+    const int cv = std::min(chunk_v, nv - v0);
+    const char* ps = (const char*)psi + eb * ng * (size_t)v0;
+    char* o = (char*)out + eb * ng * (size_t)v0;
+    launch_gram(c->dtype, xi, n, ps, cv, ng, part, c->h * c->h * c->h, z, c->stream, nullptr);
+    launch_apply_out(c->dtype, xi, n, ng, z, cv, o, c->stream, nullptr);
+  }
+  return hip_check(hipGetLastError());
+}
+
 int exchange_apply_direct(ace_ctx* c, const void* phi, int n, const void* psi, int nv, void* out) {
   if (!c || !phi || !psi || !out || n < 1 || n > max_orbitals(c->dtype) || nv < 1) return ACE_ERR_INVALID;
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
@@ -449,6 +522,7 @@ const char* ace_strerror(int code) {
     case ACE_ERR_OOM: return "device out of memory";
     case ACE_ERR_NOT_POSDEF: return "-M is not positive definite";
     case ACE_ERR_NONFINITE: return "non-finite value in M";
+    case ACE_ERR_SCRATCH: return "problem does not fit the static scratch of the no-allocation call";
   }
   return "unknown error";
 }
