@@ -198,10 +198,11 @@ def run_batched(mols, dtype, steps, warmup):
     torch.cuda.synchronize()
     graph_ms = e0.elapsed_time(e1) / steps
     del g
+    tuning = b.tuning()
     b.close()
     npairs = sum(m.phi.shape[0] * (m.phi.shape[0] + 1) // 2 for m in mols)
     return dict(ms_per_build=graph_ms, eager_ms_per_build=eager_ms, pair_solves=npairs,
-                pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols))
+                pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols), tuning=tuning)
 
 
 def run_tda(mol, steps, warmup):

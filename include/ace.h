@@ -184,10 +184,16 @@ int uhf_coupling(ace_ctx* ctx, const void* occ_a, int no_a, const void* virt_a, 
 
 /*
  * Uneven batches of independent systems (the ACE rebuild of Sec. 3.1, Eqs. (11)-(12), for many
- * molecules at once).  A batch owns one kernel spectrum per distinct (n, h) and groups the
- * systems into size classes that run concurrently on streams of their own between a fork and
- * a join on the batch stream (so one call can be captured into a HIP graph once the
- * workspaces have been sized by an earlier call).
+ * molecules at once).  A batch owns one kernel spectrum per distinct (n, h).  Each pass of a
+ * build is one launch over every system of every box edge: the three pair-Poisson passes are
+ * persistent launches over a device list of transform planes (largest edge first), and W / M /
+ * Cholesky / xi one launch each over all systems.  All work is enqueued on the batch stream, so
+ * a call can be captured into a HIP graph once an earlier eager call has sized the workspaces.
+ * Launch shapes (XY-pass planes per workgroup for each edge, threads of the z passes) are tuned
+ * by timing the candidates on the first eager call for each (dtype, set of box edges); the
+ * choices are kept for the process and, when the environment variable ACE_TUNE_CACHE names a
+ * file, appended to that file and read from it by later processes.  Every shape gives the same
+ * bits.
  */
 typedef struct ace_batch ace_batch;
 
@@ -211,6 +217,11 @@ int ace_batch_set_stream(ace_batch* batch, void* hip_stream);
  * compiled for the dtype.  Device-side failures are reported per system by ace_batch_status.
  */
 int ace_build_batched(ace_batch* batch, const ace_mol* mols, int nmol);
+
+/* The launch shape used by the last ace_build_batched call, as text (host buffer of len
+ * bytes): "dtype=<d>,edges=<n>-<n>... xy=<edge>:<planes>,... zf=<threads> zi=<threads>
+ * source=tuned|cache|default". */
+int ace_batch_tuning(ace_batch* batch, char* buf, int len);
 
 /*
  * Synchronise and report the first device-side failure since the last call: *status, the

@@ -39,6 +39,7 @@ SIGNATURES = {
     "ace_batch_set_stream": (_I, [_P, _P]),
     "ace_build_batched": (_I, [_P, _P, _I]),
     "ace_batch_status": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "ace_batch_tuning": (_I, [_P, ctypes.c_char_p, _I]),
     "ace_batch_trace_enable": (_I, [_P, _I]),
     "ace_batch_trace_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_longlong)]),
     "tda_excitations": (_I, [_P, _P, _P, _I, _P, _I, _I, _D, _I, _P, _P, ctypes.POINTER(_I)]),

@@ -473,7 +473,7 @@ class AceContext:
 
 class AceBatch:
     """Uneven batch of independent systems (each its own box edge, spacing and orbital count)
-    built by one call; size classes run concurrently on streams of their own."""
+    built by one call: one launch per pass over every system."""
 
     def __init__(self, dtype, device=None):
         self.dtype = dtype
@@ -533,6 +533,12 @@ class AceBatch:
         self._sync_stream()
         check(lib().ace_build_batched(self._h, arr, len(systems)), "ace_build_batched")
         return systems
+
+    def tuning(self):
+        """The launch shape of the last build (text, see ace_batch_tuning)."""
+        buf = ctypes.create_string_buffer(512)
+        check(lib().ace_batch_tuning(self._h, buf, 512), "ace_batch_tuning")
+        return buf.value.decode()
 
     def status(self):
         st, mol, info = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libace.so")
-SOURCES = ["poisson.hip", "ace_kernels.hip", "tda.hip", "linalg.hip", "scf.hip", "convnet.hip",
+SOURCES = ["poisson.hip", "poisson_queue.hip", "ace_kernels.hip", "tda.hip", "linalg.hip", "scf.hip",
+           "convnet.hip", "batch.cpp",
            "abi.cpp", "scf_driver.cpp"]
 ARCH = "gfx950"
 

@@ -529,290 +529,6 @@ const char* ace_strerror(int code) {
 
 }  // extern "C"
 
-// ---------------------------------------------------------------------------------------
-// Uneven batches: many independent systems (box edge, spacing, orbital count each their own)
-// built by one call.  Systems are grouped into size classes of equal (edge, spacing); each
-// class runs on its own stream -- all of its pair solves in one launch sequence, then one
-// launch per ACE step over all of its systems -- and the classes run concurrently between a
-// fork and a join event on the caller's stream, so the whole call is capturable in one graph.
-
-namespace {
-
-struct BatchClass {
-  int n = 0;
-  double h = 0;
-  ace_ctx* ctx = nullptr;        // kernel spectrum and twiddles of this (edge, spacing)
-  hipStream_t stream = nullptr;  // the class's own stream (default priority)
-  hipEvent_t done = nullptr;
-  Blob desc;                     // [MolArgs x nmol][PairPtrs x npairs]
-  Buf work, vbuf, wbuf, part, mred, linvh;
-};
-
-}  // namespace
-
-struct ace_batch {
-  int dtype = 0;
-  hipStream_t stream = nullptr;
-  hipEvent_t fork = nullptr;
-  std::vector<BatchClass*> classes;
-  Buf status;
-  size_t status_n = 0;
-  ace::Trace trace;
-  ace::Trace* tr(hipStream_t s) {
-    trace.stream = s;
-    return trace.on ? &trace : nullptr;
-  }
-};
-
-extern "C" {
-
-int ace_batch_create(int dtype, void* hip_stream, ace_batch** out) {
-  if (!out || dtype < ACE_C128 || dtype > ACE_R32) return ACE_ERR_INVALID;
-  *out = nullptr;
-  ace_batch* b = new (std::nothrow) ace_batch();
-  if (!b) return ACE_ERR_OOM;
-  b->dtype = dtype;
-  b->stream = (hipStream_t)hip_stream;
-  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
-    delete b;
-    return ACE_ERR_HIP;
-  }
-  *out = b;
-  return ACE_OK;
-}
-
-int ace_batch_destroy(ace_batch* b) {
-  if (!b) return ACE_OK;
-  (void)hipStreamSynchronize(b->stream);
-  for (BatchClass* c : b->classes) {
-    (void)hipStreamSynchronize(c->stream);
-    for (Buf* x : {&c->work, &c->vbuf, &c->wbuf, &c->part, &c->mred, &c->linvh})
-      if (x->p) (void)hipFree(x->p);
-    free_blob(c->desc);
-    if (c->done) (void)hipEventDestroy(c->done);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
-    ace_ctx_destroy(c->ctx);
-    delete c;
-  }
-  if (b->status.p) (void)hipFree(b->status.p);
-  if (b->fork) (void)hipEventDestroy(b->fork);
-  b->trace.stream = b->stream;
-  b->trace.release();
-  delete b;
-  return ACE_OK;
-}
-
-int ace_batch_set_stream(ace_batch* b, void* s) {
-  if (!b) return ACE_ERR_INVALID;
-  if (hipStreamSynchronize(b->stream) != hipSuccess) return ACE_ERR_HIP;
-  b->stream = (hipStream_t)s;
-  return ACE_OK;
-}
-
-int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
-  if (!b || !mols || nmol < 1) return ACE_ERR_INVALID;
-  const int dt = b->dtype;
-  for (int m = 0; m < nmol; ++m) {
-    const ace_mol& x = mols[m];
-    if (!x.phi || !x.xi || x.norb < 1 || x.norb > max_orbitals(dt) || !(x.h > 0.0) ||
-        !std::isfinite(x.h))
-      return ACE_ERR_INVALID;
-    if (!ace_size_supported(x.n, dt)) return ACE_ERR_UNSUPPORTED;
-  }
-  // status words, one pair per system
-  if (b->status_n < (size_t)nmol) {
-    if (ensure_on(b->stream, b->status, sizeof(int) * 2 * (size_t)nmol)) return ACE_ERR_OOM;
-    if (hipMemsetAsync(b->status.p, 0, sizeof(int) * 2 * (size_t)nmol, b->stream) != hipSuccess)
-      return ACE_ERR_HIP;
-    b->status_n = nmol;
-  }
-  // size classes, in order of first appearance
-  std::vector<int> cls(nmol);
-  std::vector<BatchClass*> used;
-  for (int m = 0; m < nmol; ++m) {
-    BatchClass* c = nullptr;
-    for (BatchClass* k : b->classes)
-      if (k->n == mols[m].n && k->h == mols[m].h) c = k;
-    if (!c) {
-      c = new (std::nothrow) BatchClass();
-      if (!c) return ACE_ERR_OOM;
-      c->n = mols[m].n;
-      c->h = mols[m].h;
-      int rc = ace_ctx_create(c->n, c->h, dt, b->stream, &c->ctx);
-      if (!rc && hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
-        rc = ACE_ERR_HIP;
-      if (!rc && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess)
-        rc = ACE_ERR_HIP;
-      if (rc) {
-        if (c->ctx) ace_ctx_destroy(c->ctx);
-        if (c->stream) (void)hipStreamDestroy(c->stream);
-        delete c;
-        return rc;
-      }
-      b->classes.push_back(c);
-    }
-    cls[m] = (int)(std::find(b->classes.begin(), b->classes.end(), c) - b->classes.begin());
-    if (std::find(used.begin(), used.end(), c) == used.end()) used.push_back(c);
-  }
-  const size_t eb = elem_bytes(dt), wide = is_cplx(dt) ? 16 : 8;
-  const bool fp64 = is_fp64(dt), rp = !is_cplx(dt);
-  if (hipEventRecord(b->fork, b->stream) != hipSuccess) return ACE_ERR_HIP;
-  for (BatchClass* c : used) {
-    const int ci = (int)(std::find(b->classes.begin(), b->classes.end(), c) - b->classes.begin());
-    const size_t ng = (size_t)c->n * c->n * c->n;
-    size_t chunk;
-    const int nch = gram_blocks(ng, &chunk);
-    // sizes of this class
-    // np: pair volumes; nlist: list entries (complex: off-diagonal pairs + diagonal couples)
-    size_t np = 0, norb = 0, nsq = 0, nlist = 0;
-    int nm = 0, nmax = 0;
-    for (int m = 0; m < nmol; ++m)
-      if (cls[m] == ci) {
-        const int k = mols[m].norb;
-        np += (size_t)k * (k + 1) / 2;
-        nlist += rp ? (size_t)k * (k + 1) / 2 : (size_t)k * (k - 1) / 2 + (k + 1) / 2;
-        norb += k;
-        nsq += (size_t)k * k;
-        nmax = std::max(nmax, k);
-        ++nm;
-      }
-    const size_t items = rp ? (np + 1) / 2 : nlist;
-    const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
-    const size_t budget = size_t(2) << 30;
-    const size_t batch = std::max<size_t>(1, std::min<size_t>(items, budget / per_item));
-    int rc = ensure_on(c->stream, c->work, per_item * batch);
-    if (!rc) rc = ensure_on(c->stream, c->vbuf, eb * ng * np);
-    if (!rc) rc = ensure_on(c->stream, c->wbuf, eb * ng * norb);
-    if (!rc) rc = ensure_on(c->stream, c->part, wide * (size_t)nch * nsq);
-    if (!rc) rc = ensure_on(c->stream, c->mred, wide * nsq);
-    if (!rc) rc = ensure_on(c->stream, c->linvh, wide * nsq);
-    if (rc) return rc;
-    // descriptors
-    std::vector<unsigned char> blob(sizeof(MolArgs) * nm + sizeof(PairPtrs) * nlist);
-    MolArgs* ma = (MolArgs*)blob.data();
-    PairPtrs* pp = (PairPtrs*)(blob.data() + sizeof(MolArgs) * nm);
-    size_t pv = 0, pw = 0, psq = 0, pl = 0;
-    int im = 0;
-    for (int m = 0; m < nmol; ++m) {
-      if (cls[m] != ci) continue;
-      const ace_mol& x = mols[m];
-      const int k = x.norb;
-      MolArgs a{};
-      a.phi = x.phi;
-      a.v = (char*)c->vbuf.p + eb * ng * pv;
-      a.w = (char*)c->wbuf.p + eb * ng * pw;
-      a.xi = x.xi;
-      a.part = (char*)c->part.p + wide * (size_t)nch * psq;
-      a.mred = (char*)c->mred.p + wide * psq;
-      a.linvh = (char*)c->linvh.p + wide * psq;
-      a.m_out = x.M;
-      a.ex_out = x.ex;
-      a.status = (int*)b->status.p + 2 * m;
-      a.n = k;
-      ma[im++] = a;
-      auto orb = [&](int j) { return (const char*)x.phi + eb * ng * j; };
-      auto vol = [&](int j, int i) { return (char*)a.v + eb * ng * ((size_t)i * (i + 1) / 2 + j); };
-      if (rp) {
-        for (int q = 0; q < k; ++q)
-          for (int p = 0; p <= q; ++p) {
-            PairPtrs t;
-            t.a = orb(p);
-            t.b = orb(q);
-            t.v = vol(p, q);
-            pp[pl + (size_t)q * (q + 1) / 2 + p] = t;
-          }
-        pl += (size_t)k * (k + 1) / 2;
-      } else {
-        // the same transforms as the one-system build: off-diagonal pairs, then the real
-        // diagonal densities of orbitals 2m and 2m + 1 together
-        for (int q = 0; q < k; ++q)
-          for (int p = 0; p < q; ++p) {
-            PairPtrs t;
-            t.a = orb(p);
-            t.b = orb(q);
-            t.v = vol(p, q);
-            pp[pl++] = t;
-          }
-        for (int d = 0; d < k; d += 2) {
-          PairPtrs t;
-          t.a = orb(d);
-          t.v = vol(d, d);
-          if (d + 1 < k) {
-            t.b = orb(d + 1);
-            t.v2 = vol(d + 1, d + 1);
-            t.kind = 1;
-          } else {
-            t.b = orb(d);
-            t.kind = 2;
-          }
-          pp[pl++] = t;
-        }
-      }
-      pv += (size_t)k * (k + 1) / 2;
-      pw += k;
-      psq += (size_t)k * k;
-    }
-    rc = upload_blob(c->stream, c->desc, blob.data(), blob.size());
-    if (rc) return rc;
-    if (hipStreamWaitEvent(c->stream, b->fork, 0) != hipSuccess) return ACE_ERR_HIP;
-    const MolArgs* mdev = (const MolArgs*)c->desc.dev.p;
-    const PairPtrs* pdev = (const PairPtrs*)((const char*)c->desc.dev.p + sizeof(MolArgs) * nm);
-    ace::Trace* tr = b->tr(c->stream);
-    for (size_t i0 = 0; i0 < items; i0 += batch) {
-      const size_t ni = std::min(batch, items - i0);
-      const size_t p0 = rp ? 2 * i0 : i0;
-      const size_t npb = rp ? std::min(2 * ni, nlist - p0) : ni;
-      launch_pair_poisson_ptrs(c->n, fp64, rp, pdev + p0, (int)npb, c->work.p, c->ctx->gpos,
-                               c->ctx->tw, c->stream, tr);
-    }
-    launch_ace_steps_batched(dt, mdev, nm, nmax, ng, c->h * c->h * c->h, c->stream, tr);
-    if (hipEventRecord(c->done, c->stream) != hipSuccess) return ACE_ERR_HIP;
-    if (hipStreamWaitEvent(b->stream, c->done, 0) != hipSuccess) return ACE_ERR_HIP;
-  }
-  return hip_check(hipGetLastError());
-}
-
-int ace_batch_status(ace_batch* b, int* status, int* mol, int* info) {
-  if (!b || !status) return ACE_ERR_INVALID;
-  *status = 0;
-  if (mol) *mol = -1;
-  if (info) *info = 0;
-  if (hipStreamSynchronize(b->stream) != hipSuccess) return ACE_ERR_HIP;
-  if (!b->status_n) return ACE_OK;
-  std::vector<int> st(2 * b->status_n);
-  if (hipMemcpy(st.data(), b->status.p, sizeof(int) * st.size(), hipMemcpyDeviceToHost) != hipSuccess)
-    return ACE_ERR_HIP;
-  for (size_t m = 0; m < b->status_n; ++m)
-    if (st[2 * m]) {
-      *status = st[2 * m];
-      if (mol) *mol = (int)m;
-      if (info) *info = st[2 * m + 1];
-      break;
-    }
-  if (hipMemset(b->status.p, 0, sizeof(int) * st.size()) != hipSuccess) return ACE_ERR_HIP;
-  return ACE_OK;
-}
-
-int ace_batch_trace_enable(ace_batch* b, int on) {
-  if (!b) return ACE_ERR_INVALID;
-  b->trace.stream = b->stream;
-  for (BatchClass* c : b->classes) (void)hipStreamSynchronize(c->stream);
-  int rc = b->trace.collect();
-  b->trace.on = on != 0;
-  return rc;
-}
-
-int ace_batch_trace_read(ace_batch* b, int id, double* total_ms, long long* count) {
-  if (!b || id < 0 || id >= TR_COUNT || !total_ms) return ACE_ERR_INVALID;
-  for (BatchClass* c : b->classes) (void)hipStreamSynchronize(c->stream);
-  b->trace.stream = b->stream;
-  int rc = b->trace.collect();
-  *total_ms = b->trace.total_ms[id];
-  if (count) *count = b->trace.count[id];
-  return rc;
-}
-
-}  // extern "C"
 
 // ---------------------------------------------------------------------------------------
 // Tamm-Dancoff excitations (Sec. 2: A X = omega X with A = diag(eps_a - eps_i) + C) by a

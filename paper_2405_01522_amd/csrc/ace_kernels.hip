@@ -24,13 +24,35 @@ __device__ __forceinline__ size_t pair_index(int a, int b) {  // a <= b
 
 // Argument sources: one system passed by value, or many systems read from device memory
 // (index = the grid coordinate that enumerates systems).
+// Arguments of one workgroup: the system's arguments, the workgroup's 256-point block within
+// that system, and the system's point count.
+template <typename A>
+struct Placed {
+  A a;
+  size_t blk;
+  size_t ng;
+};
 struct OneMol {
   MolArgs m;
   __device__ __forceinline__ MolArgs get(int) const { return m; }
+  __device__ __forceinline__ Placed<MolArgs> place(size_t ng) const { return {m, blockIdx.x, ng}; }
 };
-struct ManyMol {
+struct ManyMol {  // systems of one box edge: grid (blocks, systems)
   const MolArgs* ms;
   __device__ __forceinline__ MolArgs get(int i) const { return ms[i]; }
+  __device__ __forceinline__ Placed<MolArgs> place(size_t ng) const {
+    return {ms[blockIdx.y], blockIdx.x, ng};
+  }
+};
+// systems of any box edges in one flat grid: bsys[blockIdx.x] is the block's system
+struct FlatMol {
+  const MolArgs* ms;
+  const int* bsys;
+  __device__ __forceinline__ MolArgs get(int i) const { return ms[i]; }
+  __device__ __forceinline__ Placed<MolArgs> place(size_t) const {
+    const MolArgs m = ms[bsys[blockIdx.x]];
+    return {m, blockIdx.x - (size_t)m.blk0, m.ng};
+  }
 };
 struct GramArgs {
   const void* A;
@@ -39,21 +61,36 @@ struct GramArgs {
   int nb;
   void* part;
 };
+__device__ __forceinline__ GramArgs gram_of(const MolArgs& m) {
+  return {m.phi, m.n, m.w, m.n, m.part};
+}
 struct OneGram {
   GramArgs g;
-  __device__ __forceinline__ GramArgs get(int) const { return g; }
-};
-struct ManyGram {
-  const MolArgs* ms;
-  __device__ __forceinline__ GramArgs get(int i) const {
-    const MolArgs m = ms[i];
-    return {m.phi, m.n, m.w, m.n, m.part};
+  __device__ __forceinline__ Placed<GramArgs> place(size_t ng) const {
+    return {g, blockIdx.x, ng};
   }
 };
+struct ManyGram {  // grid (blocks, tiles, systems)
+  const MolArgs* ms;
+  __device__ __forceinline__ Placed<GramArgs> place(size_t ng) const {
+    return {gram_of(ms[blockIdx.z]), blockIdx.x, ng};
+  }
+};
+struct FlatGram {  // grid (blocks of all systems, tiles)
+  const MolArgs* ms;
+  const int* bsys;
+  __device__ __forceinline__ Placed<GramArgs> place(size_t) const {
+    const MolArgs m = ms[bsys[blockIdx.x]];
+    return {gram_of(m), blockIdx.x - (size_t)m.blk0, m.ng};
+  }
+};
+// a reduction: partial rows, outputs per row, destination, partial rows to add, scale
 struct RedArgs {
   const void* part;
   int no;
   void* out;
+  int nblk;
+  double scale;
 };
 struct OneRed {
   RedArgs r;
@@ -63,7 +100,7 @@ struct ManyRed {
   const MolArgs* ms;
   __device__ __forceinline__ RedArgs get(int i) const {
     const MolArgs m = ms[i];
-    return {m.part, m.n * m.n, m.mred};
+    return {m.part, m.n * m.n, m.mred, (int)((m.ng + kThreads - 1) / kThreads), m.dv};
   }
 };
 
@@ -71,13 +108,15 @@ struct ManyRed {
 // One thread per point holds every phi_j(r) and W_i(r) in registers, so each pair volume is
 // read once: v_ab feeds W_b (with phi_a) and, for a != b, W_a (with phi_b and conj(v_ab)).
 template <typename E, int NMAX, typename S>
-__global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng) {
-  const MolArgs m = src.get(blockIdx.y);
+__global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng_arg) {
+  const Placed<MolArgs> pc = src.place(ng_arg);
+  const MolArgs m = pc.a;
+  const size_t ng = pc.ng;
   const E* __restrict__ phi = (const E*)m.phi;
   const E* __restrict__ v = (const E*)m.v;
   E* __restrict__ w = (E*)m.w;
   const int n = m.n;
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t r = pc.blk * kThreads + threadIdx.x;
   if (r >= ng) return;
   E ph[NMAX], acc[NMAX];
 #pragma unroll
@@ -162,10 +201,12 @@ __device__ __forceinline__ void load4(const E* __restrict__ row, size_t r0, size
 
 // skip8: complex systems with at most 8 A rows are left to k_gram_c8 (launched beside it)
 template <typename E, typename S, int TB, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng, int skip8) {
+__global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng_arg, int skip8) {
   typedef typename Elem<E>::wide W;
   constexpr bool CPLX = Elem<E>::cplx;
-  const GramArgs ga = src.get(blockIdx.z);
+  const Placed<GramArgs> pc = src.place(ng_arg);
+  const GramArgs ga = pc.a;
+  const size_t ng = pc.ng;
   const E* __restrict__ A = (const E*)ga.A;
   const E* __restrict__ B = (const E*)ga.B;
   const int na = ga.na, nb = ga.nb;
@@ -182,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng, int skip8) 
   // loads are unconditional (clamped row and point) so they issue back to back; values
   // outside the matrices are zeroed afterwards
   const E* ra = A + (size_t)(ka < na ? ka : na - 1) * ng;
-  const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * kGramChunk;
+  const size_t start = pc.blk * kGramPoints + (size_t)wave * kGramChunk;
   E av[NQ][4];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) load4<E, VEC>(ra, start + 16 * q + 4 * g, ng, av[q]);
@@ -248,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng, int skip8) 
       W v = red[0][th];
 #pragma unroll
       for (int w = 1; w < kGramWaves; ++w) v = e_add(v, red[w][th]);
-      part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l] = v;
+      part[pc.blk * na * nb + (size_t)k * nb + l] = v;
     }
   }
 }
@@ -259,10 +300,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng, int skip8) 
 //   D = [Re A; Im A] [Re B, Im B],  Re(A^H B) = D_rr + D_ii,  Im(A^H B) = D_ri - D_ir
 // with no padded rows and no third (Gauss) product.  TB tiles of 8 B columns share the A rows.
 template <typename E, typename S, int TB, bool VEC, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng) {
+__global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
   typedef typename Elem<E>::wide W;
   static_assert(Elem<E>::cplx, "complex elements");
-  const GramArgs ga = src.get(blockIdx.z);
+  const Placed<GramArgs> pc = src.place(ng_arg);
+  const GramArgs ga = pc.a;
+  const size_t ng = pc.ng;
   const E* __restrict__ A = (const E*)ga.A;
   const E* __restrict__ B = (const E*)ga.B;
   const int na = ga.na, nb = ga.nb;
@@ -278,7 +321,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng) {
   const int li = lane & 15, g = lane >> 4;
   const int ri = li & 7;
   const bool imag = li >= 8;
-  const size_t start = (size_t)blockIdx.x * kGramPoints + (size_t)wave * CHUNK;
+  const size_t start = pc.blk * kGramPoints + (size_t)wave * CHUNK;
   // Lanes li and li + 8 work on the same row (real and imaginary part).  Each loads half of the
   // wavefront's steps (li < 8 the first NH, li >= 8 the last NH) and gets the other half's
   // component from its partner lane (li ^ 8), so every element is loaded once.
@@ -346,7 +389,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng) {
       W v;
       v.r = re;
       v.i = im;
-      part[(size_t)blockIdx.x * na * nb + (size_t)k * nb + l0 + l] = v;
+      part[pc.blk * na * nb + (size_t)k * nb + l0 + l] = v;
     }
   }
 }
@@ -435,7 +478,7 @@ __device__ __forceinline__ void chol_lanes_body(const MolArgs& ma, const W* msrc
 // (each wavefront 64 points, the four summed in a fixed order), writing the same partial
 // layout part[block][o] as k_gram, so M is reduced by k_gram_reduce and W is not read again.
 template <typename E, int NMAX, typename S>
-__global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
+__global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng_arg) {
   static_assert(NMAX <= 16, "one 16 x 16 tile");
   typedef typename Elem<E>::wide W;
   constexpr bool CPLX = Elem<E>::cplx;
@@ -448,13 +491,15 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
   E* lp = reinterpret_cast<E*>(smem);
   E* lw = lp + NMAX * LD;
   W(*red)[256] = reinterpret_cast<W(*)[256]>(smem);
-  const MolArgs m = src.get(blockIdx.y);
+  const Placed<MolArgs> pc = src.place(ng_arg);
+  const MolArgs m = pc.a;
+  const size_t ng = pc.ng;
   const E* __restrict__ phi = (const E*)m.phi;
   const E* __restrict__ v = (const E*)m.v;
   E* __restrict__ w = (E*)m.w;
   W* __restrict__ part = (W*)m.part;
   const int n = m.n;
-  const size_t r0 = (size_t)blockIdx.x * kThreads;
+  const size_t r0 = pc.blk * kThreads;
   const size_t r = r0 + threadIdx.x;
   const bool in = r < ng;
   const size_t rc = in ? r : ng - 1;
@@ -520,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
       if (k < n && l < n) {
         W x = {};
         set_ri(x, re, im);
-        part[(size_t)blockIdx.x * n * n + (size_t)k * n + l] = x;
+        part[pc.blk * n * n + (size_t)k * n + l] = x;
       }
     }
   } else {
@@ -563,7 +608,7 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng) {
       W x = red[0][th];
 #pragma unroll
       for (int q = 1; q < kGramWaves; ++q) x = e_add(x, red[q][th]);
-      part[(size_t)blockIdx.x * n * n + (size_t)k * n + l] = x;
+      part[pc.blk * n * n + (size_t)k * n + l] = x;
     }
   }
 }
@@ -730,10 +775,10 @@ __device__ __forceinline__ C2<double> shfl_xor_w<C2<double>>(C2<double> v, int m
 constexpr int kColsMin = 1024;
 
 template <typename W, typename S>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, double scale,
-                                                          int only_cols) {
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int only_cols) {
   __shared__ W red[kThreads / 64];
   const RedArgs ra = src.get(blockIdx.y);
+  const int nblk = ra.nblk;
   const int o = blockIdx.x;
   if (o >= ra.no || (only_cols == 0 && ra.no >= kColsMin)) return;
   const W* __restrict__ part = (const W*)ra.part;
@@ -747,7 +792,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, doubl
     W t = red[0];
 #pragma unroll
     for (int w = 1; w < kThreads / 64; ++w) t = e_add(t, red[w]);
-    ((W*)ra.out)[o] = e_scale(t, scale);
+    ((W*)ra.out)[o] = e_scale(t, ra.scale);
   }
 }
 
@@ -756,11 +801,11 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int nblk, doubl
 // cache line; thread (block group bg, output ol) adds blocks bg, bg + 16, ... in order and the
 // 16 group sums are added in order.
 template <typename W, typename S>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, double scale,
-                                                               int only_cols) {
+__global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int only_cols) {
   constexpr int NO = 16, NG = kThreads / NO;
   __shared__ W red[NG][NO];
   const RedArgs ra = src.get(blockIdx.y);
+  const int nblk = ra.nblk;
   if (only_cols == 1 && ra.no < kColsMin) return;
   const int ol = threadIdx.x % NO, bg = threadIdx.x / NO;
   const int o = blockIdx.x * NO + ol;
@@ -783,7 +828,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, 
   if (threadIdx.x < NO && o < ra.no) {
     W t = red[0][ol];
     for (int g2 = 1; g2 < NG; ++g2) t = e_add(t, red[g2][ol]);
-    ((W*)ra.out)[o] = e_scale(t, scale);
+    ((W*)ra.out)[o] = e_scale(t, ra.scale);
   }
 }
 
@@ -791,18 +836,18 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce_cols(S src, int nblk, 
 // size selects; a batch whose largest system is large runs both kernels, each skipping the
 // systems of the other size class.
 template <typename W, typename S>
-void reduce_launch(S sr, int nout, int nsys, int nblk, double scale, hipStream_t s) {
+void reduce_launch(S sr, int nout, int nsys, hipStream_t s) {
   if (nout < kColsMin) {
     dim3 rg(nout, nsys);
-    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, -1);
+    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, -1);
     return;
   }
   if (nsys > 1) {
     dim3 rg(kColsMin - 1, nsys);
-    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, 0);
+    k_gram_reduce<W, S><<<rg, kThreads, 0, s>>>(sr, 0);
   }
   dim3 rg((nout + 15) / 16, nsys);
-  k_gram_reduce_cols<W, S><<<rg, kThreads, 0, s>>>(sr, nblk, scale, nsys > 1 ? 1 : -1);
+  k_gram_reduce_cols<W, S><<<rg, kThreads, 0, s>>>(sr, nsys > 1 ? 1 : -1);
 }
 
 // Cholesky of -M (Hermitised), L^{-H} and E_x in one wavefront, FP64.  Lane i holds row i of
@@ -905,8 +950,10 @@ __global__ __launch_bounds__(64) void k_chol(S src) {
 // xi_k(r) = sum_{i<=k} W_i(r) (L^{-H})_{ik}; in place allowed (xi may alias W).  L^{-H} is
 // staged in LDS, rounded once to the storage precision.
 template <typename E, int NMAX, typename S>
-__global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
-  const MolArgs ma = src.get(blockIdx.y);
+__global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng_arg) {
+  const Placed<MolArgs> pc = src.place(ng_arg);
+  const MolArgs ma = pc.a;
+  const size_t ng = pc.ng;
   const E* w = (const E*)ma.w;  // xi may alias w
   E* xi = (E*)ma.xi;
   const int n = ma.n;
@@ -914,7 +961,7 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
   __shared__ E lh[NMAX * NMAX];
   // this thread's W values are requested before the staging of L^{-H}, so the two loads
   // overlap (points past the end read the last point and are not stored)
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t r = pc.blk * kThreads + threadIdx.x;
   const size_t rc = r < ng ? r : ng - 1;
   E wr[NMAX];
 #pragma unroll
@@ -938,20 +985,22 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng) {
 // its first wavefront (the same arithmetic as k_chol_lanes, so the same bits) while its W
 // values load; workgroup 0 writes M, E_x, L^{-H} and the status.
 template <typename E, typename S>
-__global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng) {
+__global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng_arg) {
   typedef typename Elem<E>::wide W;
-  const MolArgs ma = src.get(blockIdx.y);
+  const Placed<MolArgs> pc = src.place(ng_arg);
+  const MolArgs ma = pc.a;
+  const size_t ng = pc.ng;
   const E* w = (const E*)ma.w;  // xi may alias w
   E* xi = (E*)ma.xi;
   const int n = ma.n;
   __shared__ W lw[64];
   __shared__ E lh[64];
-  const size_t r = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  const size_t r = pc.blk * kThreads + threadIdx.x;
   const size_t rc = r < ng ? r : ng - 1;
   E wr[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + rc];
-  if (threadIdx.x < 64) chol_lanes_body<W>(ma, (const W*)ma.mred, lw, blockIdx.x == 0);
+  if (threadIdx.x < 64) chol_lanes_body<W>(ma, (const W*)ma.mred, lw, pc.blk == 0);
   __syncthreads();
   for (int t = threadIdx.x; t < n * n; t += kThreads) lh[(t / n) * 8 + t % n] = e_narrow<E>(lw[t]);
   __syncthreads();
@@ -1019,23 +1068,35 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
 
 // ta row tiles; tb column tiles (upper bounds over the systems of a launch); the B tiles of
 // a row tile are taken two at a time for single-precision storage
+// Launch extent of a pointwise step: bx blocks of 256 points along x (one system's blocks, or
+// the blocks of every system of a flat launch), sys systems along the last grid dimension
+// (1 for a flat launch), the point count passed to single-edge sources, and whether every
+// system's point count is a multiple of 4 (16-byte vector loads in the Gram kernels).
+struct Grid {
+  unsigned bx;
+  unsigned sys;
+  size_t ng;
+  bool vec;
+};
+inline Grid grid_one_edge(size_t ng, int nsys) {
+  return {(unsigned)((ng + kThreads - 1) / kThreads), (unsigned)nsys, ng, ng % 4 == 0};
+}
+
 template <typename E, typename S>
-void gram_impl(S src, int ta, int tb, int nsys, size_t ng, int nchunks, int skip8,
-               hipStream_t s) {
+void gram_impl(S src, int ta, int tb, Grid g, int skip8, hipStream_t s) {
   constexpr bool SMALL = sizeof(typename Elem<E>::real) == 4;
-  const bool vec = ng % 4 == 0;
   if (SMALL && tb >= 2) {
-    dim3 grid(nchunks, ta * ((tb + 1) / 2), nsys);
-    if (vec)
-      k_gram<E, S, 2, true><<<grid, kThreads, 0, s>>>(src, ng, skip8);
+    dim3 grid(g.bx, ta * ((tb + 1) / 2), g.sys);
+    if (g.vec)
+      k_gram<E, S, 2, true><<<grid, kThreads, 0, s>>>(src, g.ng, skip8);
     else
-      k_gram<E, S, 2, false><<<grid, kThreads, 0, s>>>(src, ng, skip8);
+      k_gram<E, S, 2, false><<<grid, kThreads, 0, s>>>(src, g.ng, skip8);
   } else {
-    dim3 grid(nchunks, ta * tb, nsys);
-    if (vec)
-      k_gram<E, S, 1, true><<<grid, kThreads, 0, s>>>(src, ng, skip8);
+    dim3 grid(g.bx, ta * tb, g.sys);
+    if (g.vec)
+      k_gram<E, S, 1, true><<<grid, kThreads, 0, s>>>(src, g.ng, skip8);
     else
-      k_gram<E, S, 1, false><<<grid, kThreads, 0, s>>>(src, ng, skip8);
+      k_gram<E, S, 1, false><<<grid, kThreads, 0, s>>>(src, g.ng, skip8);
   }
 }
 
@@ -1053,16 +1114,16 @@ void by_elem(int et, Args... args) {
 template <typename E>
 struct WaccRun {
   template <typename S>
-  static void run(S src, int nmax, int nsys, size_t ng, hipStream_t s) {
-    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+  static void run(S src, int nmax, Grid g, hipStream_t s) {
+    dim3 grid(g.bx, g.sys);
     if (nmax <= 8)
-      k_wacc<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc<E, 8, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if (nmax <= 16)
-      k_wacc<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc<E, 16, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if (nmax <= 32 || Elem<E>::cplx)
-      k_wacc<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc<E, 32, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if constexpr (!Elem<E>::cplx)
-      k_wacc<E, 64, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc<E, 64, S><<<grid, kThreads, 0, s>>>(src, g.ng);
   }
 };
 
@@ -1071,15 +1132,15 @@ struct WaccRun {
 template <typename E>
 struct WaccGramRun {
   template <typename S>
-  static void run(S src, int nmax, int nsys, size_t ng, bool* done, hipStream_t s) {
+  static void run(S src, int nmax, Grid g, bool* done, hipStream_t s) {
     *done = false;
     const int lim = sizeof(E) > 8 ? 8 : 16;
     if (kGramPoints != kThreads || nmax > lim) return;
-    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+    dim3 grid(g.bx, g.sys);
     if (nmax <= 8)
-      k_wacc_gram<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc_gram<E, 8, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if constexpr (sizeof(E) <= 8)
-      k_wacc_gram<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_wacc_gram<E, 16, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     *done = true;
   }
 };
@@ -1087,16 +1148,16 @@ struct WaccGramRun {
 template <typename E>
 struct TrsmRun {
   template <typename S>
-  static void run(S src, int nmax, int nsys, size_t ng, hipStream_t s) {
-    dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), nsys);
+  static void run(S src, int nmax, Grid g, hipStream_t s) {
+    dim3 grid(g.bx, g.sys);
     if (nmax <= 8)
-      k_trsm<E, 8, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_trsm<E, 8, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if (nmax <= 16)
-      k_trsm<E, 16, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_trsm<E, 16, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if (nmax <= 32 || Elem<E>::cplx)
-      k_trsm<E, 32, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_trsm<E, 32, S><<<grid, kThreads, 0, s>>>(src, g.ng);
     else if constexpr (!Elem<E>::cplx)
-      k_trsm<E, 64, S><<<grid, kThreads, 0, s>>>(src, ng);
+      k_trsm<E, 64, S><<<grid, kThreads, 0, s>>>(src, g.ng);
   }
 };
 
@@ -1104,35 +1165,33 @@ struct TrsmRun {
 // summation order, for M of a build; 8 is faster for xi^H psi)
 template <typename E>
 struct GramRun {
+  // nred: systems of the reduction (the grid's sys is 1 for a flat launch)
   template <typename SG, typename SR>
-  static void run(SG sg, SR sr, int namax, int nbmax, int nout, int nsys, size_t ng,
-                  double scale, int c8_waves, hipStream_t s) {
+  static void run(SG sg, SR sr, int namax, int nbmax, int nout, int nred, Grid g, int c8_waves,
+                  hipStream_t s) {
     typedef typename Elem<E>::wide W;
-    size_t chunk;
-    const int nch = gram_blocks(ng, &chunk);
     // complex systems with at most 8 A rows (every one, when namax <= 8) take the stacked
     // kernel; the others the general one
     if constexpr (Elem<E>::cplx) {
-      const bool vec = ng % 4 == 0;
       // four 8-column tiles per workgroup (measured best of 2/4 tiles and 4/8/16 wavefronts
       // at 48^3, 8 x 32: eight wavefronts of 32 points)
       const int groups = ((nbmax + 7) / 8 + 3) / 4;
-      dim3 grid(nch, groups, nsys);
+      dim3 grid(g.bx, groups, g.sys);
       if (c8_waves == 8) {
-        if (vec)
-          k_gram_c8<E, SG, 4, true, 8><<<grid, 512, 0, s>>>(sg, ng);
+        if (g.vec)
+          k_gram_c8<E, SG, 4, true, 8><<<grid, 512, 0, s>>>(sg, g.ng);
         else
-          k_gram_c8<E, SG, 4, false, 8><<<grid, 512, 0, s>>>(sg, ng);
+          k_gram_c8<E, SG, 4, false, 8><<<grid, 512, 0, s>>>(sg, g.ng);
       } else {
-        if (vec)
-          k_gram_c8<E, SG, 4, true, 4><<<grid, 256, 0, s>>>(sg, ng);
+        if (g.vec)
+          k_gram_c8<E, SG, 4, true, 4><<<grid, 256, 0, s>>>(sg, g.ng);
         else
-          k_gram_c8<E, SG, 4, false, 4><<<grid, 256, 0, s>>>(sg, ng);
+          k_gram_c8<E, SG, 4, false, 4><<<grid, 256, 0, s>>>(sg, g.ng);
       }
     }
     if (!Elem<E>::cplx || namax > 8)
-      gram_impl<E, SG>(sg, (namax + 15) / 16, (nbmax + 15) / 16, nsys, ng, nch, 1, s);
-    reduce_launch<W, SR>(sr, nout, nsys, nch, scale, s);
+      gram_impl<E, SG>(sg, (namax + 15) / 16, (nbmax + 15) / 16, g, 1, s);
+    reduce_launch<W, SR>(sr, nout, nred, s);
   }
 };
 
@@ -1172,7 +1231,7 @@ int gram_blocks(size_t ng, size_t* chunk) {
 }
 
 static MolArgs single(const void* phi, const void* v, void* w, void* xi, void* mred, void* linvh,
-                      void* m_out, double* ex_out, int* status, int n) {
+                      void* m_out, double* ex_out, int* status, int n, size_t ng) {
   MolArgs m{};
   m.phi = phi;
   m.v = v;
@@ -1184,40 +1243,45 @@ static MolArgs single(const void* phi, const void* v, void* w, void* xi, void* m
   m.ex_out = ex_out;
   m.status = status;
   m.n = n;
+  m.blk0 = 0;
+  m.ng = ng;
   return m;
+}
+
+static int gram_rows(size_t ng) {
+  size_t chunk;
+  return gram_blocks(ng, &chunk);
 }
 
 void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void* w, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_WACC);
-  OneMol src{single(phi, v, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, n)};
-  by_elem<WaccRun>(et, src, n, 1, ng, s);
+  OneMol src{single(phi, v, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, n, ng)};
+  by_elem<WaccRun>(et, src, n, grid_one_edge(ng, 1), s);
 }
 
 template <typename S>
-static void reduce_any(int et, S src, int nout, int nsys, int nblk, double scale, hipStream_t s) {
+static void reduce_any(int et, S src, int nout, int nsys, hipStream_t s) {
   if (et == ET_C128 || et == ET_C64)
-    reduce_launch<C2<double>, S>(src, nout, nsys, nblk, scale, s);
+    reduce_launch<C2<double>, S>(src, nout, nsys, s);
   else
-    reduce_launch<double, S>(src, nout, nsys, nblk, scale, s);
+    reduce_launch<double, S>(src, nout, nsys, s);
 }
 
 void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
                       void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
-  MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n);
+  MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n, ng);
   m.part = part;
   bool done = false;
   {
     TraceScope ts(tr, TR_WACC);
-    by_elem<WaccGramRun>(et, OneMol{m}, n, 1, ng, &done, s);
+    by_elem<WaccGramRun>(et, OneMol{m}, n, grid_one_edge(ng, 1), &done, s);
   }
   if (!done) {
     launch_wacc(et, phi, v, n, ng, w, s, tr);
     launch_gram(et, phi, n, w, n, ng, part, scale, mred, s, tr);
   } else {
     TraceScope ts(tr, TR_GRAM);
-    size_t chunk;
-    const int nch = gram_blocks(ng, &chunk);
-    reduce_any(et, OneRed{RedArgs{part, n * n, mred}}, n * n, 1, nch, scale, s);
+    reduce_any(et, OneRed{RedArgs{part, n * n, mred, gram_rows(ng), scale}}, n * n, 1, s);
   }
 }
 
@@ -1230,7 +1294,7 @@ void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_o
   }
   TraceScope ts(tr, TR_TRSM);
   OneMol src{single(nullptr, nullptr, const_cast<void*>(w), xi, const_cast<void*>(mred), linvh,
-                    m_out, ex_out, status, n)};
+                    m_out, ex_out, status, n, ng)};
   dim3 grid((unsigned)((ng + kThreads - 1) / kThreads), 1);
   switch (et) {
     case ET_C128: k_chol_trsm<C2<double>, OneMol><<<grid, kThreads, 0, s>>>(src, ng); break;
@@ -1243,65 +1307,66 @@ void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_o
 void launch_gram(int et, const void* A, int na, const void* B, int nb, size_t ng, void* part,
                  double scale, void* out, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_GRAM);
+  const int nch = gram_rows(ng);
   if ((et == ET_R32 || et == ET_R64) && na > 16 && nb > 16 && na <= kWideRows &&
       nb <= kWideRows) {
-    size_t chunk;
-    const int nch = gram_blocks(ng, &chunk);
     if (et == ET_R32)
       k_gram_wide<float><<<nch, kThreads, 0, s>>>((const float*)A, na, (const float*)B, nb, ng,
                                                   (double*)part);
     else
       k_gram_wide<double><<<nch, kThreads, 0, s>>>((const double*)A, na, (const double*)B, nb,
                                                    ng, (double*)part);
-    OneRed sr{RedArgs{part, na * nb, out}};
-    reduce_launch<double, OneRed>(sr, na * nb, 1, nch, scale, s);
+    OneRed sr{RedArgs{part, na * nb, out, nch, scale}};
+    reduce_launch<double, OneRed>(sr, na * nb, 1, s);
     return;
   }
   OneGram sg{GramArgs{A, na, B, nb, part}};
-  OneRed sr{RedArgs{part, na * nb, out}};
-  by_elem<GramRun>(et, sg, sr, na, nb, na * nb, 1, ng, scale, 8, s);
+  OneRed sr{RedArgs{part, na * nb, out, nch, scale}};
+  by_elem<GramRun>(et, sg, sr, na, nb, na * nb, 1, grid_one_edge(ng, 1), 8, s);
 }
 
 void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
                  int* status, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_CHOL);
   OneMol src{single(nullptr, nullptr, nullptr, nullptr, const_cast<void*>(mred), linvh, m_out,
-                    ex_out, status, n)};
+                    ex_out, status, n, 0)};
   chol_any(et, src, n, 1, s);
 }
 
 void launch_trsm(int et, const void* w, int n, size_t ng, const void* linvh, void* xi, hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_TRSM);
   OneMol src{single(nullptr, nullptr, const_cast<void*>(w), xi, nullptr, const_cast<void*>(linvh),
-                    nullptr, nullptr, nullptr, n)};
-  by_elem<TrsmRun>(et, src, n, 1, ng, s);
+                    nullptr, nullptr, nullptr, n, ng)};
+  by_elem<TrsmRun>(et, src, n, grid_one_edge(ng, 1), s);
 }
 
-void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nmax, size_t ng,
-                              double dv, hipStream_t s, Trace* tr) {
-  ManyMol mm{mols_dev};
+void launch_ace_steps_flat(int et, const MolArgs* mols_dev, const int* bsys_dev, int nmol,
+                           int nblk, int nmax, hipStream_t s, Trace* tr) {
+  // every system's point count is a multiple of 4 exactly when the caller says so through the
+  // sign of nblk (negative: some are not)
+  const bool vec = nblk > 0;
+  const Grid g{(unsigned)(vec ? nblk : -nblk), 1u, 0, vec};
+  FlatMol fm{mols_dev, bsys_dev};
   bool fused = false;
   {
     TraceScope ts(tr, TR_WACC);
-    by_elem<WaccGramRun>(et, mm, nmax, nmol, ng, &fused, s);
-    if (!fused) by_elem<WaccRun>(et, mm, nmax, nmol, ng, s);
+    by_elem<WaccGramRun>(et, fm, nmax, g, &fused, s);
+    if (!fused) by_elem<WaccRun>(et, fm, nmax, g, s);
   }
   {
     TraceScope ts(tr, TR_GRAM);
-    size_t chunk;
-    const int nch = gram_blocks(ng, &chunk);
     if (fused)
-      reduce_any(et, ManyRed{mols_dev}, nmax * nmax, nmol, nch, dv, s);
+      reduce_any(et, ManyRed{mols_dev}, nmax * nmax, nmol, s);
     else
-      by_elem<GramRun>(et, ManyGram{mols_dev}, ManyRed{mols_dev}, nmax, nmax, nmax * nmax, nmol,
-                       ng, dv, 4, s);
+      by_elem<GramRun>(et, FlatGram{mols_dev, bsys_dev}, ManyRed{mols_dev}, nmax, nmax,
+                       nmax * nmax, nmol, g, 4, s);
   }
   {
     TraceScope ts(tr, TR_CHOL);
-    chol_any(et, mm, nmax, nmol, s);
+    chol_any(et, ManyMol{mols_dev}, nmax, nmol, s);
   }
   TraceScope ts(tr, TR_TRSM);
-  by_elem<TrsmRun>(et, mm, nmax, nmol, ng, s);
+  by_elem<TrsmRun>(et, fm, nmax, g, s);
 }
 
 template <typename E, int VB>

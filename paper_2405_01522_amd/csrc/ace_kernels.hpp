@@ -23,6 +23,9 @@ struct MolArgs {
   double* ex_out;    // E_x for the caller, or null
   int* status;       // [2] device status word of this system
   int n;             // orbitals
+  int blk0;          // first 256-point block of this system in a launch over many systems
+  size_t ng;         // grid points of this system's box
+  double dv;         // volume element h^3 of this system's grid
 };
 
 // storage element types (same numbering as the public ace_dtype)
@@ -55,9 +58,11 @@ void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, i
 void launch_direct_acc(int et, const void* phi, int n, const void* v, int nv, size_t ng, void* out,
                        hipStream_t s, Trace* tr);
 
-// W accumulation, M Gram + reduction, Cholesky / E_x and xi for nmol systems of one box edge
-// (ng points) whose MolArgs are in device memory; nmax = largest orbital count among them.
-void launch_ace_steps_batched(int et, const MolArgs* mols_dev, int nmol, int nmax, size_t ng,
-                              double dv, hipStream_t s, Trace* tr);
+// W accumulation, M Gram + reduction, Cholesky / E_x and xi for nmol systems of any box edges
+// and spacings, one launch per step: their MolArgs (ng, blk0 and dv set) are in device memory,
+// bsys maps each of the nblk 256-point blocks of all systems to its system; nmax = largest
+// orbital count.
+void launch_ace_steps_flat(int et, const MolArgs* mols_dev, const int* bsys_dev, int nmol,
+                           int nblk, int nmax, hipStream_t s, Trace* tr);
 
 }  // namespace ace

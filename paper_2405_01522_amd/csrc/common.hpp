@@ -288,14 +288,45 @@ __host__ __device__ __forceinline__ void butterfly(C2<T>* x) {
   }
 }
 
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+// multiplicative inverse of a modulo m (gcd(a, m) = 1)
+constexpr int inv_mod(int a, int m) {
+  for (int u = 1; u < m; ++u)
+    if ((a * u) % m == 1) return u;
+  return 1;
+}
+
 // In-register DFT of length N, natural order in and out, unnormalised.
 // X_k = sum_n x_n exp(DIR 2 pi i n k / N).
+// N = R M with gcd(R, M) = 1 goes the prime-factor (Good-Thomas) way: input n = (M n1 + R n2)
+// mod N, output k = CRT(k mod R, k mod M), so W_N^{nk} = W_R^{n1 k1} W_M^{n2 k2} and no twiddle
+// is multiplied between the two factors (both maps are compile-time index permutations).
+// Otherwise decimation in time with twiddles W_N^{rk}.
 template <typename T, int N, int DIR>
 __host__ __device__ __forceinline__ void dft(C2<T>* x) {
   constexpr int R = pick_radix(N);
   constexpr int M = N / R;
   if constexpr (M == 1) {
     butterfly<T, R, DIR>(x);
+  } else if constexpr (gcd_c(R, M) == 1) {
+    constexpr int UR = inv_mod(M % R, R);  // k = (M UR k1 + R UM k2) mod N
+    constexpr int UM = inv_mod(R % M, M);
+    C2<T> y[M][R];
+#pragma unroll
+    for (int n2 = 0; n2 < M; ++n2)
+#pragma unroll
+      for (int n1 = 0; n1 < R; ++n1) y[n2][n1] = x[(M * n1 + R * n2) % N];
+#pragma unroll
+    for (int n2 = 0; n2 < M; ++n2) butterfly<T, R, DIR>(y[n2]);
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      C2<T> t[M];
+#pragma unroll
+      for (int n2 = 0; n2 < M; ++n2) t[n2] = y[n2][k1];
+      dft<T, M, DIR>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < M; ++k2) x[(M * UR * k1 + R * UM * k2) % N] = t[k2];
+    }
   } else {
     // decimation in time: y_r = DFT_M(x[r + R m]); X[k + M s] = sum_r W_R^{rs} W_N^{rk} y_r[k]
     C2<T> y[R][M];

@@ -77,4 +77,51 @@ void launch_pair_poisson_ptrs(int n, bool fp64, bool real_packed, const PairPtrs
                               void* work, const void* ghat, const void* tw, hipStream_t s,
                               Trace* tr);
 
+// ---------------------------------------------------------------------------------------
+// Persistent passes over many systems of any box edges (poisson_queue.hip).  A job is one
+// transform (one complex pair density or a couple of real ones); an item is one plane of a
+// job: an x-plane for the z passes, K consecutive qz planes for the XY pass.  Items are
+// listed largest box edge first and walked by a fixed grid of workgroups with a fixed stride.
+struct QJob {
+  PairPtrs p0, p1;   // the pair (complex) or one or two pairs (real-packed) of this transform
+  void* work;        // this transform's N*N*P complex work volume
+  const void* gpos;  // kernel spectrum in position order of this edge and spacing
+  const void* tw;    // table twiddles of this edge
+  int edge;          // box edge N
+  int np;            // pairs of the transform: 1, or 2 for a real-packed couple
+  int k;             // qz planes per XY item
+};
+struct QItem {
+  int job;
+  int idx;  // x-plane (z passes) or first qz plane (XY pass)
+};
+// Threads per workgroup of the three passes (z passes: 512 or 1024; XY: 1024).
+struct QShape {
+  int zf_nt, zi_nt;
+};
+// 1 if K qz planes per XY item are compiled for this edge and dtype (and fit in LDS).
+bool queue_xy_k_ok(int n, bool fp64, int k);
+// LDS bytes of one XY item of K planes / of one z-pass item at edge n.
+size_t queue_xy_lds(int n, bool fp64, int k);
+size_t queue_z_lds(int n, bool fp64);
+// The passes over every job, each one launch of as many workgroups as fit on the device at
+// once: z-forward and z-inverse over zitems (nz), XY over xyitems (nxy); lds_z / lds_xy: the
+// largest item's LDS bytes of the pass; nt: threads of a z pass (512 or 1024).  Return 0, or
+// -1 if the LDS does not fit.
+int launch_zfwd_queue(bool fp64, bool real_packed, const QJob* jobs, const QItem* zitems, int nz,
+                      size_t lds_z, int nt, hipStream_t s);
+int launch_xy_queue(bool fp64, const QJob* jobs, const QItem* xyitems, int nxy, size_t lds_xy,
+                    hipStream_t s);
+int launch_zinv_queue(bool fp64, bool real_packed, const QJob* jobs, const QItem* zitems, int nz,
+                      size_t lds_z, int nt, hipStream_t s);
+// XY pass of count consecutive transforms of one box edge n (their N*N*P work volumes back to
+// back from work) with the one-system kernel at nt threads (512 or 1024), one plane per
+// workgroup.  -1 if the edge is not compiled for the precision.
+int launch_xy_edge(int n, bool fp64, int nt, void* work, int count, const void* gpos,
+                   const void* tw, hipStream_t s);
+// The three in order, each timed by the tracer when it is on.
+int launch_pair_queue(bool fp64, bool real_packed, const QJob* jobs, const QItem* zitems, int nz,
+                      const QItem* xyitems, int nxy, size_t lds_z, size_t lds_xy, QShape sh,
+                      hipStream_t s, Trace* tr);
+
 }  // namespace ace
