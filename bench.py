@@ -26,12 +26,19 @@ if ROOT not in sys.path:
 
 METRIC = "pair Poisson solves/s and ACE K*psi/s, mixed vs FP64 GPU at 1e-6 Ha"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3          # published vector FP32 (two packed FMAs per lane per cycle)
+FP32_NONPACKED_TFLOPS = 78.6      # 256 CUs x 4 SIMDs x 16 lanes x 1 FMA x 2.4 GHz
 FP64_PEAK_TFLOPS = 78.6
-# HBM bytes per launch of k_xy<float, 48> (32 transforms) from rocprofv3 FETCH_SIZE /
+BF16_DENSE_PEAK_TFLOPS = 2500.0   # dense BF16 matrix cores
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HA_TO_EV = 27.211386
+# HBM bytes per launch of k_xy<float, 48, 1, 1024> (32 transforms) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE, each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00);
 # valid for the kernel and launch as they stand (profiles/k_xy_c2_hbm_traffic.md)
-XY48_F32_TRAFFIC_BYTES = 2.00 * 29439 * 1024 + 1.00 * 55296 * 1024
+XY48_F32_TRAFFIC_BYTES = 2.00 * 29446 * 1024 + 1.00 * 55296 * 1024
+# HBM bytes of one whole C2 FP32 step (ACE build + K psi of 32 vectors, nine kernels), from the
+# same counters and scaling (profiles/ace_c2_step_hbm_traffic.md)
+C2_F32_STEP_TRAFFIC_BYTES = 405.4e6
 
 
 def xy_pass_flops(n):
@@ -48,10 +55,11 @@ def xy_pass_bytes(n, elem):
 
 
 def pair_solve_model_bytes(n, s_work, s_orb):
-    """Minimum-pass HBM model of one pair solve: the three transform passes move 16 N^3 working
-    elements (z forward writes N^2 P, the xy pass reads and writes it, z inverse reads it) and
-    3 N^3 orbital / potential elements (two orbitals in, one potential out)."""
-    return 16.0 * n ** 3 * s_work + 3.0 * n ** 3 * s_orb
+    """Minimum-pass HBM model of one pair solve: the N*N*P = 2 N^3 intermediate is written by
+    the z-forward pass, read and written by the XY pass and read by the z-inverse pass, i.e.
+    8 N^3 working elements, plus 3 N^3 orbital / potential elements (two orbitals in, one
+    potential out)."""
+    return 8.0 * n ** 3 * s_work + 3.0 * n ** 3 * s_orb
 
 
 def measure_copy_gbs(reps=10):
@@ -199,10 +207,12 @@ def run_batched(mols, dtype, steps, warmup):
     graph_ms = e0.elapsed_time(e1) / steps
     del g
     tuning = b.tuning()
+    ex = [float(x["ex"].cpu()) for x in systems]
     b.close()
     npairs = sum(m.phi.shape[0] * (m.phi.shape[0] + 1) // 2 for m in mols)
     return dict(ms_per_build=graph_ms, eager_ms_per_build=eager_ms, pair_solves=npairs,
-                pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols), tuning=tuning)
+                pair_solves_per_s=npairs / (graph_ms * 1e-3), systems=len(mols), tuning=tuning,
+                ex=ex)
 
 
 def run_tda(mol, steps, warmup):
@@ -241,16 +251,43 @@ def run_tda(mol, steps, warmup):
     ms = e0.elapsed_time(e1) / steps
     del g
     ctx.close()
-    nov, noo = no * nv, no * (no + 1) // 2
+    nov, noo, nvv = no * nv, no * (no + 1) // 2, nv * (nv + 1) // 2
+    ng = mol.n ** 3
     t = (nov + 127) // 128
-    # contraction FLOPs as launched: upper 128-tiles of the symmetric ov block + the oo x vv block
-    flops = 2.0 * mol.n ** 3 * (t * (t + 1) // 2 * 128 * 128 + noo * nv * nv)
+    # entries of the two contractions: the method's (the upper triangle of the symmetric ov
+    # block, and oo pairs x vv pairs a <= b) and the launched 128 x 128 tiles
+    method_entries = nov * (nov + 1) // 2 + noo * nvv
+    launched_entries = (t * (t + 1) // 2 + ((noo + 127) // 128) * ((nvv + 127) // 128)) * 128 * 128
     gemm_ms = kt.get("tda_gemm", (float("nan"), 1))[0]
+    sec = gemm_ms * 1e-3
+    # each FP32 product is three BF16 products on the matrix cores (hi*hi + hi*lo + lo*hi)
+    method_mfma = 3 * 2.0 * ng * method_entries
+    launched_mfma = 3 * 2.0 * ng * launched_entries
     return dict(ms_per_block=ms, pair_solves=nov + noo,
                 pair_solves_per_s=(nov + noo) / (ms * 1e-3),
-                gemm_ms=gemm_ms, gemm_tflops=flops / (gemm_ms * 1e-3) / 1e12,
-                gemm_frac_fp32_mfma=flops / (gemm_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
-                kernel_ms={k: v[0] for k, v in kt.items()})
+                gemm_ms=gemm_ms,
+                gemm={"bound": "mfma", "dtype": "bf16x3 (FP32 operands split hi + lo)",
+                      "peak_tflops": BF16_DENSE_PEAK_TFLOPS,
+                      "method_fp32_gflop": 2.0 * ng * method_entries / 1e9,
+                      "method_bf16_tflops": method_mfma / sec / 1e12,
+                      "frac_method": method_mfma / sec / 1e12 / BF16_DENSE_PEAK_TFLOPS,
+                      "launched_bf16_tflops": launched_mfma / sec / 1e12,
+                      "frac_launched": launched_mfma / sec / 1e12 / BF16_DENSE_PEAK_TFLOPS},
+                kernel_ms={k: v[0] for k, v in kt.items()}, c_block=c.cpu().numpy())
+
+
+def _golden_json(name):
+    """Values the oracle wrote (tests/golden/, by scripts that call only the oracle)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def _golden_npy(name):
+    path = os.path.join(ROOT, "tests", "golden", name)
+    return np.load(path, allow_pickle=False) if os.path.exists(path) else None
 
 
 def _scf_start(s, k, seed):
@@ -444,8 +481,11 @@ def cpu_baseline(mol, budget_s=20.0):
             break
     n = mol.phi.shape[0]
     npairs = n * (n + 1) // 2
+    # the rate in the GPU's unit (unique pairs per build, build + apply time), and the oracle's
+    # own Poisson-solve rate (it solves all n^2 ordered pairs of a build)
     return dict(value=npairs * reps / (t_build + t_apply), reps=reps, ex=ex, kpsi=kp,
-                kpsi_per_s=mol.psi.shape[0] * reps / t_apply, seconds=t_build + t_apply)
+                kpsi_per_s=mol.psi.shape[0] * reps / t_apply, seconds=t_build + t_apply,
+                oracle_solves_per_s=n * n * reps / t_build)
 
 
 def main(argv=None):
@@ -500,7 +540,9 @@ def main(argv=None):
                    "grid": 48, "padded": 96, "orbitals": n, "pair_solves_per_step": npairs,
                    "vectors": nvec, "seed": 102},
         "kpsi_per_s": nvec / (mixed["apply_ms"] * 1e-3),
-        "fp64": {"pair_solves_per_s": npairs / (fp64["ms_per_step"] * 1e-3),
+        "fp64": {"path": "plain FP64 GPU path: the same kernels with FP64 storage and arithmetic, "
+                         "one launch sequence per build",
+                 "pair_solves_per_s": npairs / (fp64["ms_per_step"] * 1e-3),
                  "kpsi_per_s": nvec / (fp64["apply_ms"] * 1e-3),
                  "ms_per_step": fp64["ms_per_step"],
                  "eager_ms_per_step": fp64["eager_ms_per_step"]},
@@ -522,29 +564,42 @@ def main(argv=None):
         flops = xy_pass_flops(mol.n) * per_launch
         achieved = flops / (avg_ms * 1e-3) / 1e12
         tb = XY48_F32_TRAFFIC_BYTES
-        out["roofline"] = {"bound": "alu", "kernel": "k_xy<float,48>", "achieved": achieved,
+        out["roofline"] = {"bound": "alu", "kernel": "k_xy<float,48,1,1024>", "achieved": achieved,
                            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": tb,
                            "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
                            "traffic_gbs": tb / (avg_ms * 1e-3) / 1e9 if tb else None,
                            "transforms_per_launch": per_launch,
                            "avg_launch_ms": avg_ms,
+                           "flops_convention": "5 P log2 P per length-P transform + 2 per kernel multiply",
+                           "nonpacked_fp32_peak": FP32_NONPACKED_TFLOPS,
+                           "frac_nonpacked": achieved / FP32_NONPACKED_TFLOPS,
                            "hbm_model_gbs": xy_pass_bytes(mol.n, 8) * per_launch / (avg_ms * 1e-3) / 1e9}
         out["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in kt.items()}
-    # whole pair-solve path against the minimum-pass HBM model (context beside the kernel roofline)
+    # whole pair-solve path: HBM bytes of the step from the counters over the step time, and
+    # the minimum-pass model per pair solve (context beside the kernel roofline)
     copy_gbs = measure_copy_gbs()
+    step_gbs = C2_F32_STEP_TRAFFIC_BYTES / (mixed["ms_per_step"] * 1e-3) / 1e9
+    out["path_hbm"] = {"counter_bytes_per_step": C2_F32_STEP_TRAFFIC_BYTES,
+                       "counter_gbs": step_gbs, "frac_hbm_peak": step_gbs / HBM_PEAK_GBS,
+                       "frac_copy": step_gbs / copy_gbs, "copy_gbs": copy_gbs,
+                       "model": "8 N^3 s_w + 3 N^3 s_o bytes per pair solve (minimum passes)"}
     for key, sw, val in (("mixed", 8, out["value"]), ("fp64", 16, out["fp64"]["pair_solves_per_s"])):
         b = pair_solve_model_bytes(mol.n, sw, sw)
         gbs = b * val / 1e9
-        out.setdefault("path_roofline", {"model": "16 N^3 s_w + 3 N^3 s_o bytes per pair solve",
-                                         "copy_gbs": copy_gbs})[key] = {
-            "bytes_per_pair": b, "achieved_gbs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
-            "frac_copy": gbs / copy_gbs}
-        out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
+        out["path_hbm"][key + "_model"] = {"bytes_per_pair": b, "achieved_gbs": gbs,
+                                           "frac_hbm_peak": gbs / HBM_PEAK_GBS}
+    out["fp64"]["kernel_ms_per_step"] = {k: v[0] / a.steps for k, v in fp64["kernels"].items()}
 
     if not a.no_batched:
         c4 = synth.config4()
         bt = run_batched(c4, torch.complex64, min(a.steps, 10), 2)
+        ex_gpu = bt.pop("ex")
+        golden = _golden_json("c4_ace.json")
+        if golden is not None:
+            err = [abs(e - g["ex"]) for e, g in zip(ex_gpu, golden["systems"])]
+            bt["ex_error_ha_vs_oracle"] = {"max": max(err), "mean": sum(err) / len(err),
+                                           "systems_above_1e-6": sum(e > 1e-6 for e in err)}
         out["batched_uneven"] = {"workload": "64 systems, edges {32..64} step 8, h=0.25, 2-16 complex "
                                              "orbitals (seed 104), one graph-captured call",
                                  "dtype": "f32", **bt}
@@ -552,13 +607,26 @@ def main(argv=None):
         sub = [m for m in c4 if m.n <= 48]
         bt32 = run_batched(sub, torch.complex64, min(a.steps, 10), 2)
         bt64 = run_batched(sub, torch.complex128, min(a.steps, 10), 2)
+        bt32.pop("ex")
+        bt64.pop("ex")
         out["batched_uneven_edges_le_48"] = {
             "workload": "the %d systems of that batch with edge <= 48" % len(sub),
             "f32": bt32, "f64": bt64,
             "speedup_f32_vs_f64": bt32["pair_solves_per_s"] / bt64["pair_solves_per_s"]}
 
     if not a.no_tda:
-        td = run_tda(synth.config3(), min(a.steps, 10), 2)
+        c3 = synth.config3()
+        td = run_tda(c3, min(a.steps, 10), 2)
+        cblk = td.pop("c_block")
+        golden = _golden_json("c3_eigen.json")
+        gold_c = _golden_npy("c3_coupling_singlet.npy")
+        if golden is not None and gold_c is not None:
+            w = np.linalg.eigvalsh(np.diag(np.repeat(-c3.eps_occ, c3.phi_virt.shape[0])
+                                           + np.tile(c3.eps_virt, c3.phi.shape[0])) + cblk)
+            td["vs_oracle"] = {"c_max_rel_error": float(np.max(np.abs(cblk - gold_c)) /
+                                                       np.max(np.abs(gold_c))),
+                               "eigenvalue_max_error_ev":
+                                   float(np.max(np.abs(w - np.asarray(golden["eigenvalues_ha"])))) * HA_TO_EV}
         out["tda_block"] = {"workload": "64^3 box h=0.2 padded 128^3; 16 occupied + 32 virtual real "
                                         "orbitals (seed 103); 512 ov + 136 oo pair solves, 512x512 "
                                         "singlet coupling block; one graph-captured call",
@@ -573,7 +641,10 @@ def main(argv=None):
                                "cores": os.cpu_count(), "cpu_model": _cpu_model(), "kind": "oracle",
                                "sample": "%d full FP64 ACE builds + applies of the same workload "
                                          "(%.1f s)" % (cb["reps"], cb["seconds"]),
-                               "kpsi_per_s": cb["kpsi_per_s"]}
+                               "kpsi_per_s": cb["kpsi_per_s"],
+                               "oracle_own_solves_per_s": cb["oracle_solves_per_s"],
+                               "note": "value counts the 36 unique pairs of a build; the oracle "
+                                       "solves all 64 ordered pairs (oracle_own_solves_per_s)"}
         out["ex_error_ha"] = {"mixed": abs(mixed["ex"] - cb["ex"]), "fp64": abs(fp64["ex"] - cb["ex"])}
         ref = cb["kpsi"]
         scale = float(np.max(np.abs(ref)))

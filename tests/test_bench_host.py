@@ -20,12 +20,13 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-@pytest.mark.parametrize("n,s_w,s_o,mb", [(32, 8, 8, 5.0), (32, 16, 16, 10.0),
-                                         (48, 8, 8, 16.8), (48, 16, 16, 33.6)])
+@pytest.mark.parametrize("n,s_w,s_o,mb", [(32, 8, 8, 2.88), (32, 16, 16, 5.77),
+                                         (48, 8, 8, 9.73), (48, 16, 16, 19.46)])
 def test_pair_solve_model_bytes(n, s_w, s_o, mb):
-    # minimum-pass model: 16 N^3 working elements and 3 N^3 orbital / potential elements;
-    # C1 5.0 / 10.0 MB and C2 16.8 / 33.6 MB (FP32 / FP64 storage)
-    assert abs(bench.pair_solve_model_bytes(n, s_w, s_o) / 1e6 - mb) < 0.05
+    # minimum-pass model: the 2 N^3 intermediate written, read and written, read (8 N^3 working
+    # elements) and 3 N^3 orbital / potential elements; 32^3 2.88 / 5.77 MB and 48^3
+    # 9.73 / 19.46 MB (FP32 / FP64 storage)
+    assert abs(bench.pair_solve_model_bytes(n, s_w, s_o) / 1e6 - mb) < 0.01
 
 
 def test_xy_pass_work_at_48():
