@@ -46,7 +46,7 @@ typedef enum { ACE_C128 = 0, ACE_C64 = 1, ACE_R64 = 2, ACE_R32 = 3 } ace_dtype;
 enum {
   ACE_OK = 0,
   ACE_ERR_INVALID = -1,     /* null pointer, count < 1, bad index, bad flag */
-  ACE_ERR_UNSUPPORTED = -2, /* box edge not compiled, or FFT plane does not fit in LDS */
+  ACE_ERR_UNSUPPORTED = -2, /* box edge not compiled for the dtype */
   ACE_ERR_HIP = -3,         /* a HIP runtime call failed */
   ACE_ERR_OOM = -4,         /* device allocation failed */
   ACE_ERR_NOT_POSDEF = -5,  /* -M not positive definite (device status; info = pivot) */
@@ -73,7 +73,10 @@ int ace_ctx_destroy(ace_ctx* ctx);
 /* Change the stream later calls enqueue on (NULL = null stream). */
 int ace_ctx_set_stream(ace_ctx* ctx, void* hip_stream);
 
-/* 1 if a box edge n is compiled for the given dtype, else 0. */
+/* 1 if a box edge n is compiled for the given dtype, else 0.  Edges 8, 9, 10, 12, 15, 16, 20,
+ * 24, 32, 40, 48, 56 and 64 (padded edges with radices 2, 3, 5, 7) in every dtype; where the
+ * padded P x P plane of the XY pass does not fit in LDS (FP64 at 56 and 64) the pass keeps the
+ * N y-transformed rows and runs the x transforms over strips of columns. */
 int ace_size_supported(int n, int dtype);
 
 /*

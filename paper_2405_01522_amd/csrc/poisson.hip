@@ -50,6 +50,20 @@ __global__ __launch_bounds__(NT) void k_xy(C2<T>* __restrict__ work, const T* __
                      gpos + (size_t)qz0 * P * P, pl, tw, threadIdx.x, NT);
 }
 
+// XY pass with the rows-and-strips layout (planes larger than the LDS): workgroup (qz, p).
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_xy_strips(C2<T>* __restrict__ work,
+                                                  const T* __restrict__ gpos,
+                                                  const TwE<T>* __restrict__ twg) {
+  constexpr int P = 2 * N, SW = strip_width<T, N>();
+  C2<T>* pl = lds<T>();
+  const TwE<T>* tw = stage_twiddles<T, P>(pl, (size_t)N * (P + 1) + (size_t)P * (SW + 1), twg);
+  __syncthreads();
+  const int qz = blockIdx.x, p = blockIdx.y;
+  xy_strips<T, N, SW>(work + ((size_t)p * P + qz) * N * N, gpos + (size_t)qz * P * P, pl, tw,
+                      threadIdx.x, NT);
+}
+
 // Z-inverse pass of one launch sequence: workgroup (x, p).
 template <typename T, int N, bool RP, typename R>
 __global__ __launch_bounds__(zi_threads<N>()) void k_zinv(const C2<T>* __restrict__ work, R res,
@@ -136,7 +150,6 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
     allow_lds(k_zfwd<T, N, false, R>, lds_z);
     allow_lds(k_zinv<T, N, false, R>, lds_z);
   }
-  allow_lds(k_xy<T, N, 1, kXyThreads>, lds_xy);
   dim3 gz(N, items), gxy(P, items);
   {
     TraceScope ts(tr, TR_ZFWD);
@@ -147,7 +160,13 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
   }
   {
     TraceScope ts(tr, TR_XY);
-    k_xy<T, N, 1, kXyThreads><<<gxy, kXyThreads, lds_xy, s>>>(w, gh, t);
+    if constexpr (fits<T, N>()) {
+      allow_lds(k_xy<T, N, 1, kXyThreads>, lds_xy);
+      k_xy<T, N, 1, kXyThreads><<<gxy, kXyThreads, lds_xy, s>>>(w, gh, t);
+    } else {
+      allow_lds(k_xy_strips<T, N, 512>, strip_lds<T, N>());
+      k_xy_strips<T, N, 512><<<gxy, 512, strip_lds<T, N>(), s>>>(w, gh, t);
+    }
   }
   {
     TraceScope ts(tr, TR_ZINV);
@@ -163,7 +182,7 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
 bool poisson_size_supported(int n, bool fp64) {
 #define ACE_CASE(NN) \
   case NN:           \
-    return fp64 ? fits<double, NN>() : fits<float, NN>();
+    return fp64 ? supported<double, NN>() : supported<float, NN>();
   switch (n) {
     ACE_SIZES(ACE_CASE)
     default:
@@ -203,7 +222,7 @@ static void dispatch_poisson(int n, bool fp64, bool real_packed, R res, void* wo
                              const void* ghat, const void* tw, hipStream_t s, Trace* tr) {
 #define ACE_CASE(NN)                                                                 \
   case NN:                                                                           \
-    if constexpr (fits<double, NN>()) {                                              \
+    if constexpr (supported<double, NN>()) {                                              \
       if (fp64) {                                                                    \
         run_poisson<double, NN, R>(real_packed, res, work, ghat, tw, s, tr);         \
         return;                                                                      \
@@ -228,7 +247,10 @@ static void xy_edge(int nt, void* work, int count, const void* gpos, const void*
   C2<T>* w = reinterpret_cast<C2<T>*>(work);
   const T* g = reinterpret_cast<const T*>(gpos);
   const TwE<T>* t = reinterpret_cast<const TwE<T>*>(tw);
-  if (nt == 512) {
+  if constexpr (!fits<T, N>()) {
+    allow_lds(k_xy_strips<T, N, 512>, strip_lds<T, N>());
+    k_xy_strips<T, N, 512><<<grid, 512, strip_lds<T, N>(), s>>>(w, g, t);
+  } else if (nt == 512) {
     allow_lds(k_xy<T, N, 1, 512>, lds);
     k_xy<T, N, 1, 512><<<grid, 512, lds, s>>>(w, g, t);
   } else {
@@ -242,7 +264,7 @@ int launch_xy_edge(int n, bool fp64, int nt, void* work, int count, const void* 
   if (count <= 0) return 0;
 #define ACE_CASE(NN)                                                       \
   case NN:                                                                 \
-    if constexpr (fits<double, NN>()) {                                    \
+    if constexpr (supported<double, NN>()) {                                    \
       if (fp64) {                                                          \
         xy_edge<double, NN>(nt, work, count, gpos, tw, s);                 \
         return 0;                                                          \

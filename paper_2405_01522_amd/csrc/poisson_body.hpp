@@ -388,9 +388,138 @@ void allow_lds(K kernel, size_t bytes) {
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// the whole P x P plane of the XY pass fits in LDS
 template <typename T, int N>
 constexpr bool fits() {
   return lds_with_twiddles<T, 2 * N>((size_t)(2 * N) * (2 * N + 1)) <= kMaxLds;
+}
+
+// Otherwise (FP64 at edges 56 and 64) the XY pass keeps only the N y-transformed rows in LDS
+// and runs the x transforms over strips of SW columns: the widest divisor SW <= P/2 of P whose
+// strip fits beside the rows, or 0.
+template <typename T, int N>
+constexpr int strip_width() {
+  constexpr int P = 2 * N;
+  for (int sw = P / 2; sw >= 2; --sw)
+    if (P % sw == 0 &&
+        lds_with_twiddles<T, P>((size_t)N * (P + 1) + (size_t)P * (sw + 1)) <= kMaxLds)
+      return sw;
+  return 0;
+}
+template <typename T, int N>
+constexpr size_t strip_lds() {
+  constexpr int P = 2 * N;
+  return lds_with_twiddles<T, P>((size_t)N * (P + 1) + (size_t)P * (strip_width<T, N>() + 1));
+}
+
+// the pair-Poisson passes are compiled for this edge and precision
+template <typename T, int N>
+constexpr bool supported() {
+  return fits<T, N>() || strip_width<T, N>() > 0;
+}
+
+// XY pass of one qz plane with the rows-and-strips layout: rows x < N of the y transform in
+// LDS R[x][qy] (stride P + 1), then for each strip of SW columns the x transform forward, the
+// kernel multiply and the x transform inverse through a strip buffer S[qx][c] (stride SW + 1),
+// the N kept rows written back to R, then the y inverse.  Every item is computed as in
+// xy_planes, only the x transforms go strip by strip.  g: the plane's N x N slice, gz: its
+// kernel spectrum [qx][qy], pl: R followed by S, tw: table twiddles in LDS.
+template <typename T, int N, int SW>
+__device__ __forceinline__ void xy_strips(C2<T>* __restrict__ g, const T* __restrict__ gz,
+                                          C2<T>* __restrict__ pl, const TwE<T>* __restrict__ tw,
+                                          int tid, int nt) {
+  typedef Plan<N> PL;
+  constexpr int P = PL::P, P1 = PL::P1, P2 = PL::P2, H1 = PL::H1, RS = P + 1, SS = SW + 1;
+  static_assert(P % SW == 0, "whole strips");
+  C2<T>* R = pl;
+  C2<T>* S = pl + N * RS;
+  // 1. y forward, first factor (rows x < N, input y < N): global -> R
+  for (int it = tid; it < N * P2; it += nt) {
+    const int n2 = it % P2, x = it / P2;
+    C2<T> v[P1];
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) v[n1] = g[x * N + n1 * P2 + n2];
+    dft_in_half<T, P1, -1>(v);
+    R[x * RS + n2] = v[0];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) R[x * RS + k1 * P2 + n2] = tw_mul(v[k1], tw[n2 * k1]);
+  }
+  __syncthreads();
+  // 2. y forward, second factor
+  for (int it = tid; it < N * P1; it += nt) {
+    const int x = it % N, k1 = it / N;
+    C2<T> v[P2];
+    C2<T>* row = R + x * RS + k1 * P2;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = row[k2];
+    dft<T, P2, -1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) row[k2] = v[k2];
+  }
+  __syncthreads();
+  for (int q0 = 0; q0 < P; q0 += SW) {
+    // 3a. x forward, first factor, columns q0 .. q0 + SW - 1: R -> S
+    for (int it = tid; it < SW * P2; it += nt) {
+      const int c = it % SW, n2 = it / SW, qy = q0 + c;
+      C2<T> v[P1];
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) v[n1] = R[(n1 * P2 + n2) * RS + qy];
+      dft_in_half<T, P1, -1>(v);
+      S[n2 * SS + c] = v[0];
+#pragma unroll
+      for (int k1 = 1; k1 < P1; ++k1) S[(k1 * P2 + n2) * SS + c] = tw_mul(v[k1], tw[n2 * k1]);
+    }
+    __syncthreads();
+    // 3b. x forward second factor, kernel multiply, x inverse first factor
+    for (int it = tid; it < SW * P1; it += nt) {
+      const int c = it % SW, k1 = it / SW, qy = q0 + c;
+      C2<T> v[P2];
+#pragma unroll
+      for (int k2 = 0; k2 < P2; ++k2) v[k2] = S[(k1 * P2 + k2) * SS + c];
+      dft<T, P2, -1>(v);
+#pragma unroll
+      for (int k2 = 0; k2 < P2; ++k2) v[k2] = cscale(v[k2], gz[(k1 * P2 + k2) * P + qy]);
+      dft<T, P2, 1>(v);
+#pragma unroll
+      for (int k2 = 0; k2 < P2; ++k2) S[(k1 * P2 + k2) * SS + c] = v[k2];
+    }
+    __syncthreads();
+    // 3c. x inverse, second factor, rows x < N: S -> R
+    for (int it = tid; it < SW * P2; it += nt) {
+      const int c = it % SW, n2 = it / SW, qy = q0 + c;
+      C2<T> v[P1];
+      v[0] = S[n2 * SS + c];
+#pragma unroll
+      for (int k1 = 1; k1 < P1; ++k1) v[k1] = tw_mul_conj(S[(k1 * P2 + n2) * SS + c], tw[n2 * k1]);
+      dft_out_half<T, P1, 1>(v);
+#pragma unroll
+      for (int n1 = 0; n1 < H1; ++n1) R[(n1 * P2 + n2) * RS + qy] = v[n1];
+    }
+    __syncthreads();
+  }
+  // 4. y inverse, first factor (rows x < N)
+  for (int it = tid; it < N * P1; it += nt) {
+    const int x = it % N, k1 = it / N;
+    C2<T> v[P2];
+    C2<T>* row = R + x * RS + k1 * P2;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = row[k2];
+    dft<T, P2, 1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) row[k2] = v[k2];
+  }
+  __syncthreads();
+  // 5. y inverse, second factor, output y < N: R -> global (in place over the input slice)
+  for (int it = tid; it < N * P2; it += nt) {
+    const int n2 = it % P2, x = it / P2;
+    C2<T> v[P1];
+    v[0] = R[x * RS + n2];
+#pragma unroll
+    for (int k1 = 1; k1 < P1; ++k1) v[k1] = tw_mul_conj(R[x * RS + k1 * P2 + n2], tw[n2 * k1]);
+    dft_out_half<T, P1, 1>(v);
+#pragma unroll
+    for (int n1 = 0; n1 < H1; ++n1) g[x * N + n1 * P2 + n2] = v[n1];
+  }
 }
 
 #define ACE_SIZES(X) X(8) X(9) X(10) X(12) X(15) X(16) X(20) X(24) X(32) X(40) X(48) X(56) X(64)

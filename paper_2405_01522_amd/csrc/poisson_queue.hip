@@ -83,7 +83,7 @@ __device__ __forceinline__ void zfwd_item(const QJob* jb, int x, C2<T>* buf, int
   switch (jb->edge) {
 #define ACE_CASE(NN)                                                  \
   case NN:                                                            \
-    if constexpr (fits<T, NN>()) zfwd_item_n<T, NN, RP>(jb, x, buf, nt); \
+    if constexpr (supported<T, NN>()) zfwd_item_n<T, NN, RP>(jb, x, buf, nt); \
     break;
     ACE_SIZES(ACE_CASE)
 #undef ACE_CASE
@@ -95,11 +95,23 @@ __device__ __forceinline__ void zinv_item(const QJob* jb, int x, C2<T>* buf, int
   switch (jb->edge) {
 #define ACE_CASE(NN)                                                  \
   case NN:                                                            \
-    if constexpr (fits<T, NN>()) zinv_item_n<T, NN, RP>(jb, x, buf, nt); \
+    if constexpr (supported<T, NN>()) zinv_item_n<T, NN, RP>(jb, x, buf, nt); \
     break;
     ACE_SIZES(ACE_CASE)
 #undef ACE_CASE
   }
+}
+
+template <typename T, int N>
+__device__ __attribute__((noinline)) void xy_strip_item_n(const QJob* jb, int qz, C2<T>* pl,
+                                                          int nt) {
+  constexpr int P = 2 * N, SW = strip_width<T, N>();
+  const TwE<T>* tw = stage_twiddles<T, P>(pl, (size_t)N * (P + 1) + (size_t)P * (SW + 1),
+                                          reinterpret_cast<const TwE<T>*>(jb->tw));
+  __syncthreads();
+  xy_strips<T, N, SW>(reinterpret_cast<C2<T>*>(jb->work) + (size_t)qz * N * N,
+                      reinterpret_cast<const T*>(jb->gpos) + (size_t)qz * P * P, pl, tw,
+                      threadIdx.x, nt);
 }
 
 template <typename T>
@@ -108,6 +120,9 @@ __device__ __forceinline__ void xy_item(const QJob* jb, int qz0, C2<T>* pl, int 
   switch (jb->edge) {
 #define ACE_CASE(NN)                                                                       \
   case NN:                                                                                 \
+    if constexpr (!fits<T, NN>() && supported<T, NN>()) {                                  \
+      xy_strip_item_n<T, NN>(jb, qz0, pl, nt);                                            \
+    }                                                                                      \
     if constexpr (xy_k_fits<T, NN, 1>()) {                                                 \
       if (k == 1) xy_item_nk<T, NN, 1>(jb, qz0, pl, nt);                                  \
     }                                                                                      \
@@ -212,9 +227,9 @@ void launch_xy_pass(const QJob* jobs, const QItem* items, int n, size_t lds, hip
 template <typename T>
 bool k_ok(int n, int k) {
   switch (n) {
-#define ACE_CASE(NN)                                           \
-  case NN:                                                     \
-    return (k == 1 && xy_k_fits<T, NN, 1>()) ||                \
+#define ACE_CASE(NN)                                                           \
+  case NN:                                                                     \
+    return (k == 1 && (xy_k_fits<T, NN, 1>() || supported<T, NN>())) ||        \
            (k == 2 && xy_k_fits<T, NN, 2>()) || (k == 4 && xy_k_fits<T, NN, 4>());
     ACE_SIZES(ACE_CASE)
 #undef ACE_CASE
@@ -222,14 +237,24 @@ bool k_ok(int n, int k) {
   return false;
 }
 
+template <typename T>
+size_t xy_lds(int n, int k) {
+  switch (n) {
+#define ACE_CASE(NN)                                                                        \
+  case NN:                                                                                  \
+    return fits<T, NN>() ? lds_with_twiddles<T, 2 * NN>((size_t)k * 2 * NN * (2 * NN + 1)) \
+                         : strip_lds<T, NN>();
+    ACE_SIZES(ACE_CASE)
+#undef ACE_CASE
+  }
+  return 0;
+}
+
 }  // namespace
 
 bool queue_xy_k_ok(int n, bool fp64, int k) { return fp64 ? k_ok<double>(n, k) : k_ok<float>(n, k); }
 
-size_t queue_xy_lds(int n, bool fp64, int k) {
-  const size_t p = 2 * (size_t)n, e = fp64 ? 16 : 8;
-  return (k * p * (p + 1) * e + 15) / 16 * 16 + p * 16;
-}
+size_t queue_xy_lds(int n, bool fp64, int k) { return fp64 ? xy_lds<double>(n, k) : xy_lds<float>(n, k); }
 
 size_t queue_z_lds(int n, bool fp64) {
   const size_t p = 2 * (size_t)n, e = fp64 ? 16 : 8;

@@ -40,8 +40,8 @@ def test_size_table_and_messages():
     lib = _lib.lib()
     for n in (8, 9, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64):
         assert lib.ace_size_supported(n, 1) == 1          # FP32 complex
-    assert lib.ace_size_supported(48, 0) == 1             # FP64: P = 96 plane fits in LDS
-    assert lib.ace_size_supported(56, 0) == 0             # FP64: P = 112 plane does not
+    for n in (8, 9, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64):
+        assert lib.ace_size_supported(n, 0) == 1          # FP64 complex (56, 64: column strips)
     assert lib.ace_size_supported(11, 1) == 0             # radix 11 not compiled
     assert lib.ace_size_supported(16, 7) == 0             # bad dtype
     assert lib.ace_strerror(-5).decode() == "-M is not positive definite"

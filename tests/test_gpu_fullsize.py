@@ -59,6 +59,39 @@ def test_pair_poisson_fp32_large_edges(n):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [56, 64])
+def test_pair_poisson_fp64_strip_edges(n):
+    """FP64 at edges 56 and 64, whose P x P plane exceeds the LDS: the XY pass keeps the N
+    y-transformed rows and runs the x transforms over column strips."""
+    ace = _ace()
+    rng = np.random.default_rng(400 + n)
+    a = rng.normal(size=(2, n, n, n)) + 1j * rng.normal(size=(2, n, n, n))
+    ctx = ace.AceContext(n, 0.25, torch.complex128)
+    pairs = [[0, 1], [1, 1]]
+    v = ctx.pair_poisson_batched(_t(a, torch.complex128), _t(a, torch.complex128),
+                                 pairs).cpu().numpy()
+    for p, (j, i) in enumerate(pairs):
+        ref = poisson.fft(np.conj(a[j]) * a[i], 0.25)
+        assert _rel(v[p], ref) < 1e-12, (n, p, _rel(v[p], ref))
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [56, 64])
+def test_ace_build_fp64_strip_edges(n):
+    ace = _ace()
+    m = synth.small_complex(600 + n, n, 0.25, 3, nvec=2)
+    ctx = ace.AceContext(m.n, m.h, torch.complex128)
+    xi, mm, ex = ctx.ace_build(_t(m.phi, torch.complex128))
+    kpsi = ctx.ace_apply(xi, _t(m.psi, torch.complex128)).cpu().numpy()
+    assert ctx.status()[0] == 0
+    xi_o, m_o, _, ex_o = exchange.ace_build(m.phi, m.h)
+    assert abs(float(ex.cpu()) - ex_o) < 1e-10 * abs(ex_o)
+    assert _rel(mm.cpu().numpy(), m_o) < 1e-10
+    assert _rel(xi.cpu().numpy(), xi_o) < 1e-10
+    assert _rel(kpsi, exchange.ace_apply(xi_o, m.psi, m.h)) < 1e-10
+    ctx.close()
+
+
 @pytest.mark.parametrize("n", [40, 56])
 def test_ace_build_and_apply_fp32_large_edges(n):
     """ACE build + apply with FP32 storage at edges whose padded FFTs use radices 5 and 7."""
@@ -145,4 +178,20 @@ def test_config4_every_system_vs_oracle(c4_golden):
         _check_c4_system(g, sysd, 1e-6, 2e-5)
         edges.add(m.n)
     assert edges == set(synth.C4_EDGES)
+    b.close()
+
+
+def test_config4_every_system_fp64_vs_oracle(c4_golden):
+    """The same 64-system batch with FP64 storage (every edge, 56 and 64 through the column-strip
+    XY pass): every system's E_x, M and sampled xi within 1e-10 relative of the oracle."""
+    ace = _ace()
+    c4 = synth.config4()
+    dt = torch.complex128
+    systems = [{"h": m.h, "phi": _t(m.phi, dt)} for m in c4]
+    b = ace.AceBatch(dt)
+    b.build(systems)
+    st, mol, info = b.status()
+    assert st == 0, (st, mol, info)
+    for g, sysd in zip(c4_golden, systems):
+        _check_c4_system(g, sysd, 1e-10 * abs(g["ex"]), 1e-10)
     b.close()
