@@ -434,13 +434,29 @@ def run_scf(train_seeds=(1051, 1052, 1053, 1054, 1055), eval_seed=105, pairs=100
                scf=out, eig_only_converged_hamiltonian=eig_only, excited_states=pipe,
                energy_diff_learned_vs_kinetic=abs(out["learned"]["energy"] - out["kinetic"]["energy"]))
     if oracle_check:
+        # where the FP32 SCF's energy differs from the FP64 oracle's, term by term: the same
+        # (FP32) orbitals evaluated by the FP32 GPU path, by the GPU path in FP64 storage, by the
+        # oracle, and by the oracle after an FP64 Loewdin re-orthonormalisation
         from oracle import poisson, scf as oscf
-        p = finals["kinetic"].cpu().numpy().astype(np.float64)
+        phi32 = finals["kinetic"]
+        p = phi32.cpu().numpy().astype(np.float64)
+        khat = poisson.kernel_hat(s.n, s.h)
         t0 = time.perf_counter()
-        eo = oscf.energies(p, s.v_ext, s.h, poisson.kernel_hat(s.n, s.h))
-        res["oracle_energy_of_gpu_orbitals"] = dict(total=eo["total"],
-                                                    abs_diff=abs(eo["total"] - out["kinetic"]["energy"]),
-                                                    seconds=time.perf_counter() - t0)
+        eo = oscf.energies(p, s.v_ext, s.h, khat)
+        t_oracle = time.perf_counter() - t0
+        eo_orth = oscf.energies(oscf.loewdin(p, s.h), s.v_ext, s.h, khat)
+        e32 = ctx.scf_energies(tensor(s.v_ext[None]), phi32)
+        ctx64 = ace.AceContext(64, 0.2, torch.float64, dev)
+        e64 = ctx64.scf_energies(torch.from_numpy(np.ascontiguousarray(s.v_ext[None])).to(dev),
+                                 phi32.to(torch.float64).contiguous())
+        ctx64.close()
+        terms = ("kinetic", "external", "hartree", "exchange", "total")
+        res["oracle_energy_of_gpu_orbitals"] = dict(
+            total=eo["total"], abs_diff=abs(eo["total"] - out["kinetic"]["energy"]),
+            seconds=t_oracle,
+            gpu_fp32_minus_oracle={t: e32[t] - eo[t] for t in terms},
+            gpu_fp64_minus_oracle={t: e64[t] - eo[t] for t in terms},
+            orthonormalised_minus_oracle={t: eo_orth[t] - eo[t] for t in terms})
     net.close()
     ctx.close()
     return res

@@ -137,16 +137,15 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
       cosw[(size_t)k * ho + a] = w * cossin_2pi((long long)k * a, p).c;
     }
   const bool fp64 = is_fp64(dtype);
-  // table twiddles exp(-2 pi i m / P): FP64, or FP32 hi + lo parts (see TwE in common.hpp)
+  // table twiddles exp(-2 pi i m / P): FP64, or FP32 pairs of unit magnitude (unit_twiddle_f)
   std::vector<TwE<double>> tw64((size_t)p);
   std::vector<TwE<float>> tw32((size_t)p);
   for (int m = 0; m < p; ++m) {
     CosSin cs = cossin_2pi(m, p);
     tw64[m] = {cs.c, -cs.s};
-    const SplitF kc = split_f(cs.c), ks = split_f(-cs.s);
-    tw32[m] = {kc.hi, ks.hi, kc.lo, ks.lo};
+    tw32[m] = unit_twiddle_f(cs.c, -cs.s);
   }
-  static_assert(sizeof(TwE<double>) == 16 && sizeof(TwE<float>) == 16, "16-byte twiddles");
+  static_assert(sizeof(TwE<double>) == 16 && sizeof(TwE<float>) == 8, "twiddle sizes");
   double *d_cos = nullptr, *t0 = nullptr, *t1 = nullptr;
   int rc = ACE_OK;
   if (hipMalloc(&c->ghat64, oct * sizeof(double)) != hipSuccess ||
@@ -163,7 +162,8 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
   if (!rc) {
     if (hipMemcpy(d_cos, cosw.data(), cosw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->tw, fp64 ? (const void*)tw64.data() : (const void*)tw32.data(),
-                  16 * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
+                  (fp64 ? sizeof(TwE<double>) : sizeof(TwE<float>)) * (size_t)p,
+                  hipMemcpyHostToDevice) != hipSuccess ||
         hipMemsetAsync(c->status, 0, 4 * sizeof(int), c->stream) != hipSuccess)
       rc = ACE_ERR_HIP;
   }

@@ -109,10 +109,20 @@ inline constexpr TwTable<N> kTw{};
 // O(2^-24) matrix, and a pair energy <rho|G (*) rho> picks up a first-order bias that does not
 // average out over the grid (about 1e-7 relative in the exchange energy, measured by emulating
 // the passes in NumPy).  The rounding of the data in the arithmetic itself is unbiased and
-// costs about 100 times less.  So every constant of the FP32 transforms is carried as an
-// unevaluated sum hi + lo of two floats (hi = RNE(c), lo = RNE(c - hi)), and x * c is formed as
-// fma(x, hi, x * lo): one rounding of the product with the constant correct to about 2^-48.
-// ACE_FFT_SPLIT_CONSTANTS = 0 keeps the plain rounded constants (for measurement only).
+// costs about 100 times less.  Most of the bias comes from constants whose rounded magnitude
+// is off (|c + i s| != 1 scales every value through them the same way); a phase error leaves
+// the transform unitary and moves much less.  So:
+//  * the register-DFT constants (the cos / sin of radices 3, 5, 7 and the 45-degree factor of
+//    radix 8, few per point) are carried as an unevaluated sum hi + lo of two floats
+//    (hi = RNE(c), lo = RNE(c - hi)), and x * c is formed as fma(x, hi, x * lo): one rounding
+//    of the product with the constant correct to about 2^-48;
+//  * the inter-factor table twiddles (one complex product per point and factor) are plain
+//    float pairs chosen for unit magnitude: among the floats within 3 ulps of cos and sin, the
+//    pair with the smallest |c^2 + s^2 - 1| (then the smallest phase error).  This keeps the
+//    product at 4 instructions and, in the same NumPy emulation, removes about 90 % of the
+//    table twiddles' share of the bias.
+// ACE_FFT_SPLIT_CONSTANTS = 0 keeps the plain rounded register-DFT constants (for measurement
+// only).
 #ifndef ACE_FFT_SPLIT_CONSTANTS
 #define ACE_FFT_SPLIT_CONSTANTS 1
 #endif
@@ -193,8 +203,8 @@ struct alignas(16) TwE<double> {
   double c, s;
 };
 template <>
-struct alignas(16) TwE<float> {
-  float c, s, cl, sl;
+struct alignas(8) TwE<float> {
+  float c, s;
 };
 
 // a * w and a * conj(w) for a table twiddle w
@@ -205,14 +215,36 @@ __host__ __device__ __forceinline__ C2<double> tw_mul_conj(C2<double> a, TwE<dou
   return {a.r * w.c + a.i * w.s, a.i * w.c - a.r * w.s};
 }
 __host__ __device__ __forceinline__ C2<float> tw_mul(C2<float> a, TwE<float> w) {
-  const float cr = fmaf(a.r, w.cl, -a.i * w.sl);
-  const float ci = fmaf(a.r, w.sl, a.i * w.cl);
-  return {fmaf(a.r, w.c, fmaf(-a.i, w.s, cr)), fmaf(a.r, w.s, fmaf(a.i, w.c, ci))};
+  return {fmaf(a.r, w.c, -a.i * w.s), fmaf(a.r, w.s, a.i * w.c)};
 }
 __host__ __device__ __forceinline__ C2<float> tw_mul_conj(C2<float> a, TwE<float> w) {
-  const float cr = fmaf(a.r, w.cl, a.i * w.sl);
-  const float ci = fmaf(a.i, w.cl, -a.r * w.sl);
-  return {fmaf(a.r, w.c, fmaf(a.i, w.s, cr)), fmaf(a.i, w.c, fmaf(-a.r, w.s, ci))};
+  return {fmaf(a.r, w.c, a.i * w.s), fmaf(a.i, w.c, -a.r * w.s)};
+}
+
+// The FP32 table twiddle for cos + i sin (host side, when a context is created): the float
+// pair within 3 ulps of (RNE(cos), RNE(sin)) with the smallest |c^2 + s^2 - 1|, ties broken by
+// the smaller phase error.  Exact values (0, +-1) come back unchanged.
+inline TwE<float> unit_twiddle_f(double c, double s) {
+  auto step = [](float x, int d) {
+    for (int i = 0; i < (d < 0 ? -d : d); ++i)
+      x = __builtin_nextafterf(x, d > 0 ? __builtin_inff() : -__builtin_inff());
+    return x;
+  };
+  TwE<float> best = {float(c), float(s)};
+  double bmag = 2.0, bph = 2.0;
+  for (int dc = -3; dc <= 3; ++dc)
+    for (int ds = -3; ds <= 3; ++ds) {
+      const float fc = step(float(c), dc), fs = step(float(s), ds);
+      const double mag = __builtin_fabs((double)fc * fc + (double)fs * fs - 1.0);
+      // |sin| of the angle between (fc, fs) and (c, s): the phase error
+      const double ph = __builtin_fabs((double)fs * c - (double)fc * s);
+      if (mag < bmag || (mag == bmag && ph < bph)) {
+        bmag = mag;
+        bph = ph;
+        best = {fc, fs};
+      }
+    }
+  return best;
 }
 
 // W_N^{m} with sign DIR: exp(DIR * 2 pi i m / N); DIR = -1 forward, +1 inverse.

@@ -87,7 +87,7 @@ static void test_dft(std::mt19937_64& rng, double tol) {
   }
 }
 
-// Table twiddles exp(-2 pi i m / P) as the library builds them (FP32: hi + lo parts).
+// Table twiddles exp(-2 pi i m / P) as the library builds them (FP32: unit-magnitude pairs).
 template <typename T, int P>
 static std::vector<TwE<T>> twiddle_table() {
   std::vector<TwE<T>> tw(P);
@@ -96,8 +96,7 @@ static std::vector<TwE<T>> twiddle_table() {
     if constexpr (sizeof(T) == 8) {
       tw[m] = {cs.c, -cs.s};
     } else {
-      const SplitF kc = split_f(cs.c), ks = split_f(-cs.s);
-      tw[m] = {kc.hi, ks.hi, kc.lo, ks.lo};
+      tw[m] = unit_twiddle_f(cs.c, -cs.s);
     }
   }
   return tw;
