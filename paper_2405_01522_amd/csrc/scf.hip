@@ -18,15 +18,34 @@ constexpr int kT = 256;
 
 // Fourth-order central second difference on one axis: (-1/12, 4/3, -5/2, 4/3, -1/12) / h^2.
 // T = -1/2 Laplacian: centre 3 * 5/4 / h^2, first neighbours -2/3 / h^2, second 1/24 / h^2.
+// The weights sum to zero, and the operator is evaluated in that form,
+//   T x = c1 (n1 - 6 x) + c2 (n2 - 6 x)   (n1, n2: sums of the first / second neighbours),
+// so that rounding c1 and c2 only scales the two differences: with the weights rounded
+// separately (c0 x + c1 n1 + c2 n2) they no longer sum to zero in FP32: at h = 0.2 the
+// operator gains a constant 3.6e-6 Ha, and each doubly occupied orbital's kinetic energy
+// 7.2e-6 Ha.  FP32 also carries c1 and c2 as hi + lo pairs (the products rounded once).
+// c0 (the diagonal) is kept for the Jacobi preconditioner.
+template <typename T>
 struct Fd4 {
-  double c0, c1, c2;
+  T c0, c1, c2, c1l, c2l;
   explicit Fd4(double h) {
     const double ih2 = 1.0 / (h * h);
-    c0 = 3.75 * ih2;
-    c1 = -2.0 / 3.0 * ih2;
-    c2 = 1.0 / 24.0 * ih2;
+    const double d1 = -2.0 / 3.0 * ih2, d2 = 1.0 / 24.0 * ih2;
+    c0 = T(3.75 * ih2);
+    c1 = T(d1);
+    c2 = T(d2);
+    c1l = T(d1 - double(c1));
+    c2l = T(d2 - double(c2));
   }
 };
+
+// c1 * d1 + c2 * d2 with the constants' low parts
+__device__ __forceinline__ double fd4_comb(double d1, double d2, const Fd4<double>& f) {
+  return f.c1 * d1 + f.c2 * d2;
+}
+__device__ __forceinline__ float fd4_comb(float d1, float d2, const Fd4<float>& f) {
+  return fmaf(d1, f.c1, fmaf(d2, f.c2, fmaf(d1, f.c1l, d2 * f.c2l)));
+}
 
 // value of x at (coordinate + off) along an axis of stride `stride`, zero outside the box;
 // the load itself is always in bounds (clamped to the centre point)
@@ -40,15 +59,16 @@ __device__ __forceinline__ T nb(const T* __restrict__ xv, size_t r, int coord, i
 }
 
 template <typename T>
-__device__ __forceinline__ T kinetic_at(const T* __restrict__ xv, size_t r, int n, T c0, T c1,
-                                        T c2) {
+__device__ __forceinline__ T kinetic_at(const T* __restrict__ xv, size_t r, int n,
+                                        const Fd4<T>& f) {
   const int iz = (int)(r % n), iy = (int)((r / n) % n), ix = (int)(r / ((size_t)n * n));
   const long long sy = n, sx = (long long)n * n;
   const T n1 = nb(xv, r, iz, n, 1, -1) + nb(xv, r, iz, n, 1, 1) + nb(xv, r, iy, n, sy, -1) +
                nb(xv, r, iy, n, sy, 1) + nb(xv, r, ix, n, sx, -1) + nb(xv, r, ix, n, sx, 1);
   const T n2 = nb(xv, r, iz, n, 1, -2) + nb(xv, r, iz, n, 1, 2) + nb(xv, r, iy, n, sy, -2) +
                nb(xv, r, iy, n, sy, 2) + nb(xv, r, ix, n, sx, -2) + nb(xv, r, ix, n, sx, 2);
-  return c0 * xv[r] + c1 * n1 + c2 * n2;
+  const T x6 = T(6) * xv[r];
+  return fd4_comb(n1 - x6, n2 - x6, f);
 }
 
 // FP32, n a multiple of 4: the kinetic operator at the 4 consecutive z-points from r0 (a
@@ -62,7 +82,7 @@ __device__ __forceinline__ float f4(const float4& v, int i) {
   return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 __device__ __forceinline__ void kinetic_at4(const float* __restrict__ xv, size_t r0, int n,
-                                            float c0, float c1, float c2, float out[4]) {
+                                            const Fd4<float>& f, float out[4]) {
   const int iz = (int)(r0 % n), iy = (int)((r0 / n) % n), ix = (int)(r0 / ((size_t)n * n));
   const size_t sy = n, sx = (size_t)n * n;
   const float4 zl = ld4z(xv + r0 - (iz >= 4 ? 4 : 0), iz >= 4);
@@ -87,12 +107,13 @@ __device__ __forceinline__ void kinetic_at4(const float* __restrict__ xv, size_t
   for (int p = 0; p < 4; ++p) {
     const float n1 = w[p + 3] + w[p + 5] + f4(ym1, p) + f4(yp1, p) + f4(xm1, p) + f4(xp1, p);
     const float n2 = w[p + 2] + w[p + 6] + f4(ym2, p) + f4(yp2, p) + f4(xm2, p) + f4(xp2, p);
-    out[p] = c0 * w[p + 4] + c1 * n1 + c2 * n2;
+    const float x6 = 6.f * w[p + 4];
+    out[p] = fd4_comb(n1 - x6, n2 - x6, f);
   }
 }
 
 __global__ __launch_bounds__(kT) void k_fock_local4(const float* __restrict__ x, int n, size_t ng,
-                                                    float c0, float c1, float c2,
+                                                    Fd4<float> f,
                                                     const float* __restrict__ vloc, int acc,
                                                     float* __restrict__ y) {
   const size_t r0 = 4 * ((size_t)blockIdx.x * kT + threadIdx.x);
@@ -100,7 +121,7 @@ __global__ __launch_bounds__(kT) void k_fock_local4(const float* __restrict__ x,
   const size_t off = (size_t)blockIdx.y * ng;
   const float* xv = x + off;
   float s[4];
-  kinetic_at4(xv, r0, n, c0, c1, c2, s);
+  kinetic_at4(xv, r0, n, f, s);
   if (vloc) {
     const float4 v = *reinterpret_cast<const float4*>(vloc + r0);
     const float4 xc = *reinterpret_cast<const float4*>(xv + r0);
@@ -122,12 +143,12 @@ __global__ __launch_bounds__(kT) void k_fock_local4(const float* __restrict__ x,
 __global__ __launch_bounds__(kT) void k_jacobi_sweep4(const float* __restrict__ rr,
                                                       const float* __restrict__ zin,
                                                       float* __restrict__ zout, int n, size_t ng,
-                                                      float c0, float c1, float c2, float shift,
+                                                      Fd4<float> f, float shift,
                                                       float omega, int first) {
   const size_t r0 = 4 * ((size_t)blockIdx.x * kT + threadIdx.x);
   if (r0 >= ng) return;
   const size_t off = (size_t)blockIdx.y * ng;
-  const float inv = 1.f / (c0 + shift);
+  const float inv = 1.f / (f.c0 + shift);
   const float4 rv = *reinterpret_cast<const float4*>(rr + off + r0);
   if (first) {
     *reinterpret_cast<float4*>(zout + off + r0) =
@@ -136,7 +157,7 @@ __global__ __launch_bounds__(kT) void k_jacobi_sweep4(const float* __restrict__ 
   }
   const float* zv = zin + off;
   float k[4];
-  kinetic_at4(zv, r0, n, c0, c1, c2, k);
+  kinetic_at4(zv, r0, n, f, k);
   const float4 zc = *reinterpret_cast<const float4*>(zv + r0);
   float o[4];
 #pragma unroll
@@ -149,13 +170,13 @@ __global__ __launch_bounds__(kT) void k_jacobi_sweep4(const float* __restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(kT) void k_fock_local(const T* __restrict__ x, int n, size_t ng,
-                                                   T c0, T c1, T c2, const T* __restrict__ vloc,
+                                                   Fd4<T> f, const T* __restrict__ vloc,
                                                    int acc, T* __restrict__ y) {
   const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
   if (r >= ng) return;
   const size_t off = (size_t)blockIdx.y * ng;
   const T* xv = x + off;
-  T s = kinetic_at(xv, r, n, c0, c1, c2);
+  T s = kinetic_at(xv, r, n, f);
   if (vloc) s += vloc[r] * xv[r];
   if (acc) s += y[off + r];
   y[off + r] = s;
@@ -164,18 +185,18 @@ __global__ __launch_bounds__(kT) void k_fock_local(const T* __restrict__ x, int 
 // one damped-Jacobi step for (T + shift) z = r; first: z = r / (d + shift)
 template <typename T>
 __global__ __launch_bounds__(kT) void k_jacobi_sweep(const T* __restrict__ rr, const T* __restrict__ zin,
-                                                     T* __restrict__ zout, int n, size_t ng, T c0,
-                                                     T c1, T c2, T shift, T omega, int first) {
+                                                     T* __restrict__ zout, int n, size_t ng,
+                                                     Fd4<T> f, T shift, T omega, int first) {
   const size_t r = (size_t)blockIdx.x * kT + threadIdx.x;
   if (r >= ng) return;
   const size_t off = (size_t)blockIdx.y * ng;
-  const T inv = T(1) / (c0 + shift);
+  const T inv = T(1) / (f.c0 + shift);
   if (first) {
     zout[off + r] = rr[off + r] * inv;
     return;
   }
   const T* zv = zin + off;
-  const T az = kinetic_at(zv, r, n, c0, c1, c2) + shift * zv[r];
+  const T az = kinetic_at(zv, r, n, f) + shift * zv[r];
   zout[off + r] = zv[r] + omega * (rr[off + r] - az) * inv;
 }
 
@@ -438,25 +459,26 @@ bool aligned16(std::initializer_list<const void*> ps) {
 void launch_fock_local(bool fp64, const void* x, int nv, int n, double h, const void* vloc,
                        int acc, void* y, hipStream_t s) {
   const size_t ng = (size_t)n * n * n;
-  const Fd4 f(h);
+  const Fd4<double> fd(h);
+  const Fd4<float> ff(h);
   dim3 grid(grid_blocks(ng), nv);
   const bool v4 = !fp64 && n % 4 == 0 && aligned16({x, vloc, y});
   if (fp64)
-    k_fock_local<double><<<grid, kT, 0, s>>>((const double*)x, n, ng, f.c0, f.c1, f.c2,
-                                             (const double*)vloc, acc, (double*)y);
+    k_fock_local<double><<<grid, kT, 0, s>>>((const double*)x, n, ng, fd, (const double*)vloc,
+                                             acc, (double*)y);
   else if (v4)
-    k_fock_local4<<<dim3(grid_blocks(ng / 4), nv), kT, 0, s>>>(
-        (const float*)x, n, ng, (float)f.c0, (float)f.c1, (float)f.c2, (const float*)vloc, acc,
-        (float*)y);
+    k_fock_local4<<<dim3(grid_blocks(ng / 4), nv), kT, 0, s>>>((const float*)x, n, ng, ff,
+                                                               (const float*)vloc, acc, (float*)y);
   else
-    k_fock_local<float><<<grid, kT, 0, s>>>((const float*)x, n, ng, (float)f.c0, (float)f.c1,
-                                            (float)f.c2, (const float*)vloc, acc, (float*)y);
+    k_fock_local<float><<<grid, kT, 0, s>>>((const float*)x, n, ng, ff, (const float*)vloc, acc,
+                                            (float*)y);
 }
 
 void launch_precond_kinetic(bool fp64, const void* r, int nv, int n, double h, double shift,
                             int sweeps, double omega, void* z, void* tmp, hipStream_t s) {
   const size_t ng = (size_t)n * n * n;
-  const Fd4 f(h);
+  const Fd4<double> fd(h);
+  const Fd4<float> ff(h);
   dim3 grid(grid_blocks(ng), nv);
   const bool v4 = !fp64 && n % 4 == 0 && aligned16({r, z, tmp});
   // the last sweep must land in z: start in z if the number of later sweeps is even
@@ -468,15 +490,14 @@ void launch_precond_kinetic(bool fp64, const void* r, int nv, int n, double h, d
     if (t > 0) cur ^= 1;
     if (fp64)
       k_jacobi_sweep<double><<<grid, kT, 0, s>>>((const double*)r, (const double*)zin,
-                                                 (double*)zout, n, ng, f.c0, f.c1, f.c2, shift,
-                                                 omega, t == 0);
+                                                 (double*)zout, n, ng, fd, shift, omega, t == 0);
     else if (v4)
       k_jacobi_sweep4<<<dim3(grid_blocks(ng / 4), nv), kT, 0, s>>>(
-          (const float*)r, (const float*)zin, (float*)zout, n, ng, (float)f.c0, (float)f.c1,
-          (float)f.c2, (float)shift, (float)omega, t == 0);
+          (const float*)r, (const float*)zin, (float*)zout, n, ng, ff, (float)shift,
+          (float)omega, t == 0);
     else
       k_jacobi_sweep<float><<<grid, kT, 0, s>>>((const float*)r, (const float*)zin, (float*)zout,
-                                                n, ng, (float)f.c0, (float)f.c1, (float)f.c2,
+                                                n, ng, ff,
                                                 (float)shift, (float)omega, t == 0);
   }
 }
