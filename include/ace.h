@@ -92,6 +92,17 @@ int pair_poisson_batched(ace_ctx* ctx, const void* phi_a, int na, const void* ph
                          const int32_t* pairs, int np, void* v_out);
 
 /*
+ * pair_poisson_batched with the pair list in device memory (int32 [np][2], (j, i) as above),
+ * for a caller that builds or keeps its list on the GPU.  Nothing is copied or read on the
+ * host, so the call can be captured into a HIP graph.  The host cannot check the indices:
+ * the kernels clamp each to [0, na) / [0, nb), so no access leaves phi_a or phi_b, and record
+ * the first index out of range in the device status word (ace_ctx_status then returns
+ * ACE_ERR_INVALID with info = the offending pair); the outputs of such pairs are undefined.
+ */
+int pair_poisson_batched_dev(ace_ctx* ctx, const void* phi_a, int na, const void* phi_b, int nb,
+                             const int32_t* pairs_dev, int np, void* v_out);
+
+/*
  * Build the ACE operator from n orbitals phi (Sec. 3.1, Eqs. (11)-(12)):
  *   W_i  = -sum_j phi_j v_ji,  v_ji = dV G (*) (conj(phi_j) phi_i)      (Eq. (11), Eq. (2))
  *   M    = dV Phi^H W  (Hermitised),  -M = L L^H  (L lower, positive diagonal)
@@ -303,7 +314,8 @@ int sym_eig_small(int n, const double* A, int lda, double* w, double* V, int ldv
 /*
  * Synchronise the context stream and report the device status word: *status (host) receives
  * ACE_OK or the first device-side error recorded since the last call, *info (host, may be
- * NULL) the failing pivot for ACE_ERR_NOT_POSDEF.  The word is then cleared.
+ * NULL) the failing pivot for ACE_ERR_NOT_POSDEF, the pair for ACE_ERR_INVALID (an index out
+ * of range in a device pair list).  The word is then cleared.
  */
 int ace_ctx_status(ace_ctx* ctx, int* status, int* info);
 

@@ -27,6 +27,7 @@ SIGNATURES = {
     "ace_ctx_set_stream": (_I, [_P, _P]),
     "ace_size_supported": (_I, [_I, _I]),
     "pair_poisson_batched": (_I, [_P, _P, _I, _P, _I, ctypes.POINTER(ctypes.c_int32), _I, _P]),
+    "pair_poisson_batched_dev": (_I, [_P, _P, _I, _P, _I, _P, _I, _P]),
     "ace_build": (_I, [_P, _P, _I, _P, _P, _P]),
     "ace_apply": (_I, [_P, _P, _I, _P, _I, _P]),
     "ace_apply_noalloc": (_I, [_P, _P, _I, _P, _I, _P]),

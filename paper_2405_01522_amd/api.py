@@ -119,6 +119,11 @@ class AceContext:
 
     # -- entry points ---------------------------------------------------------------------
     def pair_poisson_batched(self, phi_a, phi_b, pairs, out=None):
+        """v[p] = G (*) (conj(phi_a[j]) phi_b[i]) for the pairs (j, i).  A pair list already on
+        the context's device (int32, contiguous, shape (np, 2)) goes to
+        pair_poisson_batched_dev and is not copied to the host."""
+        if isinstance(pairs, torch.Tensor) and pairs.is_cuda:
+            return self.pair_poisson_batched_dev(phi_a, phi_b, pairs, out)
         pr = torch.as_tensor(pairs, dtype=torch.int32).reshape(-1, 2).contiguous().cpu()
         np_ = pr.shape[0]
         if out is None:
@@ -130,6 +135,23 @@ class AceContext:
         ptr = ctypes.cast(pr.data_ptr(), ctypes.POINTER(ctypes.c_int32))
         check(lib().pair_poisson_batched(self._h, pa, phi_a.shape[0], pb, phi_b.shape[0], ptr,
                                          np_, po), "pair_poisson_batched")
+        return out
+
+    def pair_poisson_batched_dev(self, phi_a, phi_b, pairs, out=None):
+        if not isinstance(pairs, torch.Tensor) or pairs.dtype != torch.int32 or \
+                pairs.device != self.device or pairs.dim() != 2 or pairs.shape[1] != 2 or \
+                not pairs.is_contiguous():
+            raise ValueError("pairs must be a contiguous int32 (np, 2) tensor on %s" % self.device)
+        np_ = pairs.shape[0]
+        if out is None:
+            out = self._empty(np_)
+        pa = self._vol(phi_a, "phi_a")
+        pb = self._vol(phi_b, "phi_b")
+        po = self._vol(out, "v_out", np_)
+        self._sync_stream()
+        check(lib().pair_poisson_batched_dev(self._h, pa, phi_a.shape[0], pb, phi_b.shape[0],
+                                             ctypes.c_void_p(pairs.data_ptr()), np_, po),
+              "pair_poisson_batched_dev")
         return out
 
     def ace_build(self, phi, xi_out=None, m_out=None, ex_out=None):
@@ -697,6 +719,10 @@ def ace_ctx_create(n, h, dtype, device=None):
 
 def pair_poisson_batched(ctx, phi_a, phi_b, pairs, out=None):
     return ctx.pair_poisson_batched(phi_a, phi_b, pairs, out)
+
+
+def pair_poisson_batched_dev(ctx, phi_a, phi_b, pairs, out=None):
+    return ctx.pair_poisson_batched_dev(phi_a, phi_b, pairs, out)
 
 
 def ace_build(ctx, phi, xi_out=None, m_out=None, ex_out=None):

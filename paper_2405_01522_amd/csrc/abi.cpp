@@ -220,7 +220,14 @@ int pair_poisson_batched(ace_ctx* c, const void* phi_a, int na, const void* phi_
       return ACE_ERR_INVALID;
   int rc = upload_pairs(c, pairs, np);
   if (rc) return rc;
-  return run_pairs(c, phi_a, phi_b, (const int*)c->pairs.p, np, v_out);
+  return run_pairs(c, phi_a, na, phi_b, nb, (const int*)c->pairs.p, np, v_out);
+}
+
+int pair_poisson_batched_dev(ace_ctx* c, const void* phi_a, int na, const void* phi_b, int nb,
+                             const int32_t* pairs_dev, int np, void* v_out) {
+  if (!c || !phi_a || !phi_b || !pairs_dev || !v_out || na < 1 || nb < 1 || np < 1)
+    return ACE_ERR_INVALID;
+  return run_pairs(c, phi_a, na, phi_b, nb, (const int*)pairs_dev, np, v_out);
 }
 
 int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, double* ex_out) {
@@ -264,7 +271,7 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   if (!rc) rc = ensure(c, c->small, wide * 2 * (size_t)n * n);
   if (rc) return rc;
   rc = cplx ? run_slots(c, phi, (const int*)c->pairs.p, nitems, c->vbuf.p)
-            : run_pairs(c, phi, phi, (const int*)c->pairs.p, np, c->vbuf.p);
+            : run_pairs(c, phi, n, phi, n, (const int*)c->pairs.p, np, c->vbuf.p);
   if (rc) return rc;
   char* mred = (char*)c->small.p;
   char* linvh = mred + wide * (size_t)n * n;
@@ -371,7 +378,7 @@ int exchange_apply_direct(ace_ctx* c, const void* phi, int n, const void* psi, i
     rc = upload_pairs(c, pl.data(), n * cv);
     if (rc) return rc;
     const char* ps = (const char*)psi + eb * ng * (size_t)v0;
-    rc = run_pairs(c, phi, ps, (const int*)c->pairs.p, n * cv, c->vbuf.p);
+    rc = run_pairs(c, phi, n, ps, cv, (const int*)c->pairs.p, n * cv, c->vbuf.p);
     if (rc) return rc;
     launch_direct_acc(c->dtype, phi, n, c->vbuf.p, cv, ng, (char*)out + eb * ng * (size_t)v0,
                       c->stream, c->tr());

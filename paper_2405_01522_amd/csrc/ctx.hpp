@@ -226,9 +226,10 @@ inline int upload_pairs(ace_ctx* c, const int* host, int count) {
   return ACE_OK;
 }
 
-// Pair solves in batches bounded by the FFT workspace; pairs already on the device.
-inline int run_pairs(ace_ctx* c, const void* pa, const void* pb, const int* pairs_dev, int np,
-              void* vout) {
+// Pair solves in batches bounded by the FFT workspace; pairs already on the device, indices
+// into na orbitals of pa and nb of pb.
+inline int run_pairs(ace_ctx* c, const void* pa, int na, const void* pb, int nb,
+                     const int* pairs_dev, int np, void* vout) {
   const bool fp64 = is_fp64(c->dtype), rp = !is_cplx(c->dtype);
   const size_t per_item = poisson_work_bytes_per_item(c->n, fp64);
   const int items = rp ? (np + 1) / 2 : np;
@@ -242,8 +243,9 @@ inline int run_pairs(ace_ctx* c, const void* pa, const void* pb, const int* pair
     const int ni = std::min(batch, items - i0);
     const int p0 = rp ? 2 * i0 : i0;
     const int npb = rp ? std::min(2 * ni, np - p0) : ni;
-    launch_pair_poisson(c->n, fp64, rp, pa, pb, pairs_dev + 2 * p0, npb, c->work.p,
-                        (char*)vout + eb * c->ng * (size_t)p0, gh, c->tw, c->stream, c->tr());
+    launch_pair_poisson(c->n, fp64, rp, pa, na, pb, nb, pairs_dev + 2 * p0, npb, c->work.p,
+                        (char*)vout + eb * c->ng * (size_t)p0, gh, c->tw, c->status, c->stream,
+                        c->tr());
   }
   return hip_check(hipGetLastError());
 }

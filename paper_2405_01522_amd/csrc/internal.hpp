@@ -46,11 +46,12 @@ void launch_kernel_positions(int n, bool fp64, const double* oct, void* gpos, hi
 // pairs[2p+1]) and v[p] = G (*) (conj(a_j) b_i).  Real-packed mode: item p covers pairs 2p
 // and 2p+1 of the list (np pairs in total) and v is real, one volume per pair.
 // phi_*: orbital arrays; work: nitems * work_bytes_per_item; v_out: output volumes;
-// ghat: the position-ordered kernel spectrum of launch_kernel_positions.
-void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
-                         const void* phi_b, const int* pairs_dev, int np, void* work,
-                         void* v_out, const void* ghat, const void* tw, hipStream_t s,
-                         Trace* tr);
+// ghat: the position-ordered kernel spectrum of launch_kernel_positions.  Indices are clamped
+// to [0, na) / [0, nb) and an index out of range is recorded in status (may be NULL).
+void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a, int na,
+                         const void* phi_b, int nb, const int* pairs_dev, int np, void* work,
+                         void* v_out, const void* ghat, const void* tw, int* status,
+                         hipStream_t s, Trace* tr);
 
 // Pointers of one pair solve: v = G (*) (conj(a) b) (complex), or v = G (*) (a b) (real).
 // Complex mode only: kind 1 packs the two real densities |a|^2 and |b|^2 into one transform

@@ -281,11 +281,11 @@ int launch_xy_edge(int n, bool fp64, int nt, void* work, int count, const void* 
 #undef ACE_CASE
 }
 
-void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a,
-                         const void* phi_b, const int* pairs_dev, int np, void* work,
-                         void* v_out, const void* ghat, const void* tw, hipStream_t s,
-                         Trace* tr) {
-  PairsByIndex res{phi_a, phi_b, pairs_dev, v_out, np};
+void launch_pair_poisson(int n, bool fp64, bool real_packed, const void* phi_a, int na,
+                         const void* phi_b, int nb, const int* pairs_dev, int np, void* work,
+                         void* v_out, const void* ghat, const void* tw, int* status,
+                         hipStream_t s, Trace* tr) {
+  PairsByIndex res{phi_a, phi_b, pairs_dev, v_out, np, na, nb, status};
   dispatch_poisson(n, fp64, real_packed, res, work, ghat, tw, s, tr);
 }
 

@@ -65,19 +65,29 @@ __device__ __forceinline__ const TwE<T>* stage_twiddles(C2<T>* base, size_t elem
 // Where pair q's two orbitals and its output volume live.  PairsByIndex: one pair list of
 // (j, i) indices into two orbital arrays and a contiguous output array (one system);
 // PairsByPointer: explicit pointers per pair (many systems batched into one launch).
+// The indices are clamped to [0, na) and [0, nb) so that no access leaves the orbital arrays
+// (a list that the host did not check); an index out of range is recorded in the status word
+// (ACE_ERR_INVALID = -1, info = the pair), once.
 struct PairsByIndex {
   const void* pa;
   const void* pb;
   const int* pairs;
   void* vout;
   int np;
+  int na, nb;
+  int* status;
+  __device__ __forceinline__ int clamp_index(int j, int lim, int q) const {
+    if (j >= 0 && j < lim) return j;
+    if (status && atomicCAS(status, 0, -1) == 0) status[1] = q;
+    return j < 0 ? 0 : lim - 1;
+  }
   template <typename E>
   __device__ __forceinline__ const E* a(int q, size_t ng) const {
-    return reinterpret_cast<const E*>(pa) + (size_t)pairs[2 * q] * ng;
+    return reinterpret_cast<const E*>(pa) + (size_t)clamp_index(pairs[2 * q], na, q) * ng;
   }
   template <typename E>
   __device__ __forceinline__ const E* b(int q, size_t ng) const {
-    return reinterpret_cast<const E*>(pb) + (size_t)pairs[2 * q + 1] * ng;
+    return reinterpret_cast<const E*>(pb) + (size_t)clamp_index(pairs[2 * q + 1], nb, q) * ng;
   }
   template <typename E>
   __device__ __forceinline__ E* v(int q, size_t ng) const {

@@ -58,6 +58,7 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.ace_build(None, None, 1, None, None, None) == -1
     assert lib.ace_apply(None, None, 1, None, 1, None) == -1
     assert lib.pair_poisson_batched(None, None, 1, None, 1, None, 1, None) == -1
+    assert lib.pair_poisson_batched_dev(None, None, 1, None, 1, None, 1, None) == -1
     assert lib.tda_coupling(None, None, 1, None, 1, 2, None) == -1
     assert lib.ace_ctx_destroy(None) == 0
 

@@ -87,6 +87,35 @@ def test_pair_poisson_largest_box_fp32():
     assert _rel(v[0], ref) < 2e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64r"])
+def test_pair_poisson_device_pair_list(prec):
+    """A pair list already in device memory gives the same bits as the same list from the host
+    (complex pairs, and real pairs packed two per transform).  An index out of range is clamped
+    in the kernels, so no access leaves the orbital arrays, and the status word reports it with
+    the offending pair."""
+    ace = _ace()
+    rng = np.random.default_rng(11)
+    n, h = 16, 0.3
+    cplx = prec == "fp32c"
+    dt = torch.complex64 if cplx else torch.float64
+    a = _rand_fields(rng, 3, n, cplx)
+    b = _rand_fields(rng, 2, n, cplx)
+    pairs = np.array([[0, 0], [2, 1], [1, 0], [2, 0], [0, 1]], dtype=np.int32)
+    ctx = ace.AceContext(n, h, dt)
+    ta, tb = _t(a, dt), _t(b, dt)
+    host = ctx.pair_poisson_batched(ta, tb, pairs)
+    dev = ctx.pair_poisson_batched(ta, tb, torch.from_numpy(pairs).to(DEV))
+    assert ctx.status() == (0, 0)
+    assert torch.equal(host, dev)
+    bad = pairs.copy()
+    bad[3, 1] = 7
+    ctx.pair_poisson_batched_dev(ta, tb, torch.from_numpy(bad).to(DEV))
+    assert ctx.status() == (-1, 3)
+    assert ctx.status() == (0, 0)
+    with pytest.raises(ValueError):
+        ctx.pair_poisson_batched_dev(ta, tb, torch.from_numpy(pairs.astype(np.int64)).to(DEV))
+
+
 def _ace_case(m, dt):
     ace = _ace()
     ctx = ace.AceContext(m.n, m.h, dt)
