@@ -402,9 +402,11 @@ int convnet_train(ace_convnet* net, int n, const float* inputs, const float* tar
                   double* loss_hist);
 
 /* ---- block eigensolver and SCF -------------------------------------------------------- */
-/* Preconditioners: NONE (residuals as they are), KINETIC (see kinetic_precondition), NET (the
- * network's output on the RMS-normalised residuals as a block of its own beside the kinetic
- * block, so the kinetic directions remain available as the fallback; needs 3k <= 64). */
+/* Preconditioners: NONE (residuals as they are), KINETIC (see kinetic_precondition; the
+ * recommended default), NET (the network's output on the RMS-normalised residuals as a block of
+ * its own beside the kinetic block, so the kinetic directions remain available as the
+ * fallback; needs 3k <= 64).  NET saves iterations but, with its larger Rayleigh-Ritz order and
+ * the network's own cost, has not saved time on the systems measured. */
 enum { ACE_PRECOND_NONE = 0, ACE_PRECOND_KINETIC = 1, ACE_PRECOND_NET = 2 };
 
 typedef struct ace_eig_opts {
@@ -452,7 +454,9 @@ int unocc_states(ace_ctx* ctx, const void* v_local, const void* phi_occ, int no,
 int scf_energies(ace_ctx* ctx, const void* v_ext, const void* phi, int k, double* energy);
 
 typedef struct ace_scf_opts {
-  ace_eig_opts eig;  /* eigensolver per iteration; eig.tol also enters the stop test */
+  ace_eig_opts eig;  /* eigensolver per iteration; eig.tol also enters the stop test.  When
+                        the residuals after eig.max_steps steps exceed eig.tol and ten times
+                        the previous density error, up to 3 * max_steps more follow */
   double alpha;      /* states mixing q_{N+1} = alpha q_{N-1} + (1 - alpha) q_N, Eq. (14) */
   double tol;        /* relative density error stop, Eq. (15) */
   int max_iter;
