@@ -76,6 +76,21 @@ def test_register_dft_and_two_step_transform_on_host(tmp_path):
     assert run.returncode == 0 and "OK" in run.stdout, run.stdout
 
 
+@pytest.mark.slow
+def test_abi_layer_under_address_and_ub_sanitizers(tmp_path):
+    """The host side of the C ABI (abi.cpp, batch.cpp, scf_driver.cpp) rebuilt with ASan and
+    UBSan, linked with the kernels' objects, and driven through every entry point's argument
+    checks and, on a machine without a GPU, the failure paths of context / batch / network
+    creation (partial set-up released).  Any sanitizer report fails the run."""
+    from paper_2405_01522_amd import build
+    exe = build.build_sanitized_driver(os.path.join(ROOT, "tests", "native", "abi_sanitize.cpp"),
+                                       str(tmp_path), jobs=8)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert run.returncode == 0 and "OK" in run.stdout, (run.stdout + run.stderr)[-4000:]
+
+
 def test_binding_rejects_wrong_result_tensors():
     """Caller-supplied result tensors are checked before their pointers reach the library:
     a wrong dtype for M or a result block of the wrong shape is a ValueError, not a write past
