@@ -107,6 +107,9 @@ struct ManyRed {
 // W_i(r) = -sum_j phi_j(r) v_ji(r); v holds pair (a<=b) volumes G (*) conj(phi_a) phi_b.
 // One thread per point holds every phi_j(r) and W_i(r) in registers, so each pair volume is
 // read once: v_ab feeds W_b (with phi_a) and, for a != b, W_a (with phi_b and conj(v_ab)).
+// W is accumulated in FP64 for every storage type: a product of two FP32 values is exact in
+// FP64, so FP32 storage gets the exact sum rounded once (in place of a compensated FP32 sum);
+// the pass stays bound by its HBM traffic.
 template <typename E, int NMAX, typename S>
 __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng_arg) {
   const Placed<MolArgs> pc = src.place(ng_arg);
@@ -118,10 +121,12 @@ __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng_arg) {
   const int n = m.n;
   const size_t r = pc.blk * kThreads + threadIdx.x;
   if (r >= ng) return;
-  E ph[NMAX], acc[NMAX];
+  typedef typename Elem<E>::wide A;
+  E ph[NMAX];
+  A acc[NMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
-    acc[j] = e_zero<E>();
+    acc[j] = e_zero<A>();
     ph[j] = phi[(size_t)(j < n ? j : n - 1) * ng + r];  // unconditional: loads issue together
   }
 #pragma unroll
@@ -129,15 +134,15 @@ __global__ __launch_bounds__(kThreads) void k_wacc(S src, size_t ng_arg) {
     if (b < n) {
 #pragma unroll
       for (int a = 0; a <= b; ++a) {
-        const E vab = v[pair_index(a, b) * ng + r];
-        acc[b] = e_add(acc[b], e_mul(ph[a], vab));
-        if (a != b) acc[a] = e_add(acc[a], e_mul(ph[b], e_conj(vab)));
+        const A vab = e_wide(v[pair_index(a, b) * ng + r]);
+        acc[b] = e_add(acc[b], e_mul(e_wide(ph[a]), vab));
+        if (a != b) acc[a] = e_add(acc[a], e_mul(e_wide(ph[b]), e_conj(vab)));
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i)
-    if (i < n) w[(size_t)i * ng + r] = e_neg(acc[i]);
+    if (i < n) w[(size_t)i * ng + r] = e_narrow<E>(e_neg(acc[i]));
 }
 
 // Partial Gram sums G_kl = sum_r conj(A_k(r)) B_l(r) on the matrix cores.  A workgroup of 4
@@ -503,10 +508,12 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng_arg) {
   const size_t r = r0 + threadIdx.x;
   const bool in = r < ng;
   const size_t rc = in ? r : ng - 1;
-  E ph[NMAX], acc[NMAX];
+  typedef typename Elem<E>::wide A;
+  E ph[NMAX];
+  A acc[NMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
-    acc[j] = e_zero<E>();
+    acc[j] = e_zero<A>();
     ph[j] = phi[(size_t)(j < n ? j : n - 1) * ng + rc];
   }
 #pragma unroll
@@ -514,16 +521,16 @@ __global__ __launch_bounds__(kThreads) void k_wacc_gram(S src, size_t ng_arg) {
     if (b < n) {
 #pragma unroll
       for (int a = 0; a <= b; ++a) {
-        const E vab = v[pair_index(a, b) * ng + rc];
-        acc[b] = e_add(acc[b], e_mul(ph[a], vab));
-        if (a != b) acc[a] = e_add(acc[a], e_mul(ph[b], e_conj(vab)));
+        const A vab = e_wide(v[pair_index(a, b) * ng + rc]);
+        acc[b] = e_add(acc[b], e_mul(e_wide(ph[a]), vab));
+        if (a != b) acc[a] = e_add(acc[a], e_mul(e_wide(ph[b]), e_conj(vab)));
       }
     }
   }
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     const bool use = i < n && in;
-    const E wi = e_neg(acc[i]);
+    const E wi = e_narrow<E>(e_neg(acc[i]));
     if (use) w[(size_t)i * ng + r] = wi;
     lp[i * LD + threadIdx.x] = use ? ph[i] : e_zero<E>();
     lw[i * LD + threadIdx.x] = use ? wi : e_zero<E>();
@@ -1415,10 +1422,10 @@ __global__ __launch_bounds__(256) void k_direct_acc(const E* __restrict__ phi, i
   const int vi = blockIdx.x % nv;
   const size_t r = (size_t)(blockIdx.x / nv) * 256 + threadIdx.x;
   if (r >= ng) return;
-  E acc = e_zero<E>();
+  typename Elem<E>::wide acc{};
   for (int j = 0; j < n; ++j)
-    acc = e_add(acc, e_mul(phi[(size_t)j * ng + r], v[((size_t)vi * n + j) * ng + r]));
-  out[(size_t)vi * ng + r] = e_neg(acc);
+    acc = e_add(acc, e_mul(e_wide(phi[(size_t)j * ng + r]), e_wide(v[((size_t)vi * n + j) * ng + r])));
+  out[(size_t)vi * ng + r] = e_narrow<E>(e_neg(acc));
 }
 
 }  // namespace

@@ -7,6 +7,8 @@
   values the oracle wrote (tests/golden/make_c3_golden.py).
 * Every one of the 64 systems of the uneven batch (edges 32-64, 2-16 complex orbitals) against
   the oracle's E_x, M and sampled xi (tests/golden/make_c4_golden.py).
+* FP64 storage at edges 56 and 64 (the rows-and-strips XY pass) and the energy terms of the
+  64^3 SCF workload.
 
 Bars: FP32 storage -- E_x within 1e-6 Ha, TDA eigenvalues within 1e-4 eV (the targets of the
 mixed-precision path), single results 2e-5 relative (an FP32 FFT convolution of length-P
@@ -195,3 +197,29 @@ def test_config4_every_system_fp64_vs_oracle(c4_golden):
     for g, sysd in zip(c4_golden, systems):
         _check_c4_system(g, sysd, 1e-10 * abs(g["ex"]), 1e-10)
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config5_energy_terms_vs_oracle(prec):
+    """The SCF energy terms of the 64^3 workload (16 doubly occupied orbitals, 8 soft nuclei):
+    kinetic (fourth-order differences), external, Hartree (the Poisson solve of the density)
+    and exchange (ACE over the 16 orbitals, 136 pair solves at P = 128), each against the
+    oracle's on the same orbitals -- FP64 storage to 1e-10 relative; FP32 storage to the unit
+    roundoff of FP32 relative to the term (each term is an FP64 sum of products of FP32 grid
+    values, each rounded once) plus 1e-7 Ha."""
+    ace = _ace()
+    from oracle import scf as oscf
+    s = synth.config5()
+    single = prec == "fp32"
+    dt = torch.float32 if single else torch.float64
+    phi = synth.to_precision(s.guess, single)
+    ctx = ace.AceContext(s.n, s.h, dt)
+    got = ctx.scf_energies(_t(synth.to_precision(s.v_ext[None], single), dt), _t(phi, dt))
+    ref = oscf.energies(phi.astype(np.float64), synth.to_precision(s.v_ext, single).astype(np.float64),
+                        s.h, poisson.kernel_hat(s.n, s.h))
+    for term in ("kinetic", "external", "hartree", "exchange", "total"):
+        if single:
+            tol = 2.0 ** -24 * abs(ref[term]) + 1e-7
+            assert abs(got[term] - ref[term]) < tol, (term, got[term], ref[term])
+        else:
+            assert abs(got[term] - ref[term]) < 1e-10 * abs(ref[term]), (term, got[term], ref[term])
