@@ -161,8 +161,9 @@ void run_poisson(bool rp, R res, void* work, const void* ghat, const void* tw, h
   {
     TraceScope ts(tr, TR_XY);
     if constexpr (fits<T, N>()) {
-      allow_lds(k_xy<T, N, 1, kXyThreads>, lds_xy);
-      k_xy<T, N, 1, kXyThreads><<<gxy, kXyThreads, lds_xy, s>>>(w, gh, t);
+      constexpr int nt = xy_threads<T, N>();
+      allow_lds(k_xy<T, N, 1, nt>, lds_xy);
+      k_xy<T, N, 1, nt><<<gxy, nt, lds_xy, s>>>(w, gh, t);
     } else {
       allow_lds(k_xy_strips<T, N, 512>, strip_lds<T, N>());
       k_xy_strips<T, N, 512><<<gxy, 512, strip_lds<T, N>(), s>>>(w, gh, t);

@@ -30,10 +30,17 @@ template <int N>
 constexpr int zi_threads() {
   return N >= 32 ? z_round(N * Plan<N>::P1) : 256;
 }
+// threads of the one-system XY pass (one P x P plane per workgroup): 512 where the phases are
+// small (FP32 up to edge 40, FP64 up to 32), else 1024 -- measured per edge with the planes of
+// a few dozen transforms (edge 32: 28.6 against 34.5 us, edge 40: 59.0 against 62.8 us, edge 48:
+// 77.6 against 71.1 us for 512 against 1024 threads); every shape gives the same bits.
 #ifndef ACE_XY_THREADS
-#define ACE_XY_THREADS 1024
+#define ACE_XY_THREADS 0
 #endif
-constexpr int kXyThreads = ACE_XY_THREADS;  // XY pass (one P x P plane per workgroup)
+template <typename T, int N>
+constexpr int xy_threads() {
+  return ACE_XY_THREADS > 0 ? ACE_XY_THREADS : (N <= (sizeof(T) == 4 ? 40 : 32) ? 512 : 1024);
+}
 
 template <typename T>
 __device__ __forceinline__ C2<T>* lds() {
