@@ -194,8 +194,8 @@ __host__ __device__ __forceinline__ C2<T> cmul_k(C2<T> a, double c, double s) {
   return {a.r * T(c) - a.i * T(s), a.r * T(s) + a.i * T(c)};
 }
 
-// Twiddle table entry exp(-2 pi i m / P) of the two-factor transforms: FP64 as is, FP32 as
-// hi + lo parts of cos and sin (16 bytes either way).
+// Twiddle table entry exp(-2 pi i m / P) of the two-factor transforms: FP64 as is (16 bytes),
+// FP32 as a float pair of unit magnitude (8 bytes, unit_twiddle_f below).
 template <typename T>
 struct TwE;
 template <>
