@@ -46,7 +46,7 @@ struct Tune {
   int k[65] = {};   // XY planes per item of the persistent XY launch, by box edge
   int nt[65] = {};  // threads of the per-edge XY launches, by box edge
   int per_edge = 0; // 1: XY as one launch per edge; 0: one persistent launch
-  int zf_nt = 512, zi_nt = 512;
+  int zf_nt = 512, zi_nt = 512;  // threads of the persistent z passes; 0: one launch per edge
   std::string source = "default";
 };
 
@@ -63,6 +63,7 @@ const char* cache_path() {
 }
 
 // cache file lines:  <key> xy=<edge>:<planes>:<threads>,... mode=<queue|edge> zf=<nt> zi=<nt>
+// (zf / zi 0: the z pass as one launch per edge)
 void load_cache_locked() {
   if (g_tune_loaded) return;
   g_tune_loaded = true;
@@ -77,8 +78,8 @@ void load_cache_locked() {
     if (std::sscanf(line, "%511s xy=%399s mode=%15s zf=%d zi=%d", key, xy, mode, &zf, &zi) != 5)
       continue;
     Tune t;
-    t.zf_nt = zf == 1024 ? 1024 : 512;
-    t.zi_nt = zi == 1024 ? 1024 : 512;
+    t.zf_nt = zf == 1024 || zf == 0 ? zf : 512;
+    t.zi_nt = zi == 1024 || zi == 0 ? zi : 512;
     t.per_edge = std::strcmp(mode, "edge") == 0;
     for (char* tok = std::strtok(xy, ","); tok; tok = std::strtok(nullptr, ",")) {
       int n = 0, k = 0, nt = 0;
@@ -462,15 +463,31 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
     }
     return 0;
   };
-  auto run_passes = [&](const Tune& t, ace::Trace* trp) -> int {
-    for (size_t c = 0; c + 1 < chunk_start.size(); ++c) {
-      const size_t j0 = chunk_start[c], j1 = chunk_start[c + 1];
+  // a z pass of chunk c: the persistent launch with nt threads over its items, or (nt 0) one
+  // launch per run of jobs of one edge
+  auto z_pass = [&](bool forward, int nt, size_t c) -> int {
+    const size_t j0 = chunk_start[c], j1 = chunk_start[c + 1];
+    if (nt > 0) {
       const int nz = (int)(z_off[c + 1] - z_off[c]);
       const size_t lz = z_lds_of(jobs, j0, j1, fp64);
+      return forward ? launch_zfwd_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, nt, s)
+                     : launch_zinv_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, nt, s);
+    }
+    for (size_t g0 = j0; g0 < j1;) {
+      size_t g1 = g0;
+      while (g1 < j1 && jobs[g1].edge == jobs[g0].edge) ++g1;
+      if (launch_z_edge(forward, jobs[g0].edge, fp64, rp, dev_jobs() + g0, (int)(g1 - g0), s))
+        return -1;
+      g0 = g1;
+    }
+    return 0;
+  };
+  auto run_passes = [&](const Tune& t, ace::Trace* trp) -> int {
+    for (size_t c = 0; c + 1 < chunk_start.size(); ++c) {
       int r = 0;
       {
         TraceScope ts(trp, TR_ZFWD);
-        r |= launch_zfwd_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, t.zf_nt, s);
+        r |= z_pass(true, t.zf_nt, c);
       }
       {
         TraceScope ts(trp, TR_XY);
@@ -478,7 +495,7 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
       }
       {
         TraceScope ts(trp, TR_ZINV);
-        r |= launch_zinv_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, t.zi_nt, s);
+        r |= z_pass(false, t.zi_nt, c);
       }
       if (r) return ACE_ERR_UNSUPPORTED;
     }
@@ -502,11 +519,7 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
       if (upload()) return -1.0;
       double tot = 0.0;
       for (size_t c = 0; c + 1 < chunk_start.size(); ++c) {
-        const size_t j0 = chunk_start[c], j1 = chunk_start[c + 1];
-        if (launch_zfwd_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c],
-                              (int)(z_off[c + 1] - z_off[c]), z_lds_of(jobs, j0, j1, fp64),
-                              t.zf_nt, s))
-          return -1.0;
+        if (z_pass(true, t.zf_nt, c)) return -1.0;
         const double ms = time_ms(s, 2, [&]() { (void)xy_pass(t, c); });
         if (ms < 0) return -1.0;
         tot += ms;
@@ -541,21 +554,14 @@ int ace_build_batched(ace_batch* b, const ace_mol* mols, int nmol) {
     tune = (best_e >= 0 && (best_q < 0 || best_e < best_q)) ? te : tq;
     set_k(tune);
     if (upload()) return ACE_ERR_HIP;
-    // z passes: 512 or 1024 threads, timed over the whole pass (both passes are idempotent)
+    // z passes: persistent with 512 or 1024 threads, or one launch per edge; timed over the
+    // whole pass (both passes are idempotent)
     for (int pass = 0; pass < 2; ++pass) {
       double tbest = -1.0;
       int nbest = 512;
-      for (int nt : {512, 1024}) {
+      for (int nt : {512, 1024, 0}) {
         const double ms = time_ms(s, 2, [&]() {
-          for (size_t c = 0; c + 1 < chunk_start.size(); ++c) {
-            const size_t j0 = chunk_start[c], j1 = chunk_start[c + 1];
-            const int nz = (int)(z_off[c + 1] - z_off[c]);
-            const size_t lz = z_lds_of(jobs, j0, j1, fp64);
-            if (pass == 0)
-              (void)launch_zfwd_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, nt, s);
-            else
-              (void)launch_zinv_queue(fp64, rp, dev_jobs(), dev_z() + z_off[c], nz, lz, nt, s);
-          }
+          for (size_t c = 0; c + 1 < chunk_start.size(); ++c) (void)z_pass(pass == 0, nt, c);
         });
         if (ms >= 0 && (tbest < 0 || ms < tbest)) {
           tbest = ms;

@@ -115,6 +115,11 @@ int launch_xy_queue(bool fp64, const QJob* jobs, const QItem* xyitems, int nxy, 
                     hipStream_t s);
 int launch_zinv_queue(bool fp64, bool real_packed, const QJob* jobs, const QItem* zitems, int nz,
                       size_t lds_z, int nt, hipStream_t s);
+// The z-forward (forward) or z-inverse pass of count consecutive jobs of one box edge n
+// (jobs: device pointer to the first), one workgroup per (x-plane, job) with the one-system
+// kernels' shapes.  -1 if the edge is not compiled for the precision.
+int launch_z_edge(bool forward, int n, bool fp64, bool real_packed, const QJob* jobs, int count,
+                  hipStream_t s);
 // XY pass of count consecutive transforms of one box edge n (their N*N*P work volumes back to
 // back from work) with the one-system kernel at nt threads (512 or 1024), one plane per
 // workgroup.  -1 if the edge is not compiled for the precision.

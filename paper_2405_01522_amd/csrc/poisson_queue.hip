@@ -163,6 +163,67 @@ __global__ __launch_bounds__(NT) void k_zinv_q(const QJob* __restrict__ jobs,
   }
 }
 
+// ---- per-edge forms of the z passes -------------------------------------------------------
+// One launch over consecutive jobs of one box edge N (jobs[blockIdx.y], x-plane blockIdx.x)
+// with the thread count and LDS of the one-system kernels, so that every edge runs at its own
+// occupancy instead of that of a workgroup sized for the largest edge; same bodies, same bits.
+template <typename T, int N, bool RP>
+__global__ __launch_bounds__(zf_threads<N>()) void k_zfwd_e(const QJob* __restrict__ jobs) {
+  constexpr int P = 2 * N;
+  const QJob* jb = jobs + blockIdx.y;
+  C2<T>* buf = lds<T>();
+  const TwE<T>* tw =
+      stage_twiddles<T, P>(buf, (size_t)N * (P + 1), reinterpret_cast<const TwE<T>*>(jb->tw));
+  __syncthreads();
+  const JobPairs res{jb, jb->np};
+  zfwd_plane<T, N, RP, JobPairs>(res, 0, blockIdx.x, reinterpret_cast<C2<T>*>(jb->work), tw,
+                                 buf, threadIdx.x, zf_threads<N>());
+}
+
+template <typename T, int N, bool RP>
+__global__ __launch_bounds__(zi_threads<N>()) void k_zinv_e(const QJob* __restrict__ jobs) {
+  constexpr int P = 2 * N;
+  const QJob* jb = jobs + blockIdx.y;
+  C2<T>* buf = lds<T>();
+  const TwE<T>* tw =
+      stage_twiddles<T, P>(buf, (size_t)N * (P + 1), reinterpret_cast<const TwE<T>*>(jb->tw));
+  const JobPairs res{jb, jb->np};
+  // the twiddles are first read after the pass's own barrier
+  zinv_plane<T, N, RP, JobPairs>(reinterpret_cast<const C2<T>*>(jb->work), res, 0, blockIdx.x,
+                                 tw, buf, threadIdx.x, zi_threads<N>());
+}
+
+template <typename T, int N, bool RP>
+void z_edge(bool forward, const QJob* jobs, int count, hipStream_t s) {
+  constexpr int P = 2 * N;
+  const size_t lds = lds_with_twiddles<T, P>((size_t)N * (P + 1));
+  dim3 grid(N, count);
+  if (forward) {
+    allow_lds(k_zfwd_e<T, N, RP>, lds);
+    k_zfwd_e<T, N, RP><<<grid, zf_threads<N>(), lds, s>>>(jobs);
+  } else {
+    allow_lds(k_zinv_e<T, N, RP>, lds);
+    k_zinv_e<T, N, RP><<<grid, zi_threads<N>(), lds, s>>>(jobs);
+  }
+}
+
+template <typename T>
+int z_edge_any(bool forward, int n, bool rp, const QJob* jobs, int count, hipStream_t s) {
+  switch (n) {
+#define ACE_CASE(NN)                                                       \
+  case NN:                                                                 \
+    if constexpr (supported<T, NN>()) {                                    \
+      rp ? z_edge<T, NN, true>(forward, jobs, count, s)                    \
+         : z_edge<T, NN, false>(forward, jobs, count, s);                  \
+      return 0;                                                            \
+    }                                                                      \
+    return -1;
+    ACE_SIZES(ACE_CASE)
+#undef ACE_CASE
+  }
+  return -1;
+}
+
 constexpr int kXyQueueThreads = 1024;
 
 // One 1024-thread workgroup per CU: the per-edge bodies are separate functions (inlined into
@@ -271,6 +332,13 @@ int launch_zfwd_queue(bool fp64, bool rp, const QJob* jobs, const QItem* zitems,
     rp ? launch_z_passes<float, true>(true, jobs, zitems, nz, lds_z, nt, s)
        : launch_z_passes<float, false>(true, jobs, zitems, nz, lds_z, nt, s);
   return 0;
+}
+
+int launch_z_edge(bool forward, int n, bool fp64, bool rp, const QJob* jobs, int count,
+                  hipStream_t s) {
+  if (count <= 0) return 0;
+  return fp64 ? z_edge_any<double>(forward, n, rp, jobs, count, s)
+              : z_edge_any<float>(forward, n, rp, jobs, count, s);
 }
 
 int launch_xy_queue(bool fp64, const QJob* jobs, const QItem* xyitems, int nxy, size_t lds_xy,
