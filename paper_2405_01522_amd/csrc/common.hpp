@@ -110,18 +110,20 @@ inline constexpr TwTable<N> kTw{};
 // average out over the grid (about 1e-7 relative in the exchange energy, measured by emulating
 // the passes in NumPy).  The rounding of the data in the arithmetic itself is unbiased and
 // costs about 100 times less.  Most of the bias comes from constants whose rounded magnitude
-// is off (|c + i s| != 1 scales every value through them the same way); a phase error leaves
-// the transform unitary and moves much less.  So:
-//  * the register-DFT constants (the cos / sin of radices 3, 5, 7 and the 45-degree factor of
-//    radix 8, few per point) are carried as an unevaluated sum hi + lo of two floats
-//    (hi = RNE(c), lo = RNE(c - hi)), and x * c is formed as fma(x, hi, x * lo): one rounding
-//    of the product with the constant correct to about 2^-48;
-//  * the inter-factor table twiddles (one complex product per point and factor) are plain
-//    float pairs chosen for unit magnitude: among the floats within 3 ulps of cos and sin, the
-//    pair with the smallest |c^2 + s^2 - 1| (then the smallest phase error).  This keeps the
-//    product at 4 instructions and, in the same NumPy emulation, removes about 90 % of the
-//    table twiddles' share of the bias.
-// ACE_FFT_SPLIT_CONSTANTS = 0 keeps the plain rounded register-DFT constants (for measurement
+// is off (|c + i s| != 1 scales every value through them the same way); a phase error moves
+// much less.  So:
+//  * the 45-degree factor of radix 8 (c = +-s, for which no float pair has unit magnitude) is
+//    carried as an unevaluated sum hi + lo of two floats (hi = RNE(c), lo = RNE(c - hi)), and
+//    x * c is formed as fma(x, hi, x * lo): one rounding of the product with the constant
+//    correct to about 2^-48;
+//  * the cos / sin of radices 3, 5, 7 (the odd-radix butterflies) and the inter-factor table
+//    twiddles (one complex product per point and factor) are plain float pairs chosen for unit
+//    magnitude: among the floats within 3 ulps of cos and sin, the pair with the smallest
+//    |c^2 + s^2 - 1| (then the smallest phase error), one instruction per constant product.
+//    For the table twiddles this removes about 90 % of their share of the bias in the NumPy
+//    emulation; for the butterflies the round-trip bias of the 1-D transforms is as small as
+//    with hi + lo constants (a unit-magnitude 45-degree pair instead raised it fourfold).
+// ACE_FFT_SPLIT_CONSTANTS = 0 rounds the hi + lo constants to plain floats (for measurement
 // only).
 #ifndef ACE_FFT_SPLIT_CONSTANTS
 #define ACE_FFT_SPLIT_CONSTANTS 1
@@ -193,6 +195,66 @@ __host__ __device__ __forceinline__ C2<T> cmul_k(C2<T> a, double c, double s) {
   }
   return {a.r * T(c) - a.i * T(s), a.r * T(s) + a.i * T(c)};
 }
+
+// Odd-radix butterfly constants as unit-magnitude float pairs: for each angle 2 pi m / R the
+// float pair within 3 ulps of (cos, sin) with the smallest |c^2 + s^2 - 1| (then the smallest
+// phase error), one instruction per constant product instead of the two of the hi + lo form.
+// Compile-time tables.  ACE_FFT_UNIT_CONSTANTS = 0 keeps the hi + lo form (for measurement).
+#ifndef ACE_FFT_UNIT_CONSTANTS
+#define ACE_FFT_UNIT_CONSTANTS 1
+#endif
+constexpr bool kUnitConstants = ACE_FFT_UNIT_CONSTANTS != 0;
+
+// spacing of the floats around float(x), as a double (the spacing of its binade)
+constexpr double float_ulp(double x) {
+  double a = x < 0 ? -x : x;
+  if (a == 0.0) return 1.0e-45;
+  double p = 1.0;
+  while (p > a) p *= 0.5;
+  while (p * 2.0 <= a) p *= 2.0;
+  return p * 1.1920928955078125e-07;  // 2^-23
+}
+constexpr double abs_c(double x) { return x < 0 ? -x : x; }
+
+struct UnitF {
+  float c, s;
+};
+constexpr UnitF unit_pair_f(double c, double s) {
+  const float c0 = float(c), s0 = float(s);
+  const bool exact =
+      (c0 == 0.f || c0 == 1.f || c0 == -1.f) && (s0 == 0.f || s0 == 1.f || s0 == -1.f);
+  if (exact) return {c0, s0};
+  const double uc = float_ulp(c0), us = float_ulp(s0);
+  UnitF best{c0, s0};
+  double bm = 2.0, bp = 2.0;
+  for (int dc = -3; dc <= 3; ++dc)
+    for (int ds = -3; ds <= 3; ++ds) {
+      const float fc = float(double(c0) + dc * uc), fs = float(double(s0) + ds * us);
+      const double m = abs_c(double(fc) * fc + double(fs) * fs - 1.0);
+      const double ph = abs_c(double(fs) * c - double(fc) * s);
+      if (m < bm || (m == bm && ph < bp)) {
+        bm = m;
+        bp = ph;
+        best = {fc, fs};
+      }
+    }
+  return best;
+}
+
+template <int N>
+struct TwTableU {
+  float c[N];
+  float s[N];
+  constexpr TwTableU() : c(), s() {
+    for (int m = 0; m < N; ++m) {
+      const UnitF u = unit_pair_f(kTw<N>.c[m], kTw<N>.s[m]);
+      c[m] = u.c;
+      s[m] = u.s;
+    }
+  }
+};
+template <int N>
+inline constexpr TwTableU<N> kTwU{};
 
 // Twiddle table entry exp(-2 pi i m / P) of the two-factor transforms: FP64 as is (16 bytes),
 // FP32 as a float pair of unit magnitude (8 bytes, unit_twiddle_f below).
@@ -298,16 +360,24 @@ __host__ __device__ __forceinline__ void butterfly(C2<T>* x) {
 #pragma unroll
       for (int m = 1; m <= Hh; ++m) {
         const int mk = (m * k) % R;
-        const double c = kTw<R>.c[mk];
-        const double s = kTw<R>.s[mk];
-        re.r = fma_k(sp[m - 1].r, c, re.r);
-        re.i = fma_k(sp[m - 1].i, c, re.i);
-        if (m == 1) {
-          im.r = mul_k(sm[0].r, s);
-          im.i = mul_k(sm[0].i, s);
+        if constexpr (sizeof(T) == 4 && kUnitConstants) {
+          const float c = kTwU<R>.c[mk], s = kTwU<R>.s[mk];
+          re.r = fmaf(sp[m - 1].r, c, re.r);
+          re.i = fmaf(sp[m - 1].i, c, re.i);
+          im.r = m == 1 ? sm[0].r * s : fmaf(sm[m - 1].r, s, im.r);
+          im.i = m == 1 ? sm[0].i * s : fmaf(sm[m - 1].i, s, im.i);
         } else {
-          im.r = fma_k(sm[m - 1].r, s, im.r);
-          im.i = fma_k(sm[m - 1].i, s, im.i);
+          const double c = kTw<R>.c[mk];
+          const double s = kTw<R>.s[mk];
+          re.r = fma_k(sp[m - 1].r, c, re.r);
+          re.i = fma_k(sp[m - 1].i, c, re.i);
+          if (m == 1) {
+            im.r = mul_k(sm[0].r, s);
+            im.i = mul_k(sm[0].i, s);
+          } else {
+            im.r = fma_k(sm[m - 1].r, s, im.r);
+            im.i = fma_k(sm[m - 1].i, s, im.i);
+          }
         }
       }
       // DIR * i * im
