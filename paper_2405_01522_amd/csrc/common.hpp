@@ -116,9 +116,9 @@ inline constexpr TwTable<N> kTw{};
 //    carried as an unevaluated sum hi + lo of two floats (hi = RNE(c), lo = RNE(c - hi)), and
 //    x * c is formed as fma(x, hi, x * lo): one rounding of the product with the constant
 //    correct to about 2^-48;
-//  * the cos / sin of radices 3, 5, 7 (the odd-radix butterflies) and the inter-factor table
-//    twiddles (one complex product per point and factor) are plain float pairs chosen for unit
-//    magnitude: among the floats within 3 ulps of cos and sin, the pair with the smallest
+//  * the cos / sin of radices 3, 5, 7 (the odd-radix butterflies), the in-register twiddles off
+//    the multiples of 45 degrees and the inter-factor table twiddles (one complex product per
+//    point and factor) are plain float pairs chosen for unit magnitude: among the floats within 3 ulps of cos and sin, the pair with the smallest
 //    |c^2 + s^2 - 1| (then the smallest phase error), one instruction per constant product.
 //    For the table twiddles this removes about 90 % of their share of the bias in the NumPy
 //    emulation; for the butterflies the round-trip bias of the 1-D transforms is as small as
@@ -313,6 +313,13 @@ inline TwE<float> unit_twiddle_f(double c, double s) {
 template <typename T, int N, int DIR>
 __host__ __device__ __forceinline__ C2<T> twk(C2<T> a, int m) {
   const int mm = m % N;
+  if constexpr (sizeof(T) == 4 && kUnitConstants) {
+    // angles off the multiples of 45 degrees: a unit-magnitude float pair, 4 instructions
+    if ((8 * mm) % N != 0) {
+      const float c = kTwU<N>.c[mm], s = DIR * kTwU<N>.s[mm];
+      return {fmaf(a.r, c, -a.i * s), fmaf(a.r, s, a.i * c)};
+    }
+  }
   return cmul_k<T>(a, kTw<N>.c[mm], DIR * kTw<N>.s[mm]);
 }
 
