@@ -138,6 +138,22 @@ int ace_build_targets(ace_ctx* ctx, const void* phi_occ, int no, const void* psi
 int ace_apply(ace_ctx* ctx, const void* xi, int n, const void* psi, int nv, void* kpsi_out);
 
 /*
+ * ace_build followed by ace_apply in one call (Eqs. (11)-(13)): the same xi_out, M_out and
+ * ex_out as ace_build (the same arithmetic, so the same bits) and
+ *   kpsi_out[v] = -sum_k xi_k dV <xi_k | psi_v>,
+ * with dV <xi_k | psi_v> taken as (L^{-1} Y)_kv, Y = dV W^H psi (FP64 sums, as ace_apply's):
+ * Y needs only W, so for complex storage and n <= 8 its Gram shares a launch with the
+ * reduction of M, and its reduction and L^{-1} Y one with the Cholesky factorisation and xi
+ * (two fewer launches on the path than ace_build + ace_apply).  K psi agrees with ace_build + ace_apply
+ * to rounding.  Arguments as in ace_build and ace_apply; psi: [nv][N^3], kpsi_out:
+ * [nv][N^3]; kpsi_out may not alias psi, phi or xi_out.  Everything runs on the context
+ * stream; the call can be captured into a HIP graph once its workspace exists (make one
+ * uncaptured call of the same sizes first).
+ */
+int ace_build_apply(ace_ctx* ctx, const void* phi, int n, const void* psi, int nv, void* xi_out,
+                    double* M_out, double* ex_out, void* kpsi_out);
+
+/*
  * ace_apply without any allocation, for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
  * arguments and results as ace_apply (the same kernels and passes, so the same bits); its

@@ -7,7 +7,7 @@ package only marshals torch tensors into it.  Build with
 
 from .api import (  # noqa: F401
     AceContext, AceBatch, ace_ctx_create, ace_build_batched, pair_poisson_batched,
-    pair_poisson_batched_dev, ace_build, ace_apply,
+    pair_poisson_batched_dev, ace_build, ace_apply, ace_build_apply,
     exchange_apply_direct, tda_coupling, ace_ctx_status, size_supported, MAX_ORBITALS,
     strength_function, dense_gemm, sym_eig_small, ConvNet, eig_opts, scf_opts, ENERGY_TERMS,
 )

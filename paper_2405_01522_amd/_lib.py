@@ -30,6 +30,7 @@ SIGNATURES = {
     "pair_poisson_batched_dev": (_I, [_P, _P, _I, _P, _I, _P, _I, _P]),
     "ace_build": (_I, [_P, _P, _I, _P, _P, _P]),
     "ace_apply": (_I, [_P, _P, _I, _P, _I, _P]),
+    "ace_build_apply": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P]),
     "ace_apply_noalloc": (_I, [_P, _P, _I, _P, _I, _P]),
     "exchange_apply_direct": (_I, [_P, _P, _I, _P, _I, _P]),
     "tda_coupling": (_I, [_P, _P, _I, _P, _I, _I, _P]),

@@ -183,6 +183,32 @@ class AceContext:
         check(lib().ace_apply(self._h, x, xi.shape[0], p, psi.shape[0], o), "ace_apply")
         return out
 
+    def ace_build_apply(self, phi, psi, xi_out=None, m_out=None, ex_out=None, kpsi_out=None):
+        """ace_build and ace_apply in one call (the K psi Gram overlaps the factorisation);
+        returns (xi, M, E_x, K psi)."""
+        n = phi.shape[0]
+        if xi_out is None:
+            xi_out = self._empty(n)
+        if kpsi_out is None:
+            kpsi_out = self._empty(psi.shape[0])
+        cplx = self.dtype.is_complex
+        if m_out is None:
+            m_out = torch.empty((n, n), dtype=torch.complex128 if cplx else torch.float64,
+                                device=self.device)
+        if ex_out is None:
+            ex_out = torch.empty((), dtype=torch.float64, device=self.device)
+        mp = check_out(m_out, "m_out", (n, n), torch.complex128 if cplx else torch.float64,
+                       self.device)
+        ep = check_out(ex_out, "ex_out", (), torch.float64, self.device)
+        p = self._vol(phi, "phi")
+        ps = self._vol(psi, "psi")
+        x = self._vol(xi_out, "xi_out", n)
+        o = self._vol(kpsi_out, "kpsi_out", psi.shape[0])
+        self._sync_stream()
+        check(lib().ace_build_apply(self._h, p, n, ps, psi.shape[0], x, mp, ep, o),
+              "ace_build_apply")
+        return xi_out, m_out, ex_out, kpsi_out
+
     def ace_apply_noalloc(self, xi, psi, out):
         """ace_apply through the entry point that allocates nothing (static device scratch);
         the caller provides ``out``."""
@@ -731,6 +757,10 @@ def ace_build(ctx, phi, xi_out=None, m_out=None, ex_out=None):
 
 def ace_apply(ctx, xi, psi, out=None):
     return ctx.ace_apply(xi, psi, out)
+
+
+def ace_build_apply(ctx, phi, psi, xi_out=None, m_out=None, ex_out=None, kpsi_out=None):
+    return ctx.ace_build_apply(phi, psi, xi_out, m_out, ex_out, kpsi_out)
 
 
 def exchange_apply_direct(ctx, phi, psi, out=None):

@@ -123,7 +123,7 @@ int ace_ctx_create(int n, double h, int dtype, void* hip_stream, ace_ctx** out) 
     void* sp = nullptr;
     const int src = scratch_address(c->device, &sp);
     if (src) {
-      delete c;
+      ace_ctx_destroy(c);
       return src;
     }
   }
@@ -189,7 +189,8 @@ int ace_ctx_destroy(ace_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   c->trace.stream = c->stream;
   c->trace.release();
-  for (Buf* b : {&c->work, &c->vbuf, &c->wbuf, &c->part, &c->small, &c->pairs, &c->tda})
+  for (Buf* b : {&c->work, &c->vbuf, &c->wbuf, &c->part, &c->small, &c->pairs, &c->tda,
+                 &c->part2, &c->ybuf})
     if (b->p) (void)hipFree(b->p);
   if (c->ghat64) (void)hipFree(c->ghat64);
   if (c->ghat32) (void)hipFree(c->ghat32);
@@ -230,8 +231,13 @@ int pair_poisson_batched_dev(ace_ctx* c, const void* phi_a, int na, const void* 
   return run_pairs(c, phi_a, na, phi_b, nb, (const int*)pairs_dev, np, v_out);
 }
 
-int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, double* ex_out) {
-  if (!c || !phi || !xi_out || n < 1 || n > max_orbitals(c->dtype)) return ACE_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// The pair solves of an ACE build (Eqs. (11), (2)) into c->vbuf, and the workspace of the
+// steps after them (W in c->wbuf, Gram partials in c->part, M and L^{-H} in c->small).
+int build_pairs(ace_ctx* c, const void* phi, int n) {
   const size_t eb = elem_bytes(c->dtype), ng = c->ng;
   const int np = n * (n + 1) / 2;
   const bool cplx = is_cplx(c->dtype);
@@ -270,8 +276,18 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
   if (!rc) rc = ensure(c, c->part, wide * (size_t)nblk * n * n);
   if (!rc) rc = ensure(c, c->small, wide * 2 * (size_t)n * n);
   if (rc) return rc;
-  rc = cplx ? run_slots(c, phi, (const int*)c->pairs.p, nitems, c->vbuf.p)
-            : run_pairs(c, phi, n, phi, n, (const int*)c->pairs.p, np, c->vbuf.p);
+  return cplx ? run_slots(c, phi, (const int*)c->pairs.p, nitems, c->vbuf.p)
+              : run_pairs(c, phi, n, phi, n, (const int*)c->pairs.p, np, c->vbuf.p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, double* ex_out) {
+  if (!c || !phi || !xi_out || n < 1 || n > max_orbitals(c->dtype)) return ACE_ERR_INVALID;
+  const size_t ng = c->ng, wide = is_cplx(c->dtype) ? 16 : 8;
+  int rc = build_pairs(c, phi, n);
   if (rc) return rc;
   char* mred = (char*)c->small.p;
   char* linvh = mred + wide * (size_t)n * n;
@@ -279,6 +295,60 @@ int ace_build(ace_ctx* c, const void* phi, int n, void* xi_out, double* M_out, d
                    mred, c->stream, c->tr());
   launch_chol_trsm(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->wbuf.p, ng, xi_out,
                    c->stream, c->tr());
+  return hip_check(hipGetLastError());
+}
+
+int ace_build_apply(ace_ctx* c, const void* phi, int n, const void* psi, int nv, void* xi_out,
+                    double* M_out, double* ex_out, void* kpsi_out) {
+  if (!c || !phi || !psi || !xi_out || !kpsi_out || n < 1 || n > max_orbitals(c->dtype) ||
+      nv < 1)
+    return ACE_ERR_INVALID;
+  const size_t eb = elem_bytes(c->dtype), ng = c->ng;
+  const size_t wide = is_cplx(c->dtype) ? 16 : 8;
+  const double dv = c->h * c->h * c->h;
+  // vectors per Gram / update pass, as in ace_apply
+  const int chunk_v = std::max(1, std::min(nv, 64));
+  size_t chunk;
+  const int nblk = gram_blocks(ng, &chunk);
+  int rc = ensure(c, c->part2, wide * (size_t)nblk * n * chunk_v);
+  if (!rc) rc = ensure(c, c->ybuf, wide * (size_t)n * nv);
+  if (!rc) rc = build_pairs(c, phi, n);
+  if (rc) return rc;
+  char* mred = (char*)c->small.p;
+  char* linvh = mred + wide * (size_t)n * n;
+  char* y = (char*)c->ybuf.p;
+  Trace* tr = c->tr();
+  auto psi_at = [&](int v0) { return (const char*)psi + eb * ng * (size_t)v0; };
+  const bool partials =
+      launch_wacc_partials(c->dtype, phi, c->vbuf.p, n, ng, c->wbuf.p, c->part.p, c->stream, tr);
+  // xi^H psi dV = L^{-1} Y with Y = W^H psi dV, so Y needs only W: for complex storage and
+  // n <= 8 its Gram shares a launch with the reduction of M, and its reduction and L^{-1} one
+  // with the Cholesky and xi (the first pass of vectors); otherwise the steps run one after
+  // another and the update forms L^{-1} Y itself
+  const int cv0 = std::min(chunk_v, nv);
+  int first = 0;
+  if (partials && launch_gram_y_reduce_m(c->dtype, c->wbuf.p, n, psi, cv0, ng, c->part2.p,
+                                         c->part.p, dv, mred, c->stream, tr)) {
+    launch_chol_trsm_zcol(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->wbuf.p, ng,
+                          xi_out, c->part2.p, cv0, y, dv, c->stream, tr);
+    launch_apply_out(c->dtype, xi_out, n, ng, y, cv0, kpsi_out, c->stream, tr);
+    first = cv0;
+  } else {
+    launch_wacc_finish(c->dtype, partials, phi, n, ng, c->wbuf.p, c->part.p, dv, mred, c->stream,
+                       tr);
+    launch_chol_trsm(c->dtype, mred, n, M_out, ex_out, linvh, c->status, c->wbuf.p, ng, xi_out,
+                     c->stream, tr);
+  }
+  for (int v0 = first; v0 < nv; v0 += chunk_v) {
+    const int cv = std::min(chunk_v, nv - v0);
+    launch_gram(c->dtype, c->wbuf.p, n, psi_at(v0), cv, ng, c->part2.p, dv,
+                y + wide * (size_t)n * v0, c->stream, tr);
+  }
+  for (int v0 = first; v0 < nv; v0 += chunk_v) {
+    const int cv = std::min(chunk_v, nv - v0);
+    launch_apply_from_y(c->dtype, xi_out, n, ng, linvh, y + wide * (size_t)n * v0, cv,
+                        (char*)kpsi_out + eb * ng * (size_t)v0, c->stream, tr);
+  }
   return hip_check(hipGetLastError());
 }
 

@@ -304,19 +304,17 @@ __global__ __launch_bounds__(kThreads) void k_gram(S src, size_t ng_arg, int ski
 // 16x16x4 product per 4 points gives all four real products of the 8 x 8 complex tile
 //   D = [Re A; Im A] [Re B, Im B],  Re(A^H B) = D_rr + D_ii,  Im(A^H B) = D_ri - D_ir
 // with no padded rows and no third (Gauss) product.  TB tiles of 8 B columns share the A rows.
-template <typename E, typename S, int TB, bool VEC, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
+// (body: partial row blk, tile group grp of the B columns)
+template <typename E, int TB, bool VEC, int WAVES>
+__device__ __forceinline__ void gram_c8_body(const GramArgs& ga, size_t blk, int grp, size_t ng) {
   typedef typename Elem<E>::wide W;
   static_assert(Elem<E>::cplx, "complex elements");
-  const Placed<GramArgs> pc = src.place(ng_arg);
-  const GramArgs ga = pc.a;
-  const size_t ng = pc.ng;
   const E* __restrict__ A = (const E*)ga.A;
   const E* __restrict__ B = (const E*)ga.B;
   const int na = ga.na, nb = ga.nb;
   W* __restrict__ part = (W*)ga.part;
   const int tiles_l = (nb + 7) / 8;
-  if ((int)blockIdx.y * TB >= tiles_l || na > 8) return;  // beyond this system, or k_gram's
+  if (grp * TB >= tiles_l || na > 8) return;  // beyond this system, or k_gram's
   constexpr int CHUNK = kGramPoints / WAVES;  // points per wavefront
   constexpr int NQ = CHUNK / 16;
   static_assert(NQ >= 2 && NQ % 2 == 0 && CHUNK % 16 == 0, "even number of 16-point steps");
@@ -326,7 +324,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
   const int li = lane & 15, g = lane >> 4;
   const int ri = li & 7;
   const bool imag = li >= 8;
-  const size_t start = pc.blk * kGramPoints + (size_t)wave * CHUNK;
+  const size_t start = blk * kGramPoints + (size_t)wave * CHUNK;
   // Lanes li and li + 8 work on the same row (real and imaginary part).  Each loads half of the
   // wavefront's steps (li < 8 the first NH, li >= 8 the last NH) and gets the other half's
   // component from its partner lane (li ^ 8), so every element is loaded once.
@@ -358,7 +356,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
   E bv[TB][NH][4];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
-    const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
+    const int l0 = (grp * TB + t) * 8, lb = l0 + ri;
     if (l0 >= nb) break;  // uniform
     const E* rb = B + (size_t)(lb < nb ? lb : nb - 1) * ng;
 #pragma unroll
@@ -366,7 +364,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
   }
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
-    const int l0 = ((int)blockIdx.y * TB + t) * 8, lb = l0 + ri;
+    const int l0 = (grp * TB + t) * 8, lb = l0 + ri;
     if (l0 >= nb) break;  // uniform; these outputs are not written
     double bo[NQ][4];
     operands(bv[t], lb, nb, bo);
@@ -382,7 +380,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
   // TB * 64 complex outputs
   for (int th = threadIdx.x; th < TB * 64; th += 64 * WAVES) {
     const int t = th >> 6, k = (th >> 3) & 7, l = th & 7;
-    const int l0 = ((int)blockIdx.y * TB + t) * 8;
+    const int l0 = (grp * TB + t) * 8;
     const double* rt = &red[0][t * 256];
     double re = 0.0, im = 0.0;
 #pragma unroll
@@ -394,9 +392,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
       W v;
       v.r = re;
       v.i = im;
-      part[pc.blk * na * nb + (size_t)k * nb + l0 + l] = v;
+      part[blk * na * nb + (size_t)k * nb + l0 + l] = v;
     }
   }
+}
+
+template <typename E, typename S, int TB, bool VEC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gram_c8(S src, size_t ng_arg) {
+  const Placed<GramArgs> pc = src.place(ng_arg);
+  gram_c8_body<E, TB, VEC, WAVES>(pc.a, pc.blk, (int)blockIdx.y, pc.ng);
 }
 
 template <typename W>
@@ -781,19 +785,20 @@ __device__ __forceinline__ C2<double> shfl_xor_w<C2<double>>(C2<double> v, int m
 // ones only).
 constexpr int kColsMin = 1024;
 
-template <typename W, typename S>
-__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int only_cols) {
+// Output o of a reduction by the first kThreads threads of the workgroup (any further
+// wavefronts only take the barrier), so the order of the sums does not depend on the
+// workgroup size of the launch it runs in.
+template <typename W>
+__device__ __forceinline__ void gram_reduce_one(const RedArgs& ra, int o) {
   __shared__ W red[kThreads / 64];
-  const RedArgs ra = src.get(blockIdx.y);
-  const int nblk = ra.nblk;
-  const int o = blockIdx.x;
-  if (o >= ra.no || (only_cols == 0 && ra.no >= kColsMin)) return;
-  const W* __restrict__ part = (const W*)ra.part;
-  W s = W{};
-  for (int b = threadIdx.x; b < nblk; b += kThreads) s = e_add(s, part[(size_t)b * ra.no + o]);
+  if (threadIdx.x < kThreads) {
+    const W* __restrict__ part = (const W*)ra.part;
+    W s = W{};
+    for (int b = threadIdx.x; b < ra.nblk; b += kThreads) s = e_add(s, part[(size_t)b * ra.no + o]);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s = e_add(s, shfl_xor_w(s, off));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    for (int off = 32; off > 0; off >>= 1) s = e_add(s, shfl_xor_w(s, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     W t = red[0];
@@ -801,6 +806,14 @@ __global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int only_cols) 
     for (int w = 1; w < kThreads / 64; ++w) t = e_add(t, red[w]);
     ((W*)ra.out)[o] = e_scale(t, ra.scale);
   }
+}
+
+template <typename W, typename S>
+__global__ __launch_bounds__(kThreads) void k_gram_reduce(S src, int only_cols) {
+  const RedArgs ra = src.get(blockIdx.y);
+  const int o = blockIdx.x;
+  if (o >= ra.no || (only_cols == 0 && ra.no >= kColsMin)) return;
+  gram_reduce_one<W>(ra, o);
 }
 
 // The same sums for many outputs (large Gram matrices): a workgroup takes 16 consecutive
@@ -991,23 +1004,21 @@ __global__ __launch_bounds__(kThreads) void k_trsm(S src, size_t ng_arg) {
 // Cholesky (n <= 8) and xi = W L^{-H} in one launch: every workgroup factorises M itself in
 // its first wavefront (the same arithmetic as k_chol_lanes, so the same bits) while its W
 // values load; workgroup 0 writes M, E_x, L^{-H} and the status.
-template <typename E, typename S>
-__global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng_arg) {
+// (body: point block blk of the system ma)
+template <typename E>
+__device__ __forceinline__ void chol_trsm_body(const MolArgs& ma, size_t blk, size_t ng) {
   typedef typename Elem<E>::wide W;
-  const Placed<MolArgs> pc = src.place(ng_arg);
-  const MolArgs ma = pc.a;
-  const size_t ng = pc.ng;
   const E* w = (const E*)ma.w;  // xi may alias w
   E* xi = (E*)ma.xi;
   const int n = ma.n;
   __shared__ W lw[64];
   __shared__ E lh[64];
-  const size_t r = pc.blk * kThreads + threadIdx.x;
+  const size_t r = blk * kThreads + threadIdx.x;
   const size_t rc = r < ng ? r : ng - 1;
   E wr[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) wr[i] = w[(size_t)(i < n ? i : n - 1) * ng + rc];
-  if (threadIdx.x < 64) chol_lanes_body<W>(ma, (const W*)ma.mred, lw, pc.blk == 0);
+  if (threadIdx.x < 64) chol_lanes_body<W>(ma, (const W*)ma.mred, lw, blk == 0);
   __syncthreads();
   for (int t = threadIdx.x; t < n * n; t += kThreads) lh[(t / n) * 8 + t % n] = e_narrow<E>(lw[t]);
   __syncthreads();
@@ -1021,6 +1032,86 @@ __global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng_arg) {
       xi[(size_t)k * ng + r] = s;
     }
   }
+}
+
+template <typename E, typename S>
+__global__ __launch_bounds__(kThreads) void k_chol_trsm(S src, size_t ng_arg) {
+  const Placed<MolArgs> pc = src.place(ng_arg);
+  chol_trsm_body<E>(pc.a, pc.blk, pc.ng);
+}
+
+// Column v of Z = L^{-1} Y (n <= 8) with Y = scale * (sum of the partial rows in ra; row b
+// holds entry (k, v) at k * nv + v): the first wavefront factorises -M into LDS (the same
+// arithmetic as every Cholesky workgroup) while the other three reduce the n entries of the
+// column, each thread over every G-th row; the G group sums are added in order.
+template <typename W>
+__device__ __forceinline__ void z_column_body(const MolArgs& ma, const RedArgs& ra, int nv, int v) {
+  constexpr int G = (kThreads - 64) / 8;
+  __shared__ W lz[64];
+  __shared__ W red[G][8];
+  __shared__ W ycol[8];
+  const int n = ma.n;
+  if (threadIdx.x < 64) {
+    chol_lanes_body<W>(ma, (const W*)ma.mred, lz, false);
+  } else {
+    const int t = threadIdx.x - 64, k = t & 7, g = t >> 3;
+    W acc{};
+    if (k < n) {
+      const W* __restrict__ part = (const W*)ra.part + (size_t)k * nv + v;
+      const size_t row = (size_t)ra.no;
+      int b = g;
+      // loads six at a time; the additions keep their order
+      for (; b + 5 * G < ra.nblk; b += 6 * G) {
+        W x[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) x[u] = part[(size_t)(b + u * G) * row];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) acc = e_add(acc, x[u]);
+      }
+      for (; b < ra.nblk; b += G) acc = e_add(acc, part[(size_t)b * row]);
+    }
+    red[g][k] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    W y = red[0][threadIdx.x];
+    for (int g = 1; g < G; ++g) y = e_add(y, red[g][threadIdx.x]);
+    ycol[threadIdx.x] = e_scale(y, ra.scale);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < n) {
+    const int k = threadIdx.x;
+    W z{};
+    for (int i = 0; i <= k; ++i) z = e_add(z, e_mul(e_conj(lz[i * n + k]), ycol[i]));
+    ((W*)ra.out)[k * nv + v] = z;
+  }
+}
+
+// Two launches of an ACE build + K psi (complex storage, at most 8 orbitals, one system) that
+// each carry a second, independent step in extra workgroups:
+//   k_gram_c8_reduce: the partials of Y = W^H psi dV, and in its first nred workgroups (of
+//     tile group 0) the reduction of M's partials, one output each -- the code of
+//     k_gram_c8 and k_gram_reduce, so the same bits;
+//   k_chol_trsm_zcol: the Cholesky factorisation and xi = W L^{-H} (k_chol_trsm's code and
+//     bits), and in nv workgroups after them the columns of Z = xi^H psi dV = L^{-1} Y.
+template <typename E, int TB, bool VEC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gram_c8_reduce(GramArgs ga, size_t ng, RedArgs ra,
+                                                               int nred) {
+  if ((int)blockIdx.x < nred) {
+    if (blockIdx.y == 0) gram_reduce_one<typename Elem<E>::wide>(ra, blockIdx.x);
+    return;
+  }
+  gram_c8_body<E, TB, VEC, WAVES>(ga, blockIdx.x - nred, (int)blockIdx.y, ng);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kThreads) void k_chol_trsm_zcol(MolArgs ma, size_t ng, RedArgs ra,
+                                                             int nv) {
+  const size_t nbx = (ng + kThreads - 1) / kThreads;
+  if (blockIdx.x < nbx)
+    chol_trsm_body<E>(ma, blockIdx.x, ng);
+  else
+    z_column_body<typename Elem<E>::wide>(ma, ra, nv, (int)(blockIdx.x - nbx));
 }
 
 // Streaming (nontemporal) store: the K psi outputs are not read again by this step, and the
@@ -1041,10 +1132,14 @@ __device__ __forceinline__ void store_stream(E* p, E v) {
 
 // out_v(r) = -sum_k xi_k(r) Z_kv,  Z = xi^H psi dV (already scaled).  Grid: (point blocks,
 // groups of VB vectors); the group's slice of Z is staged in LDS in the storage precision.
-template <typename E, int NMAX, int VB>
+// FROM_Y: z holds Y = W^H psi dV instead, and the staging forms Z = L^{-1} Y in FP64 from
+// linvh = L^{-H} (xi = W L^{-H}, so xi^H = L^{-1} W^H).
+template <typename E, int NMAX, int VB, bool FROM_Y = false>
 __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi, int n, size_t ng,
                                                         const typename Elem<E>::wide* __restrict__ z,
-                                                        int nv, E* __restrict__ out) {
+                                                        int nv, E* __restrict__ out,
+                                                        const typename Elem<E>::wide* __restrict__ linvh = nullptr) {
+  typedef typename Elem<E>::wide W;
   __shared__ E zs[NMAX * VB];
   const int v0 = blockIdx.y * VB;
   // xi is requested before the staging of Z, so the two loads overlap (points past the end
@@ -1054,9 +1149,41 @@ __global__ __launch_bounds__(kThreads) void k_apply_out(const E* __restrict__ xi
   E xr[NMAX];
 #pragma unroll
   for (int k = 0; k < NMAX; ++k) xr[k] = xi[(size_t)(k < n ? k : n - 1) * ng + rc];
-  for (int t = threadIdx.x; t < n * VB; t += kThreads) {
-    const int k = t / VB, vb = t % VB;
-    zs[k * VB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
+  if constexpr (FROM_Y) {
+    // Z_kv = sum_{i<=k} conj((L^{-H})_ik) Y_iv: four lanes per entry, lane p adding the terms
+    // i = p, p + 4, ..., then the quad's sums (the quads are whole, as 4 n VB is a multiple
+    // of 4);
+    for (int t = threadIdx.x; t < 4 * n * VB; t += kThreads) {
+      const int e = t >> 2, p = t & 3;
+      const int k = e / VB, vb = e % VB;
+      const int vc = v0 + vb < nv ? v0 + vb : nv - 1;
+      W s{};
+      if constexpr (NMAX <= 16) {
+        // all of the lane's loads are issued before its sums (terms past k read row 0 and are
+        // not added)
+        constexpr int NT = NMAX / 4;
+        W lv[NT], yv[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          const int i = p + 4 * j, ic = i <= k ? i : 0;
+          lv[j] = linvh[ic * n + k];
+          yv[j] = z[ic * nv + vc];
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          if (p + 4 * j <= k) s = e_add(s, e_mul(e_conj(lv[j]), yv[j]));
+      } else {
+        for (int i = p; i <= k; i += 4) s = e_add(s, e_mul(e_conj(linvh[i * n + k]), z[i * nv + vc]));
+      }
+      s = e_add(s, shfl_xor_w(s, 1));
+      s = e_add(s, shfl_xor_w(s, 2));
+      if (p == 0) zs[k * VB + vb] = v0 + vb < nv ? e_narrow<E>(s) : e_zero<E>();
+    }
+  } else {
+    for (int t = threadIdx.x; t < n * VB; t += kThreads) {
+      const int k = t / VB, vb = t % VB;
+      zs[k * VB + vb] = (v0 + vb < nv) ? e_narrow<E>(z[k * nv + v0 + vb]) : e_zero<E>();
+    }
   }
   __syncthreads();
   if (r >= ng) return;
@@ -1274,22 +1401,33 @@ static void reduce_any(int et, S src, int nout, int nsys, hipStream_t s) {
     reduce_launch<double, S>(src, nout, nsys, s);
 }
 
-void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
-                      void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
-  MolArgs m = single(phi, v, w, nullptr, mred, nullptr, nullptr, nullptr, nullptr, n, ng);
+bool launch_wacc_partials(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                          void* part, hipStream_t s, Trace* tr) {
+  MolArgs m = single(phi, v, w, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, n, ng);
   m.part = part;
   bool done = false;
   {
     TraceScope ts(tr, TR_WACC);
     by_elem<WaccGramRun>(et, OneMol{m}, n, grid_one_edge(ng, 1), &done, s);
   }
-  if (!done) {
-    launch_wacc(et, phi, v, n, ng, w, s, tr);
+  if (!done) launch_wacc(et, phi, v, n, ng, w, s, tr);
+  return done;
+}
+
+void launch_wacc_finish(int et, bool partials, const void* phi, int n, size_t ng, const void* w,
+                        void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
+  if (!partials) {
     launch_gram(et, phi, n, w, n, ng, part, scale, mred, s, tr);
   } else {
     TraceScope ts(tr, TR_GRAM);
     reduce_any(et, OneRed{RedArgs{part, n * n, mred, gram_rows(ng), scale}}, n * n, 1, s);
   }
+}
+
+void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                      void* part, double scale, void* mred, hipStream_t s, Trace* tr) {
+  const bool partials = launch_wacc_partials(et, phi, v, n, ng, w, part, s, tr);
+  launch_wacc_finish(et, partials, phi, n, ng, w, part, scale, mred, s, tr);
 }
 
 void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
@@ -1376,37 +1514,91 @@ void launch_ace_steps_flat(int et, const MolArgs* mols_dev, const int* bsys_dev,
   by_elem<TrsmRun>(et, fm, nmax, g, s);
 }
 
-template <typename E, int VB>
+template <typename E, int VB, bool FROM_Y>
 static void apply_vb(const void* xi, int n, size_t ng, const void* z, int nv, void* out,
-                     hipStream_t s) {
+                     const void* linvh, hipStream_t s) {
   typedef typename Elem<E>::wide W;
   dim3 blocks((unsigned)((ng + kThreads - 1) / kThreads), (unsigned)((nv + VB - 1) / VB));
+  const W* lh = (const W*)linvh;
   if (n <= 8)
-    k_apply_out<E, 8, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+    k_apply_out<E, 8, VB, FROM_Y><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out, lh);
   else if (n <= 16)
-    k_apply_out<E, 16, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+    k_apply_out<E, 16, VB, FROM_Y><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out, lh);
   else if (n <= 32 || Elem<E>::cplx)
-    k_apply_out<E, 32, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+    k_apply_out<E, 32, VB, FROM_Y><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out, lh);
   else if constexpr (!Elem<E>::cplx)
-    k_apply_out<E, 64, VB><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out);
+    k_apply_out<E, 64, VB, FROM_Y><<<blocks, kThreads, 0, s>>>((const E*)xi, n, ng, (const W*)z, nv, (E*)out, lh);
 }
 
 // 8 vectors per workgroup row (measured against 4, 16 and 32 at 48^3, 8 orbitals, 32 vectors)
-template <typename E>
+template <typename E, bool FROM_Y>
 static void apply_impl(const void* xi, int n, size_t ng, const void* z, int nv, void* out,
-                       hipStream_t s) {
-  apply_vb<E, 8>(xi, n, ng, z, nv, out, s);
+                       const void* linvh, hipStream_t s) {
+  apply_vb<E, 8, FROM_Y>(xi, n, ng, z, nv, out, linvh, s);
+}
+
+template <bool FROM_Y>
+static void apply_any(int et, const void* xi, int n, size_t ng, const void* z, int nv, void* out,
+                      const void* linvh, hipStream_t s) {
+  switch (et) {
+    case ET_C128: apply_impl<C2<double>, FROM_Y>(xi, n, ng, z, nv, out, linvh, s); break;
+    case ET_C64: apply_impl<C2<float>, FROM_Y>(xi, n, ng, z, nv, out, linvh, s); break;
+    case ET_R64: apply_impl<double, FROM_Y>(xi, n, ng, z, nv, out, linvh, s); break;
+    case ET_R32: apply_impl<float, FROM_Y>(xi, n, ng, z, nv, out, linvh, s); break;
+  }
 }
 
 void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, int nv, void* out,
                       hipStream_t s, Trace* tr) {
   TraceScope ts(tr, TR_APPLY);
-  switch (et) {
-    case ET_C128: apply_impl<C2<double>>(xi, n, ng, z, nv, out, s); break;
-    case ET_C64: apply_impl<C2<float>>(xi, n, ng, z, nv, out, s); break;
-    case ET_R64: apply_impl<double>(xi, n, ng, z, nv, out, s); break;
-    case ET_R32: apply_impl<float>(xi, n, ng, z, nv, out, s); break;
+  apply_any<false>(et, xi, n, ng, z, nv, out, nullptr, s);
+}
+
+void launch_apply_from_y(int et, const void* xi, int n, size_t ng, const void* linvh,
+                         const void* y, int nv, void* out, hipStream_t s, Trace* tr) {
+  TraceScope ts(tr, TR_APPLY);
+  apply_any<true>(et, xi, n, ng, y, nv, out, linvh, s);
+}
+
+bool launch_gram_y_reduce_m(int et, const void* w, int n, const void* psi, int nv, size_t ng,
+                            void* part_y, const void* part_m, double scale, void* mred,
+                            hipStream_t s, Trace* tr) {
+  if ((et != ET_C64 && et != ET_C128) || n > 8 || nv < 1) return false;
+  TraceScope ts(tr, TR_GRAM);
+  const Grid g = grid_one_edge(ng, 1);
+  const int nred = n * n;
+  // four 8-column tiles per workgroup and eight wavefronts, as launch_gram's Gram of xi^H psi
+  const int groups = ((nv + 7) / 8 + 3) / 4;
+  dim3 grid(g.bx + nred, groups);
+  const GramArgs ga{w, n, psi, nv, part_y};
+  const RedArgs ra{part_m, nred, mred, gram_rows(ng), scale};
+  if (et == ET_C64) {
+    if (g.vec)
+      k_gram_c8_reduce<C2<float>, 4, true, 8><<<grid, 512, 0, s>>>(ga, ng, ra, nred);
+    else
+      k_gram_c8_reduce<C2<float>, 4, false, 8><<<grid, 512, 0, s>>>(ga, ng, ra, nred);
+  } else {
+    if (g.vec)
+      k_gram_c8_reduce<C2<double>, 4, true, 8><<<grid, 512, 0, s>>>(ga, ng, ra, nred);
+    else
+      k_gram_c8_reduce<C2<double>, 4, false, 8><<<grid, 512, 0, s>>>(ga, ng, ra, nred);
   }
+  return true;
+}
+
+void launch_chol_trsm_zcol(int et, const void* mred, int n, void* m_out, double* ex_out,
+                           void* linvh, int* status, const void* w, size_t ng, void* xi,
+                           const void* part_y, int nv, void* z, double scale, hipStream_t s,
+                           Trace* tr) {
+  TraceScope ts(tr, TR_TRSM);
+  const MolArgs ma = single(nullptr, nullptr, const_cast<void*>(w), xi, const_cast<void*>(mred),
+                            linvh, m_out, ex_out, status, n, ng);
+  const RedArgs ra{part_y, n * nv, z, gram_rows(ng), scale};
+  dim3 grid((unsigned)((ng + kThreads - 1) / kThreads) + nv);
+  if (et == ET_C64)
+    k_chol_trsm_zcol<C2<float>><<<grid, kThreads, 0, s>>>(ma, ng, ra, nv);
+  else
+    k_chol_trsm_zcol<C2<double>><<<grid, kThreads, 0, s>>>(ma, ng, ra, nv);
 }
 
 }  // namespace ace

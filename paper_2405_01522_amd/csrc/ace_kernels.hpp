@@ -41,6 +41,13 @@ void launch_wacc(int et, const void* phi, const void* v, int n, size_t ng, void*
 // complex FP64), else from the separate kernels.  part: gram_blocks(ng) * n * n partials.
 void launch_wacc_gram(int et, const void* phi, const void* v, int n, size_t ng, void* w,
                       void* part, double scale, void* mred, hipStream_t s, Trace* tr);
+// launch_wacc_gram in two steps: W (and, from the fused kernel, the Gram partials: the
+// result is true then) ...
+bool launch_wacc_partials(int et, const void* phi, const void* v, int n, size_t ng, void* w,
+                          void* part, hipStream_t s, Trace* tr);
+// ... then M into mred: the reduction of the partials, or the Gram of Phi and W.
+void launch_wacc_finish(int et, bool partials, const void* phi, int n, size_t ng, const void* w,
+                        void* part, double scale, void* mred, hipStream_t s, Trace* tr);
 // launch_chol followed by launch_trsm (one fused kernel for n <= 8).
 void launch_chol_trsm(int et, const void* mred, int n, void* m_out, double* ex_out, void* linvh,
                       int* status, const void* w, size_t ng, void* xi, hipStream_t s, Trace* tr);
@@ -53,6 +60,23 @@ void launch_chol(int et, const void* mred, int n, void* m_out, double* ex_out, v
 void launch_trsm(int et, const void* w, int n, size_t ng, const void* linvh, void* xi, hipStream_t s, Trace* tr);
 void launch_apply_out(int et, const void* xi, int n, size_t ng, const void* z, int nv, void* out,
                       hipStream_t s, Trace* tr);
+// The same update from y = W^H psi dV ([n][nv] FP64): Z = L^{-1} y is formed per workgroup
+// from linvh = L^{-H} ([n][n] FP64, as written by launch_chol / launch_chol_trsm).
+void launch_apply_from_y(int et, const void* xi, int n, size_t ng, const void* linvh,
+                         const void* y, int nv, void* out, hipStream_t s, Trace* tr);
+// Complex storage, n <= 8, one system (false, nothing launched, otherwise): the Gram
+// partials of y = W^H psi (nv <= 64 vectors) into part_y, and in the same launch M into mred
+// from the partials part_m of launch_wacc_partials -- the bits of launch_wacc_finish.
+bool launch_gram_y_reduce_m(int et, const void* w, int n, const void* psi, int nv, size_t ng,
+                            void* part_y, const void* part_m, double scale, void* mred,
+                            hipStream_t s, Trace* tr);
+// After it: launch_chol_trsm's Cholesky and xi (same bits), and in the same launch
+// z = L^{-1} Y ([n][nv] FP64, = xi^H psi dV) from Y = scale * sum of part_y, the layout of
+// launch_gram's partials for na = n, nb = nv.
+void launch_chol_trsm_zcol(int et, const void* mred, int n, void* m_out, double* ex_out,
+                           void* linvh, int* status, const void* w, size_t ng, void* xi,
+                           const void* part_y, int nv, void* z, double scale, hipStream_t s,
+                           Trace* tr);
 
 // Direct exchange accumulation: out_v = -sum_j phi_j v[v*n + j]  (v: [nv][n][ng] pair volumes).
 void launch_direct_acc(int et, const void* phi, int n, const void* v, int nv, size_t ng, void* out,

@@ -166,6 +166,9 @@ struct ace_ctx {
   void* tw = nullptr;        // P twiddles exp(-2 pi i m / P) in the compute precision
   int* status = nullptr;     // device: [code, info]
   ace::host::Buf work, vbuf, wbuf, part, small, pairs, tda;
+  // ace_build_apply: Gram partials of W^H psi (M's are in `part` at the same time) and the
+  // reduced W^H psi dV
+  ace::host::Buf part2, ybuf;
   ace::host::Blob tda_items;                // pair pointers of the TDA solves
   std::vector<int> pairs_cached;
   int* pinned_pairs = nullptr;
