@@ -496,6 +496,12 @@ def _cpu_model():
     return None
 
 
+def _done(what, t0):
+    """One progress line per finished block on stderr (stdout carries only the JSON line)."""
+    print("[bench] %s done after %.1f s" % (what, time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+
+
 def cpu_baseline(mol, budget_s=20.0):
     """The FP64 oracle, timed on the host cores on a bounded sample of the same workload:
     whole ACE builds (36 pair solves each) plus applications to the 32 vectors, repeated
@@ -555,8 +561,11 @@ def main(argv=None):
     n = mol.phi.shape[0]
     npairs = n * (n + 1) // 2
     nvec = mol.psi.shape[0]
+    t_start = time.perf_counter()
     mixed = run_gpu(mol, torch.complex64, a.steps, a.warmup, not a.no_trace, not a.no_graph)
+    _done("C2 FP32 storage", t_start)
     fp64 = run_gpu(mol, torch.complex128, a.steps, a.warmup, not a.no_trace, not a.no_graph)
+    _done("C2 FP64 storage", t_start)
 
     value = npairs / (mixed["ms_per_step"] * 1e-3)
     out = {
@@ -638,6 +647,7 @@ def main(argv=None):
     if not a.no_batched:
         c4 = synth.config4()
         bt = run_batched(c4, torch.complex64, min(a.steps, 10), 2)
+        _done("C4 batch FP32", t_start)
         ex_gpu = bt.pop("ex")
         golden = _golden_json("c4_ace.json")
         if golden is not None:
@@ -649,6 +659,7 @@ def main(argv=None):
                                  "dtype": "f32", **bt}
         # the same batch with FP64 storage (the plain FP64 path of the batch)
         bt64 = run_batched(c4, torch.complex128, min(a.steps, 10), 2)
+        _done("C4 batch FP64", t_start)
         ex64 = bt64.pop("ex")
         if golden is not None:
             rel = [abs(e - g["ex"]) / abs(g["ex"]) for e, g in zip(ex64, golden["systems"])]
@@ -660,6 +671,7 @@ def main(argv=None):
     if not a.no_tda:
         c3 = synth.config3()
         td = run_tda(c3, min(a.steps, 10), 2)
+        _done("C3 TDA block", t_start)
         cblk = td.pop("c_block")
         golden = _golden_json("c3_eigen.json")
         gold_c = _golden_npy("c3_coupling_singlet.npy")
@@ -677,9 +689,11 @@ def main(argv=None):
 
     if not a.no_scf:
         out["scf_learned_preconditioner"] = run_scf(oracle_check=not a.no_scf_oracle)
+        _done("C5 SCF", t_start)
 
     if not a.no_cpu_baseline:
         cb = cpu_baseline(mol)
+        _done("oracle on the host", t_start)
         out["cpu_baseline"] = {"value": cb["value"], "unit": "pair solves/s",
                                "cores": os.cpu_count(), "cpu_model": _cpu_model(), "kind": "oracle",
                                "sample": "%d full FP64 ACE builds + applies of the same workload "
