@@ -72,6 +72,35 @@ def test_ace_build_and_apply_random_shapes(n, count, kind, h, seed):
     assert _rel(got, ref) < tol
 
 
+@settings(max_examples=16, **SETTINGS)
+@given(n=st.sampled_from(EDGES), count=st.integers(1, 9), nv=st.integers(1, 9),
+       kind=st.sampled_from(sorted(DTYPES)), h=st.floats(0.2, 0.5), seed=st.integers(0, 10 ** 6))
+def test_ace_build_apply_random_shapes(n, count, nv, kind, h, seed):
+    """The one-call build + update (merged launches for complex storage and up to 8 orbitals,
+    the steps one after another otherwise): xi, M and E_x bit for bit as ace_build, K psi at
+    the apply bar against the oracle."""
+    ace = _ace()
+    dt = DTYPES[kind]
+    cplx = dt.is_complex
+    phi = _orbitals(seed, n, h, count, cplx)
+    rng = np.random.default_rng(seed + 2)
+    v = rng.normal(size=(nv, n, n, n))
+    if cplx:
+        v = v + 1j * rng.normal(size=(nv, n, n, n))
+    ctx = ace.AceContext(n, h, dt)
+    tphi, tv = _t(phi, dt), _t(v, dt)
+    xb, mb, eb = ctx.ace_build(tphi)
+    xi, m, ex, kp = ctx.ace_build_apply(tphi, tv)
+    assert ctx.status() == (0, 0)
+    assert torch.equal(xi, xb) and torch.equal(m, mb) and torch.equal(ex, eb)
+    fp64 = dt in (torch.complex128, torch.float64)
+    phi_used = synth.to_precision(phi, not fp64).astype(np.complex128 if cplx else np.float64)
+    v_used = synth.to_precision(v, not fp64).astype(np.complex128 if cplx else np.float64)
+    xr, _, _, _ = exchange.ace_build(phi_used, h)
+    ref = exchange.ace_apply(xr, v_used, h)
+    assert _rel(kp.cpu().numpy(), ref) < (1e-10 if fp64 else 3e-6)
+
+
 @settings(max_examples=12, **SETTINGS)
 @given(n=st.sampled_from(EDGES), na=st.integers(1, 4), nb=st.integers(1, 4),
        npairs=st.integers(1, 7), kind=st.sampled_from(sorted(DTYPES)),
