@@ -284,6 +284,16 @@ __device__ __forceinline__ void xy_planes(C2<T>* __restrict__ g, size_t g_stride
 #pragma unroll
     for (int k1 = 1; k1 < P1; ++k1) pj[(k1 * P2 + n2) * RS + qy] = tw_mul(v[k1], tw[n2 * k1]);
   }
+  // the kernel spectrum values of this thread's first phase-4 item are requested before the
+  // barrier, so that their latency overlaps the wait and the phase's LDS reads
+  T gpre[P2];
+  if (tid < K * P * P1) {
+    const int j = tid / (P * P1), r = tid - j * (P * P1);
+    const int qy = r % P, k1 = r / P;
+    const T* gj = gz + (size_t)j * P * P;
+#pragma unroll
+    for (int k2 = 0; k2 < P2; ++k2) gpre[k2] = gj[(k1 * P2 + k2) * P + qy];
+  }
   __syncthreads();
   // 4. x forward second factor, kernel multiply, x inverse first factor (in registers)
   for (int it = tid; it < K * P * P1; it += nt) {
@@ -294,9 +304,13 @@ __device__ __forceinline__ void xy_planes(C2<T>* __restrict__ g, size_t g_stride
     C2<T> v[P2];
 #pragma unroll
     for (int k2 = 0; k2 < P2; ++k2) v[k2] = pj[(k1 * P2 + k2) * RS + qy];
+    if (it != tid) {
+#pragma unroll
+      for (int k2 = 0; k2 < P2; ++k2) gpre[k2] = gj[(k1 * P2 + k2) * P + qy];
+    }
     dft<T, P2, -1>(v);
 #pragma unroll
-    for (int k2 = 0; k2 < P2; ++k2) v[k2] = cscale(v[k2], gj[(k1 * P2 + k2) * P + qy]);
+    for (int k2 = 0; k2 < P2; ++k2) v[k2] = cscale(v[k2], gpre[k2]);
     dft<T, P2, 1>(v);
 #pragma unroll
     for (int k2 = 0; k2 < P2; ++k2) pj[(k1 * P2 + k2) * RS + qy] = v[k2];
