@@ -35,7 +35,7 @@ HA_TO_EV = 27.211386
 # HBM bytes per launch of k_xy<float, 48, 1, 1024> (32 transforms) from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE, each scaled by its reading on a plain 256 MiB copy (factors 2.00 and 1.00);
 # valid for the kernel and launch as they stand (profiles/k_xy_c2_hbm_traffic.md)
-XY48_F32_TRAFFIC_BYTES = 2.00 * 29442 * 1024 + 1.00 * 55296 * 1024
+XY48_F32_TRAFFIC_BYTES = 2.00 * 29431 * 1024 + 1.00 * 55296 * 1024
 # HBM bytes of one whole C2 FP32 step (ace_build_apply over 32 vectors, seven kernels), from
 # the same counters and scaling (profiles/ace_c2_step_hbm_traffic.md)
 C2_F32_STEP_TRAFFIC_BYTES = 423.4e6
