@@ -151,7 +151,10 @@ __device__ __forceinline__ void tile_rows(const Op<float>& o, int m0, int M, siz
   rows[r] = longlong2{(long long)((size_t)ip * ng), (long long)((size_t)iq * ng)};
 }
 
-template <bool VEC, bool PROD>
+// EDGE: the tile reaches past row M or the step past the chunk end k1, so the rows and points
+// outside are zeroed and the loads clamped; interior steps (EDGE false) skip both (the same
+// values: the zeroing factor is then 1).
+template <bool VEC, bool PROD, bool EDGE>
 __device__ __forceinline__ void stage_tile(const Op<float>& o, const longlong2* rows, int m0, int M,
                                            size_t kt, size_t k1, size_t ng, __bf16* H,
                                            __bf16* L) {
@@ -164,34 +167,35 @@ __device__ __forceinline__ void stage_tile(const Op<float>& o, const longlong2* 
     const bool valid = m0 + r < M;
     const longlong2 rr = rows[r];
     const float* p = o.p + rr.x;
-    float x[4];
+    float x[4], y[4] = {};  // y: the second factor of a product operand
     if constexpr (VEC) {
-      const size_t kc = k + 3 < ng ? k : ng - 4;
+      const size_t kc = !EDGE || k + 3 < ng ? k : ng - 4;
       const float4 a = *reinterpret_cast<const float4*>(p + kc);
       x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
       if constexpr (PROD) {
         const float4 b = *reinterpret_cast<const float4*>(o.q + rr.y + kc);
-        x[0] *= b.x; x[1] *= b.y; x[2] *= b.z; x[3] *= b.w;
+        y[0] = b.x; y[1] = b.y; y[2] = b.z; y[3] = b.w;
       }
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const size_t kc = k + e < ng ? k + e : ng - 1;
-        if constexpr (PROD)
-          x[e] = p[kc] * o.q[rr.y + kc];
-        else
-          x[e] = p[kc];
+        const size_t kc = !EDGE || k + e < ng ? k + e : ng - 1;
+        x[e] = p[kc];
+        if constexpr (PROD) y[e] = o.q[rr.y + kc];
       }
     }
     bf16x4 h, l;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       // zeroing by a 0 / 1 factor (all loaded values are finite), not a select the compiler
-      // may turn into a branch around the load
-      const float v = x[e] * ((valid && k + e < k1) ? 1.f : 0.f);
+      // may turn into a branch around the load; exact, so interior and edge steps agree
+      const float xe = EDGE ? x[e] * ((valid && k + e < k1) ? 1.f : 0.f) : x[e];
+      const float v = PROD ? xe * y[e] : xe;
       const __bf16 vh = (__bf16)v;
       h[e] = vh;
-      l[e] = (__bf16)(v - (float)vh);
+      // the low part of a product from the exact product (one rounding), of a plain value
+      // from the exact difference
+      l[e] = (__bf16)(PROD ? fmaf(xe, y[e], -(float)vh) : v - (float)vh);
     }
     *reinterpret_cast<bf16x4*>(H + r * LB + c4) = h;
     *reinterpret_cast<bf16x4*>(L + r * LB + c4) = l;
@@ -222,6 +226,7 @@ __device__ __forceinline__ void load_rows(const Op<float>& o, const longlong2* r
   }
 }
 
+template <bool EDGE>
 __device__ __forceinline__ void store_rows(const float4* x, int m0, int M, size_t kt, size_t k1,
                                            __bf16* H, __bf16* L) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -235,7 +240,7 @@ __device__ __forceinline__ void store_rows(const float4* x, int m0, int M, size_
     bf16x4 h, l;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const float v = xv[e] * ((valid && k + e < k1) ? 1.f : 0.f);
+      const float v = EDGE ? xv[e] * ((valid && k + e < k1) ? 1.f : 0.f) : xv[e];
       const __bf16 vh = (__bf16)v;
       h[e] = vh;
       l[e] = (__bf16)(v - (float)vh);
@@ -285,20 +290,40 @@ __global__ __launch_bounds__(256) void k_gemm_nt_mfma(Op<float> A, int M, Op<flo
   float4 xb[MT / 16];
   if constexpr (PREF) load_rows<VEC>(B, rows_b, k0, ng, xb);
   for (size_t kt = k0; kt < k1; kt += KB) {
+    // uniform per workgroup and step: whether the A / B tile needs its rows or points masked
+    const bool step_in = kt + KB <= k1;
+    const bool edge_a = !step_in || m0 + MT > M, edge_b = !step_in || n0 + MT > N;
     if constexpr (PREF) {
-      store_rows(xb, n0, N, kt, k1, Bh, Bl);
+      if (edge_b)
+        store_rows<true>(xb, n0, N, kt, k1, Bh, Bl);
+      else
+        store_rows<false>(xb, n0, N, kt, k1, Bh, Bl);
       if (kt + KB < k1) load_rows<VEC>(B, rows_b, kt + KB, ng, xb);
     }
     // product (generated) operands load two rows; the choice is uniform per launch
-    if (A.q)
-      stage_tile<VEC, true>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
-    else
-      stage_tile<VEC, false>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
-    if constexpr (!PREF) {
-      if (B.q)
-        stage_tile<VEC, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+    if (A.q) {
+      if (edge_a)
+        stage_tile<VEC, true, true>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
       else
-        stage_tile<VEC, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+        stage_tile<VEC, true, false>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
+    } else {
+      if (edge_a)
+        stage_tile<VEC, false, true>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
+      else
+        stage_tile<VEC, false, false>(A, rows_a, m0, M, kt, k1, ng, Ah, Al);
+    }
+    if constexpr (!PREF) {
+      if (B.q) {
+        if (edge_b)
+          stage_tile<VEC, true, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+        else
+          stage_tile<VEC, true, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+      } else {
+        if (edge_b)
+          stage_tile<VEC, false, true>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+        else
+          stage_tile<VEC, false, false>(B, rows_b, n0, N, kt, k1, ng, Bh, Bl);
+      }
     }
     __syncthreads();
 #pragma unroll
