@@ -200,6 +200,30 @@ def test_config2_mixed(c2, c2_oracle):
     assert _rel(g["kpsi"], kp) < 1e-5
 
 
+@pytest.mark.parametrize("dt", [torch.complex128, torch.complex64])
+def test_config2_build_apply(c2, c2_oracle, dt):
+    """The benchmarked step, ace_build_apply on the 48^3, 8-orbital, 32-vector workload (the
+    launch configuration bench.py times), against the oracle: FP64 storage at 1e-10, FP32
+    storage at the E_x target of 1e-6 Ha and 1e-5 relative on K psi."""
+    _, mm_o, ex_o, kp_o = c2_oracle
+    ace = _ace()
+    single = dt == torch.complex64
+    ctx = ace.AceContext(c2.n, c2.h, dt)
+    phi = _t(synth.to_precision(c2.phi, single), dt)
+    psi = _t(synth.to_precision(c2.psi, single), dt)
+    _, mm, ex, kp = ctx.ace_build_apply(phi, psi)
+    assert ctx.status() == (0, 0)
+    if single:
+        assert abs(float(ex.cpu()) - ex_o) < 1e-6
+        assert _rel(mm.cpu().numpy(), mm_o) < 2e-6
+        assert _rel(kp.cpu().numpy(), kp_o) < 1e-5
+    else:
+        assert abs(float(ex.cpu()) - ex_o) < 1e-10 * abs(ex_o)
+        assert _rel(mm.cpu().numpy(), mm_o) < 1e-10
+        assert _rel(kp.cpu().numpy(), kp_o) < 1e-10
+    ctx.close()
+
+
 def test_exchange_direct_and_ace_identical_on_occupied():
     """The paper's statement that ACE reproduces the exchange operator on the orbitals it was
     built from, checked on the GPU path itself (direct Eq. (2) vs ACE Eq. (13))."""
